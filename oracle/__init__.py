@@ -1,0 +1,298 @@
+"""FP64 CPU oracle for the constrained forward-dynamics step.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the smoke check and by
+the CPU-baseline leg of the benchmark, never by the library.  It wraps the
+plain C reference in ``kamx_oracle.c`` (built with gcc, no fast-math) through
+ctypes; see that file for the equations it follows.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "kamx_oracle.c")
+LIB = os.path.join(HERE, "_kamx_oracle.so")
+
+ROW_BILATERAL, ROW_LIMIT, ROW_NORMAL, ROW_TANGENT = 0, 1, 2, 3
+OK, MAXITER, NONFINITE, FACTOR_FAIL = 0, 1, 2, 4
+
+
+def build(force=True):
+    """Compile the oracle with gcc (-O2, no fast-math, OpenMP over worlds)."""
+    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
+        return LIB
+    tmp = LIB + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-fno-fast-math",
+           "-Wall", "-Wno-unused-function", SRC, "-o", tmp, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+class _Params(C.Structure):
+    _fields_ = [
+        ("dt", C.c_double), ("gravity", C.c_double * 3), ("eta", C.c_double),
+        ("rho_bil", C.c_double), ("rho_c", C.c_double), ("eps", C.c_double),
+        ("max_iters", C.c_int32), ("fixed_iters", C.c_int32), ("accel", C.c_int32),
+        ("restart_factor", C.c_double), ("precond", C.c_int32), ("baumgarte", C.c_double),
+        ("warmstart", C.c_int32), ("replay", C.c_int32), ("log_stride", C.c_int32),
+    ]
+
+
+class _Batch(C.Structure):
+    _fields_ = [
+        ("n_worlds", C.c_int32), ("n_bodies", C.c_int32),
+        ("body_world", C.c_void_p), ("mass", C.c_void_p), ("inertia", C.c_void_p),
+        ("n_joints", C.c_int32), ("joint_type", C.c_void_p), ("joint_world", C.c_void_p),
+        ("joint_body", C.c_void_p), ("joint_frame", C.c_void_p), ("joint_limit", C.c_void_p),
+        ("n_contacts", C.c_int32), ("contact_world", C.c_void_p), ("contact_body", C.c_void_p),
+        ("contact_point", C.c_void_p), ("contact_normal", C.c_void_p), ("contact_gap", C.c_void_p),
+        ("contact_mu", C.c_void_p),
+    ]
+
+
+class _IO(C.Structure):
+    _fields_ = [
+        ("q", C.c_void_p), ("u", C.c_void_p), ("joint_torque", C.c_void_p), ("lambda_ws", C.c_void_p),
+        ("q_out", C.c_void_p), ("u_out", C.c_void_p), ("lam", C.c_void_p), ("lambda_tilde", C.c_void_p),
+        ("row_offset", C.c_void_p), ("iters", C.c_void_p), ("resid", C.c_void_p), ("status", C.c_void_p),
+        ("restart_log", C.c_void_p),
+    ]
+
+
+@dataclass
+class Params:
+    """Solver parameters (Alg. 1 and Sec. 4.1)."""
+
+    dt: float = 1e-3
+    gravity: tuple = (0.0, 0.0, -9.81)
+    eta: float = 1e-6
+    rho_bil: float = 1e-6
+    rho_c: float = 1.0
+    eps: float = 1e-6
+    max_iters: int = 2000
+    fixed_iters: int = 0
+    accel: int = 1
+    restart_factor: float = 0.999
+    precond: int = 1
+    baumgarte: float = 0.2
+    warmstart: int = 0
+
+    def replace(self, **kw):
+        return dataclasses.replace(self, **kw)
+
+    def _c(self, replay=0, log_stride=0):
+        p = _Params()
+        p.dt = self.dt
+        for k in range(3):
+            p.gravity[k] = self.gravity[k]
+        p.eta, p.rho_bil, p.rho_c, p.eps = self.eta, self.rho_bil, self.rho_c, self.eps
+        p.max_iters, p.fixed_iters, p.accel = self.max_iters, self.fixed_iters, self.accel
+        p.restart_factor, p.precond, p.baumgarte = self.restart_factor, self.precond, self.baumgarte
+        p.warmstart, p.replay, p.log_stride = self.warmstart, replay, log_stride
+        return p
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build()
+        L = C.CDLL(LIB)
+        L.orc_step.restype = C.c_int
+        L.orc_step.argtypes = [C.POINTER(_Batch), C.POINTER(_Params), C.POINTER(_IO)]
+        L.orc_row_offsets.argtypes = [C.POINTER(_Batch), C.c_void_p]
+        L.orc_world_dims.argtypes = [C.POINTER(_Batch), C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.orc_world_system.restype = C.c_int
+        L.orc_world_system.argtypes = [C.POINTER(_Batch), C.POINTER(_Params)] + [C.c_void_p] * 3 + [C.c_int] + [C.c_void_p] * 9
+        L.orc_joint_coordinate.restype = C.c_double
+        L.orc_joint_coordinate.argtypes = [C.POINTER(_Batch), C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
+        L.orc_cholesky.restype = C.c_int
+        L.orc_cholesky.argtypes = [C.c_int, C.c_void_p, C.c_void_p]
+        L.orc_project_block.argtypes = [C.c_int, C.c_double, C.c_void_p, C.c_void_p]
+        L.orc_tangent_basis.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_solve_ncp.restype = C.c_int
+        L.orc_solve_ncp.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(_Params),
+                                    C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int), C.c_void_p,
+                                    C.c_void_p, C.c_void_p]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data if a is not None and a.size else None
+
+
+class _Keep:
+    """Holds the contiguous arrays a C struct points into."""
+
+    def __init__(self):
+        self.items = []
+
+    def __call__(self, a, dtype):
+        a = np.ascontiguousarray(a, dtype=dtype)
+        self.items.append(a)
+        return a
+
+
+def _batch(scene, keep):
+    b = _Batch()
+    b.n_worlds = scene.n_worlds
+    b.n_bodies = scene.n_bodies
+    b.body_world = _p(keep(scene.body_world, np.int32))
+    b.mass = _p(keep(scene.body_mass, np.float64))
+    b.inertia = _p(keep(scene.body_inertia, np.float64))
+    b.n_joints = scene.n_joints
+    b.joint_type = _p(keep(scene.joint_type, np.int32))
+    b.joint_world = _p(keep(scene.joint_world, np.int32))
+    b.joint_body = _p(keep(scene.joint_body, np.int32))
+    b.joint_frame = _p(keep(scene.joint_frame, np.float64))
+    b.joint_limit = _p(keep(scene.joint_limit, np.float64))
+    b.n_contacts = scene.n_contacts
+    b.contact_world = _p(keep(scene.contact_world, np.int32))
+    b.contact_body = _p(keep(scene.contact_body, np.int32))
+    b.contact_point = _p(keep(scene.contact_point, np.float64))
+    b.contact_normal = _p(keep(scene.contact_normal, np.float64))
+    b.contact_gap = _p(keep(scene.contact_gap, np.float64))
+    b.contact_mu = _p(keep(scene.contact_mu, np.float64))
+    return b
+
+
+def row_offsets(scene):
+    keep = _Keep()
+    b = _batch(scene, keep)
+    off = np.zeros(scene.n_worlds + 1, np.int64)
+    lib().orc_row_offsets(C.byref(b), off.ctypes.data)
+    return off
+
+
+def step(scene, params: Params, q=None, u=None, joint_torque=None, lambda_ws=None,
+         replay_log=None, log_iters=None):
+    """One time step of every world.  Returns a dict with q, u (after the
+    step), lam (impulses, physical units, per world rows concatenated),
+    lam_tilde, row_offset, iters, resid [nw, 4], status and, when
+    ``log_iters`` is given, the restart decisions [nw, log_iters]."""
+    keep = _Keep()
+    b = _batch(scene, keep)
+    nw, nb = scene.n_worlds, scene.n_bodies
+    off = row_offsets(scene)
+    rows = int(off[-1])
+    q = keep(scene.q if q is None else q, np.float64)
+    u = keep(scene.u if u is None else u, np.float64)
+    out = dict(
+        q=np.zeros((nb, 7)), u=np.zeros((nb, 6)), lam=np.zeros(rows), lam_tilde=np.zeros(rows),
+        row_offset=np.zeros(nw + 1, np.int64), iters=np.zeros(nw, np.int32), resid=np.zeros((nw, 4)),
+        status=np.zeros(nw, np.int32),
+    )
+    stride = 0
+    log = None
+    replay = 0
+    if replay_log is not None:
+        log = keep(replay_log, np.uint8)
+        stride = log.shape[1]
+        replay = 1
+    elif log_iters:
+        stride = int(log_iters)
+        log = np.zeros((nw, stride), np.uint8)
+    io = _IO()
+    io.q, io.u = _p(q), _p(u)
+    io.joint_torque = _p(keep(joint_torque, np.float64)) if joint_torque is not None else None
+    io.lambda_ws = _p(keep(lambda_ws, np.float64)) if lambda_ws is not None else None
+    io.q_out, io.u_out = _p(out["q"]), _p(out["u"])
+    io.lam, io.lambda_tilde = _p(out["lam"]), _p(out["lam_tilde"])
+    io.row_offset = _p(out["row_offset"])
+    io.iters, io.resid, io.status = _p(out["iters"]), _p(out["resid"]), _p(out["status"])
+    io.restart_log = _p(log) if log is not None else None
+    pp = params.replace(warmstart=1 if lambda_ws is not None else 0)._c(replay, stride)
+    rc = lib().orc_step(C.byref(b), C.byref(pp), C.byref(io))
+    if rc != 0:
+        raise MemoryError("oracle step failed")
+    if log is not None and not replay:
+        out["restart_log"] = log
+    return out
+
+
+def world_dims(scene, w):
+    keep = _Keep()
+    b = _batch(scene, keep)
+    nb, m = C.c_int(), C.c_int()
+    lib().orc_world_dims(C.byref(b), w, C.byref(nb), C.byref(m))
+    return nb.value, m.value
+
+
+def world_system(scene, params: Params, w, q=None, u=None, joint_torque=None):
+    """Assembled quantities of world ``w``: J, f, vstar, kind, mu, Minv
+    (nb x 6 x 6), uf, D, vf."""
+    keep = _Keep()
+    b = _batch(scene, keep)
+    nb, m = world_dims(scene, w)
+    q = keep(scene.q if q is None else q, np.float64)
+    u = keep(scene.u if u is None else u, np.float64)
+    jt = keep(joint_torque, np.float64) if joint_torque is not None else None
+    o = dict(J=np.zeros((m, 6 * nb)), f=np.zeros(m), vstar=np.zeros(m), kind=np.zeros(m, np.int32),
+             mu=np.zeros(m), Minv=np.zeros((nb, 6, 6)), uf=np.zeros(6 * nb), D=np.zeros((m, m)),
+             vf=np.zeros(m))
+    pp = params._c()
+    rc = lib().orc_world_system(C.byref(b), C.byref(pp), _p(q), _p(u), _p(jt) if jt is not None else None, w,
+                                _p(o["J"]), _p(o["f"]), _p(o["vstar"]), _p(o["kind"]), _p(o["mu"]),
+                                _p(o["Minv"]), _p(o["uf"]), _p(o["D"]), _p(o["vf"]))
+    if rc != 0:
+        raise MemoryError("oracle world_system failed")
+    return o
+
+
+def joint_coordinate(scene, q, j):
+    keep = _Keep()
+    b = _batch(scene, keep)
+    q = keep(q, np.float64)
+    Ja, Jb = np.zeros(6), np.zeros(6)
+    c = lib().orc_joint_coordinate(C.byref(b), _p(q), j, _p(Ja), _p(Jb))
+    return c, Ja, Jb
+
+
+def cholesky(A):
+    A = np.ascontiguousarray(A, np.float64)
+    n = A.shape[0]
+    L = np.zeros_like(A)
+    rc = lib().orc_cholesky(n, _p(A), _p(L))
+    return L, rc
+
+
+def project_block(kind, mu, w):
+    w = np.ascontiguousarray(w, np.float64)
+    o = np.zeros_like(w)
+    lib().orc_project_block(kind, mu, _p(w), _p(o))
+    return o
+
+
+def tangent_basis(n):
+    n = np.ascontiguousarray(n, np.float64)
+    t1, t2 = np.zeros(3), np.zeros(3)
+    lib().orc_tangent_basis(_p(n), _p(t1), _p(t2))
+    return t1, t2
+
+
+def solve_ncp(D, vf, kind, mu, params: Params, lambda_ws=None):
+    """PADMM on an explicit dual problem (Eq. 3): returns lambda, lambda_tilde,
+    iterations, residuals, status."""
+    D = np.ascontiguousarray(D, np.float64)
+    vf = np.ascontiguousarray(vf, np.float64)
+    kind = np.ascontiguousarray(kind, np.int32)
+    mu = np.ascontiguousarray(mu, np.float64)
+    m = D.shape[0]
+    lam, lt, res = np.zeros(m), np.zeros(m), np.zeros(4)
+    it = C.c_int()
+    ws = np.ascontiguousarray(lambda_ws, np.float64) if lambda_ws is not None else None
+    pp = params.replace(warmstart=1 if ws is not None else 0)._c()
+    st = lib().orc_solve_ncp(m, _p(D), _p(vf), _p(kind), _p(mu), C.byref(pp), _p(ws) if ws is not None else None,
+                             _p(lam), _p(lt), C.byref(it), _p(res), None, None)
+    return dict(lam=lam, lam_tilde=lt, iters=it.value, resid=res, status=st)
