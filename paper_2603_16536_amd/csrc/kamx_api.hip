@@ -1,0 +1,579 @@
+// Host runtime of libkamx: model construction, device buffers, size
+// buckets, and the C entry points declared in include/kamx.h.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "kamx_internal.h"
+
+namespace kamx {
+hipError_t launch_step(const StepArgs &args, int mc, int n, hipStream_t stream);
+int bucket_capacity(int rows);
+size_t step_smem_bytes(int mc);
+}  // namespace kamx
+
+using namespace kamx;
+
+static thread_local std::string g_error;
+
+static kamx_status fail(kamx_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) return fail(KAMX_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+struct Bucket {
+    int mc;
+    int n;
+    int32_t *d_worlds;
+};
+
+struct kamx_model_s {
+    int device = 0;
+    int n_worlds = 0, nb = 0, nj = 0, np = 0;
+    int rows_cap = 0;
+    int max_contacts = 0;
+    kamx_params params{};
+    uint32_t step_index = 0;
+    std::vector<int32_t> row_offsets;
+    std::vector<Bucket> buckets;
+    std::vector<void *> allocations;
+    // device buffers
+    WorldInfo *d_worlds = nullptr;
+    float *d_mass = nullptr, *d_inertia = nullptr, *d_q = nullptr, *d_u = nullptr, *d_q0 = nullptr, *d_u0 = nullptr;
+    int32_t *d_jint = nullptr;
+    float *d_jf = nullptr;
+    int32_t *d_pbody = nullptr;
+    float *d_pf = nullptr;
+    int32_t *d_coff = nullptr;
+    const kamx_contact *d_contacts = nullptr;  // caller-owned
+    const float *d_ext = nullptr;              // caller-owned
+    float *d_lambda = nullptr, *d_lambda_ext = nullptr;
+    int32_t *d_keys = nullptr, *d_iters = nullptr, *d_status = nullptr, *d_rows = nullptr;
+    float *d_resid = nullptr;
+    uint8_t *d_rlog = nullptr;
+    int rlog_stride = 0;
+    float *d_tau = nullptr;
+    kamx_contact *d_contacts_out = nullptr;
+    int32_t *d_ncontacts = nullptr, *d_reset_count = nullptr;
+};
+
+template <typename T>
+static kamx_status dalloc(kamx_model m, T **p, size_t count) {
+    void *ptr = nullptr;
+    size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    hipError_t e = hipMalloc(&ptr, bytes);
+    if (e != hipSuccess) return fail(KAMX_ENOMEM, "hipMalloc(%zu bytes): %s", bytes, hipGetErrorString(e));
+    e = hipMemset(ptr, 0, bytes);
+    if (e != hipSuccess) return fail(KAMX_EDEVICE, "hipMemset: %s", hipGetErrorString(e));
+    m->allocations.push_back(ptr);
+    *p = reinterpret_cast<T *>(ptr);
+    return KAMX_OK;
+}
+
+#define K_TRY(expr)                       \
+    do {                                  \
+        kamx_status s_ = (expr);          \
+        if (s_ != KAMX_OK) return s_;     \
+    } while (0)
+
+static kamx_status check_device() {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(KAMX_EDEVICE, "pending device error: %s", hipGetErrorString(e));
+    return KAMX_OK;
+}
+
+static kamx_status validate_params(const kamx_params *p) {
+    if (!p) return fail(KAMX_EINVAL, "params is NULL");
+    if (!(p->dt > 0.f)) return fail(KAMX_EINVAL, "dt must be positive");
+    if (!(p->eta >= 0.f) || !(p->rho_bilateral > 0.f) || !(p->rho_contact > 0.f))
+        return fail(KAMX_EINVAL, "eta must be >= 0 and both rho > 0");
+    if (p->max_iters < 1 || p->max_iters > 1000000) return fail(KAMX_EINVAL, "max_iters out of range");
+    if (p->fixed_iters < 0 || p->fixed_iters > 1000000) return fail(KAMX_EINVAL, "fixed_iters out of range");
+    if (!(p->restart_factor > 0.f)) return fail(KAMX_EINVAL, "restart_factor must be positive");
+    if (p->warmstart < KAMX_WARM_COLD || p->warmstart > KAMX_WARM_EXTERNAL) return fail(KAMX_EINVAL, "bad warmstart");
+    return KAMX_OK;
+}
+
+static SolverParams to_solver(const kamx_params &p) {
+    SolverParams s;
+    s.dt = p.dt;
+    s.gx = p.gravity[0];
+    s.gy = p.gravity[1];
+    s.gz = p.gravity[2];
+    s.eta = p.eta;
+    s.rho_bil = p.rho_bilateral;
+    s.rho_c = p.rho_contact;
+    s.eps = p.eps;
+    s.max_iters = p.max_iters;
+    s.fixed_iters = p.fixed_iters;
+    s.accel = p.accel;
+    s.restart_factor = p.restart_factor;
+    s.precond = p.precond;
+    s.baumgarte = p.baumgarte;
+    s.warmstart = p.warmstart;
+    s.contact_margin = p.contact_margin;
+    s.torque_sigma = p.torque_sigma;
+    s.seed_lo = (uint32_t)(p.seed & 0xFFFFFFFFull);
+    s.seed_hi = (uint32_t)(p.seed >> 32);
+    s.reset_height = p.reset_height;
+    s.log_restarts = p.log_restarts;
+    return s;
+}
+
+extern "C" {
+
+void kamx_default_params(kamx_params *p) {
+    if (!p) return;
+    memset(p, 0, sizeof *p);
+    p->dt = 2e-3f;
+    p->gravity[2] = -9.81f;
+    p->eta = 1e-4f;
+    p->rho_bilateral = 1e-4f;
+    p->rho_contact = 0.3f;
+    p->eps = 1e-6f;
+    p->max_iters = 2000;
+    p->fixed_iters = 0;
+    p->accel = 1;
+    p->restart_factor = 0.999f;
+    p->precond = 1;
+    p->baumgarte = 0.2f;
+    p->warmstart = KAMX_WARM_COLD;
+    p->contact_margin = 0.02f;
+    p->torque_sigma = 0.f;
+    p->seed = 0;
+    p->reset_height = -INFINITY;
+    p->log_restarts = 0;
+}
+
+const char *kamx_last_error(void) { return g_error.c_str(); }
+
+static kamx_status ensure_rlog(kamx_model m) {
+    if (!m->params.log_restarts) return KAMX_OK;
+    if (m->d_rlog && m->rlog_stride == m->params.max_iters) return KAMX_OK;
+    if (m->d_rlog) {
+        HIP_TRY(hipDeviceSynchronize());
+        auto it = std::find(m->allocations.begin(), m->allocations.end(), (void *)m->d_rlog);
+        if (it != m->allocations.end()) m->allocations.erase(it);
+        HIP_TRY(hipFree(m->d_rlog));
+        m->d_rlog = nullptr;
+    }
+    K_TRY(dalloc(m, &m->d_rlog, (size_t)m->n_worlds * m->params.max_iters));
+    m->rlog_stride = m->params.max_iters;
+    return KAMX_OK;
+}
+
+kamx_status kamx_model_create(const kamx_body_desc *bodies, int32_t nb, const kamx_joint_desc *joints, int32_t nj,
+                              const kamx_probe_desc *probes, int32_t np, const int32_t *reset_body, int32_t n_worlds,
+                              int32_t max_contacts_per_world, const kamx_params *params, kamx_model *out) {
+    if (!out) return fail(KAMX_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n_worlds <= 0 || nb <= 0 || nj < 0 || np < 0) return fail(KAMX_EINVAL, "bad sizes");
+    if (!bodies || (nj > 0 && !joints) || (np > 0 && !probes)) return fail(KAMX_EINVAL, "NULL descriptor array");
+    if (max_contacts_per_world < 0 || max_contacts_per_world > kMaxContacts)
+        return fail(KAMX_EINVAL, "max_contacts_per_world must be in [0, %d]", kMaxContacts);
+    K_TRY(validate_params(params));
+    K_TRY(check_device());
+
+    // per-world ranges (inputs sorted by world)
+    std::vector<WorldInfo> wi(n_worlds);
+    memset(wi.data(), 0, sizeof(WorldInfo) * n_worlds);
+    for (int w = 0; w < n_worlds; ++w) wi[w].reset_body = -1;
+    auto ranges = [&](auto get_world, int n, const char *what, auto set) -> kamx_status {
+        int prev = -1;
+        for (int k = 0; k < n; ++k) {
+            int w = get_world(k);
+            if (w < 0 || w >= n_worlds) return fail(KAMX_EINVAL, "%s %d: world %d out of range", what, k, w);
+            if (w < prev) return fail(KAMX_EINVAL, "%s must be sorted by world (%s %d)", what, what, k);
+            if (w != prev) set(w, k);
+            prev = w;
+        }
+        return KAMX_OK;
+    };
+    std::vector<int> bstart(n_worlds, -1), jstart(n_worlds, -1), pstart(n_worlds, -1);
+    K_TRY(ranges([&](int k) { return bodies[k].world; }, nb, "body", [&](int w, int k) { bstart[w] = k; }));
+    K_TRY(ranges([&](int k) { return joints[k].world; }, nj, "joint", [&](int w, int k) { jstart[w] = k; }));
+    K_TRY(ranges([&](int k) { return probes[k].world; }, np, "probe", [&](int w, int k) { pstart[w] = k; }));
+    for (int k = 0; k < nb; ++k) wi[bodies[k].world].nb++;
+    for (int k = 0; k < nj; ++k) wi[joints[k].world].nj++;
+    for (int k = 0; k < np; ++k) wi[probes[k].world].np++;
+    for (int k = 0; k < nb; ++k) {
+        const kamx_body_desc &b = bodies[k];
+        if (!(b.mass > 0.f) || !(b.inertia[0] > 0.f) || !(b.inertia[1] > 0.f) || !(b.inertia[2] > 0.f))
+            return fail(KAMX_EINVAL, "body %d: mass and inertia must be positive", k);
+    }
+    std::vector<int32_t> row_off(n_worlds + 1, 0);
+    int cursor_b = 0, cursor_j = 0, cursor_p = 0;
+    for (int w = 0; w < n_worlds; ++w) {
+        WorldInfo &W = wi[w];
+        W.b0 = cursor_b;
+        W.j0 = cursor_j;
+        W.p0 = cursor_p;
+        cursor_b += W.nb;
+        cursor_j += W.nj;
+        cursor_p += W.np;
+        if (W.nb < 1 || W.nb > kMaxBodies) return fail(KAMX_EINVAL, "world %d: %d bodies (1..%d)", w, W.nb, kMaxBodies);
+        if (W.nj > kMaxJoints) return fail(KAMX_EINVAL, "world %d: %d joints (max %d)", w, W.nj, kMaxJoints);
+        if (W.np > kMaxContacts) return fail(KAMX_EINVAL, "world %d: %d probes (max %d)", w, W.np, kMaxContacts);
+        W.nlim = 0;
+        for (int j = W.j0; j < W.j0 + W.nj; ++j) {
+            const kamx_joint_desc &J = joints[j];
+            if (J.type != KAMX_REVOLUTE && J.type != KAMX_PRISMATIC)
+                return fail(KAMX_EINVAL, "joint %d: unknown type %d", j, J.type);
+            if (J.body_a < W.b0 || J.body_a >= W.b0 + W.nb)
+                return fail(KAMX_EINVAL, "joint %d: body_a %d not in world %d", j, J.body_a, w);
+            if (J.body_b != -1 && (J.body_b < W.b0 || J.body_b >= W.b0 + W.nb || J.body_b == J.body_a))
+                return fail(KAMX_EINVAL, "joint %d: body_b %d invalid", j, J.body_b);
+            if (!isnan(J.limit_lo) || !isnan(J.limit_hi)) W.nlim++;
+        }
+        for (int k = W.p0; k < W.p0 + W.np; ++k)
+            if (probes[k].body < W.b0 || probes[k].body >= W.b0 + W.nb)
+                return fail(KAMX_EINVAL, "probe %d: body %d not in world %d", k, probes[k].body, w);
+        W.contact_cap = std::max(W.np, (int)max_contacts_per_world);
+        W.row_cap = 5 * W.nj + W.nlim + 3 * W.contact_cap;
+        if (W.row_cap > kMaxRows)
+            return fail(KAMX_EINVAL, "world %d: row capacity %d exceeds %d", w, W.row_cap, kMaxRows);
+        W.row_base = row_off[w];
+        row_off[w + 1] = row_off[w] + W.row_cap;
+        if (reset_body && reset_body[w] >= 0) {
+            if (reset_body[w] < W.b0 || reset_body[w] >= W.b0 + W.nb)
+                return fail(KAMX_EINVAL, "reset_body of world %d not in the world", w);
+            W.reset_body = reset_body[w] - W.b0;
+        }
+    }
+
+    kamx_model m = new kamx_model_s();
+    HIP_TRY(hipGetDevice(&m->device));
+    m->n_worlds = n_worlds;
+    m->nb = nb;
+    m->nj = nj;
+    m->np = np;
+    m->rows_cap = row_off[n_worlds];
+    m->max_contacts = max_contacts_per_world;
+    m->params = *params;
+    m->row_offsets = row_off;
+
+    auto cleanup_fail = [&](kamx_status st) {
+        kamx_model_destroy(m);
+        return st;
+    };
+#define M_TRY(expr)                               \
+    do {                                          \
+        kamx_status s_ = (expr);                  \
+        if (s_ != KAMX_OK) return cleanup_fail(s_); \
+    } while (0)
+
+    // host staging
+    std::vector<float> mass(nb), inertia(3 * (size_t)nb);
+    for (int k = 0; k < nb; ++k) {
+        mass[k] = bodies[k].mass;
+        for (int e = 0; e < 3; ++e) inertia[3 * k + e] = bodies[k].inertia[e];
+    }
+    std::vector<int32_t> jint(4 * (size_t)std::max(nj, 1), 0);
+    std::vector<float> jf(kJointFloats * (size_t)std::max(nj, 1), 0.f);
+    for (int j = 0; j < nj; ++j) {
+        const kamx_joint_desc &J = joints[j];
+        const WorldInfo &W = wi[J.world];
+        jint[4 * j] = J.type;
+        jint[4 * j + 1] = J.body_a - W.b0;
+        jint[4 * j + 2] = J.body_b < 0 ? -1 : J.body_b - W.b0;
+        int fl = 0;
+        if (J.actuated) fl |= kJointActuated;
+        if (!isnan(J.limit_lo) || !isnan(J.limit_hi)) fl |= kJointLimited;
+        jint[4 * j + 3] = fl;
+        float *f = &jf[kJointFloats * (size_t)j];
+        for (int e = 0; e < 7; ++e) {
+            f[e] = J.frame_a[e];
+            f[7 + e] = J.frame_b[e];
+        }
+        f[14] = J.limit_lo;
+        f[15] = J.limit_hi;
+        f[16] = J.kp;
+        f[17] = J.kd;
+        f[18] = J.ref;
+    }
+    std::vector<int32_t> pbody(std::max(np, 1), 0);
+    std::vector<float> pf(4 * (size_t)std::max(np, 1), 0.f);
+    for (int k = 0; k < np; ++k) {
+        const WorldInfo &W = wi[probes[k].world];
+        pbody[k] = probes[k].body - W.b0;
+        for (int e = 0; e < 3; ++e) pf[4 * k + e] = probes[k].point[e];
+        pf[4 * k + 3] = probes[k].mu;
+    }
+
+    M_TRY(dalloc(m, &m->d_worlds, n_worlds));
+    M_TRY(dalloc(m, &m->d_mass, nb));
+    M_TRY(dalloc(m, &m->d_inertia, 3 * (size_t)nb));
+    M_TRY(dalloc(m, &m->d_q, 7 * (size_t)nb));
+    M_TRY(dalloc(m, &m->d_u, 6 * (size_t)nb));
+    M_TRY(dalloc(m, &m->d_q0, 7 * (size_t)nb));
+    M_TRY(dalloc(m, &m->d_u0, 6 * (size_t)nb));
+    M_TRY(dalloc(m, &m->d_jint, jint.size()));
+    M_TRY(dalloc(m, &m->d_jf, jf.size()));
+    M_TRY(dalloc(m, &m->d_pbody, pbody.size()));
+    M_TRY(dalloc(m, &m->d_pf, pf.size()));
+    M_TRY(dalloc(m, &m->d_coff, n_worlds + 1));
+    M_TRY(dalloc(m, &m->d_lambda, m->rows_cap));
+    M_TRY(dalloc(m, &m->d_lambda_ext, m->rows_cap));
+    M_TRY(dalloc(m, &m->d_keys, (size_t)n_worlds * kMaxContacts));
+    M_TRY(dalloc(m, &m->d_iters, n_worlds));
+    M_TRY(dalloc(m, &m->d_status, n_worlds));
+    M_TRY(dalloc(m, &m->d_rows, n_worlds));
+    M_TRY(dalloc(m, &m->d_resid, 4 * (size_t)n_worlds));
+    M_TRY(dalloc(m, &m->d_tau, std::max(nj, 1)));
+    M_TRY(dalloc(m, &m->d_contacts_out, (size_t)n_worlds * kMaxContacts));
+    M_TRY(dalloc(m, &m->d_ncontacts, n_worlds));
+    M_TRY(dalloc(m, &m->d_reset_count, n_worlds));
+    M_TRY(ensure_rlog(m));
+
+    auto up = [&](void *dst, const void *src, size_t bytes) -> kamx_status {
+        hipError_t e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return fail(KAMX_EDEVICE, "upload: %s", hipGetErrorString(e));
+        return KAMX_OK;
+    };
+    M_TRY(up(m->d_worlds, wi.data(), sizeof(WorldInfo) * n_worlds));
+    M_TRY(up(m->d_mass, mass.data(), sizeof(float) * nb));
+    M_TRY(up(m->d_inertia, inertia.data(), sizeof(float) * 3 * nb));
+    M_TRY(up(m->d_jint, jint.data(), sizeof(int32_t) * jint.size()));
+    M_TRY(up(m->d_jf, jf.data(), sizeof(float) * jf.size()));
+    M_TRY(up(m->d_pbody, pbody.data(), sizeof(int32_t) * pbody.size()));
+    M_TRY(up(m->d_pf, pf.data(), sizeof(float) * pf.size()));
+
+    // size buckets: worlds grouped by the smallest row capacity class
+    std::vector<std::vector<int32_t>> groups(8);
+    std::vector<int> caps;
+    for (int w = 0; w < n_worlds; ++w) {
+        int mc = bucket_capacity(std::max(wi[w].row_cap, 1));
+        if (mc < 0) return cleanup_fail(fail(KAMX_EINVAL, "world %d: no bucket for %d rows", w, wi[w].row_cap));
+        int slot = mc / 32 - 1;
+        groups[slot].push_back(w);
+    }
+    for (int s = 7; s >= 0; --s) {  // largest worlds first
+        if (groups[s].empty()) continue;
+        Bucket b;
+        b.mc = 32 * (s + 1);
+        b.n = (int)groups[s].size();
+        b.d_worlds = nullptr;
+        M_TRY(dalloc(m, &b.d_worlds, groups[s].size()));
+        M_TRY(up(b.d_worlds, groups[s].data(), sizeof(int32_t) * groups[s].size()));
+        m->buckets.push_back(b);
+    }
+    *out = m;
+    return KAMX_OK;
+#undef M_TRY
+}
+
+kamx_status kamx_model_destroy(kamx_model m) {
+    if (!m) return KAMX_OK;
+    hipDeviceSynchronize();
+    for (void *p : m->allocations) hipFree(p);
+    delete m;
+    return KAMX_OK;
+}
+
+kamx_status kamx_set_params(kamx_model m, const kamx_params *params) {
+    if (!m) return fail(KAMX_EINVAL, "model is NULL");
+    K_TRY(validate_params(params));
+    m->params = *params;
+    K_TRY(ensure_rlog(m));
+    return KAMX_OK;
+}
+
+kamx_status kamx_model_info(kamx_model m, int32_t *n_bodies, int32_t *n_joints, int32_t *rows_capacity,
+                            int32_t *n_buckets, int32_t *row_offsets) {
+    if (!m) return fail(KAMX_EINVAL, "model is NULL");
+    if (n_bodies) *n_bodies = m->nb;
+    if (n_joints) *n_joints = m->nj;
+    if (rows_capacity) *rows_capacity = m->rows_cap;
+    if (n_buckets) *n_buckets = (int32_t)m->buckets.size();
+    if (row_offsets) memcpy(row_offsets, m->row_offsets.data(), sizeof(int32_t) * (m->n_worlds + 1));
+    return KAMX_OK;
+}
+
+kamx_status kamx_state_upload(kamx_model m, const float *q_dev, const float *u_dev, int32_t as_reset_state,
+                              kamx_stream stream) {
+    if (!m || !q_dev || !u_dev) return fail(KAMX_EINVAL, "NULL argument");
+    K_TRY(check_device());
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    HIP_TRY(hipMemcpyAsync(m->d_q, q_dev, sizeof(float) * 7 * m->nb, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(m->d_u, u_dev, sizeof(float) * 6 * m->nb, hipMemcpyDeviceToDevice, s));
+    if (as_reset_state) {
+        HIP_TRY(hipMemcpyAsync(m->d_q0, q_dev, sizeof(float) * 7 * m->nb, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(m->d_u0, u_dev, sizeof(float) * 6 * m->nb, hipMemcpyDeviceToDevice, s));
+    }
+    return KAMX_OK;
+}
+
+kamx_status kamx_state_download(kamx_model m, float *q_dev, float *u_dev, kamx_stream stream) {
+    if (!m || !q_dev || !u_dev) return fail(KAMX_EINVAL, "NULL argument");
+    K_TRY(check_device());
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    HIP_TRY(hipMemcpyAsync(q_dev, m->d_q, sizeof(float) * 7 * m->nb, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(u_dev, m->d_u, sizeof(float) * 6 * m->nb, hipMemcpyDeviceToDevice, s));
+    return KAMX_OK;
+}
+
+kamx_status kamx_contacts_upload(kamx_model m, const kamx_contact *contacts_dev, const int32_t *world_offsets,
+                                 kamx_stream stream) {
+    if (!m) return fail(KAMX_EINVAL, "model is NULL");
+    if (!contacts_dev) {
+        m->d_contacts = nullptr;
+        return KAMX_OK;
+    }
+    if (!world_offsets) return fail(KAMX_EINVAL, "world_offsets is NULL");
+    if (world_offsets[0] != 0) return fail(KAMX_EINVAL, "world_offsets[0] must be 0");
+    for (int w = 0; w < m->n_worlds; ++w) {
+        int n = world_offsets[w + 1] - world_offsets[w];
+        if (n < 0 || n > m->max_contacts)
+            return fail(KAMX_EINVAL, "world %d: %d contacts (max %d for this model)", w, n, m->max_contacts);
+    }
+    K_TRY(check_device());
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    HIP_TRY(hipMemcpyAsync(m->d_coff, world_offsets, sizeof(int32_t) * (m->n_worlds + 1), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));  // world_offsets is a host array of the caller
+    m->d_contacts = contacts_dev;
+    return KAMX_OK;
+}
+
+kamx_status kamx_set_external(kamx_model m, const float *joint_torque_dev, kamx_stream stream) {
+    (void)stream;
+    if (!m) return fail(KAMX_EINVAL, "model is NULL");
+    m->d_ext = joint_torque_dev;
+    return KAMX_OK;
+}
+
+kamx_status kamx_set_warmstart(kamx_model m, const float *lambda_dev, kamx_stream stream) {
+    if (!m || !lambda_dev) return fail(KAMX_EINVAL, "NULL argument");
+    K_TRY(check_device());
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    HIP_TRY(hipMemcpyAsync(m->d_lambda_ext, lambda_dev, sizeof(float) * m->rows_cap, hipMemcpyDeviceToDevice, s));
+    return KAMX_OK;
+}
+
+kamx_status kamx_step(kamx_model m, int32_t nsteps, kamx_stream stream) {
+    if (!m) return fail(KAMX_EINVAL, "model is NULL");
+    if (nsteps < 0) return fail(KAMX_EINVAL, "nsteps < 0");
+    K_TRY(check_device());
+    if (m->params.log_restarts) K_TRY(ensure_rlog(m));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    StepArgs a;
+    memset(&a, 0, sizeof a);
+    a.worlds = m->d_worlds;
+    a.mass = m->d_mass;
+    a.inertia = m->d_inertia;
+    a.q = m->d_q;
+    a.u = m->d_u;
+    a.q0 = m->d_q0;
+    a.u0 = m->d_u0;
+    a.jint = m->d_jint;
+    a.jf = m->d_jf;
+    a.ext_tau = m->d_ext;
+    a.pbody = m->d_pbody;
+    a.pf = m->d_pf;
+    a.contacts = m->d_contacts;
+    a.coff = m->d_coff;
+    a.lambda = m->d_lambda;
+    a.lambda_ext = m->d_lambda_ext;
+    a.keys = m->d_keys;
+    a.iters = m->d_iters;
+    a.resid = m->d_resid;
+    a.status = m->d_status;
+    a.rows = m->d_rows;
+    a.rlog = m->params.log_restarts ? m->d_rlog : nullptr;
+    a.tau_out = m->d_tau;
+    a.contacts_out = m->d_contacts_out;
+    a.ncontacts_out = m->d_ncontacts;
+    a.reset_count = m->d_reset_count;
+    a.p = to_solver(m->params);
+    for (int k = 0; k < nsteps; ++k) {
+        a.step_index = m->step_index++;
+        for (const Bucket &b : m->buckets) {
+            a.bucket_worlds = b.d_worlds;
+            a.n_bucket_worlds = b.n;
+            hipError_t e = launch_step(a, b.mc, b.n, s);
+            if (e != hipSuccess) return fail(KAMX_EDEVICE, "step launch (bucket %d rows): %s", b.mc, hipGetErrorString(e));
+        }
+    }
+    return KAMX_OK;
+}
+
+kamx_status kamx_read_impulses(kamx_model m, float *lambda_dev, kamx_stream stream) {
+    if (!m || !lambda_dev) return fail(KAMX_EINVAL, "NULL argument");
+    K_TRY(check_device());
+    HIP_TRY(hipMemcpyAsync(lambda_dev, m->d_lambda, sizeof(float) * m->rows_cap, hipMemcpyDeviceToDevice,
+                           reinterpret_cast<hipStream_t>(stream)));
+    return KAMX_OK;
+}
+
+kamx_status kamx_read_stats(kamx_model m, int32_t *iters_dev, float *resid_dev, int32_t *status_dev, int32_t *rows_dev,
+                            kamx_stream stream) {
+    if (!m) return fail(KAMX_EINVAL, "model is NULL");
+    K_TRY(check_device());
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    int n = m->n_worlds;
+    if (iters_dev) HIP_TRY(hipMemcpyAsync(iters_dev, m->d_iters, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+    if (resid_dev) HIP_TRY(hipMemcpyAsync(resid_dev, m->d_resid, sizeof(float) * 4 * n, hipMemcpyDeviceToDevice, s));
+    if (status_dev) HIP_TRY(hipMemcpyAsync(status_dev, m->d_status, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+    if (rows_dev) HIP_TRY(hipMemcpyAsync(rows_dev, m->d_rows, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+    return KAMX_OK;
+}
+
+kamx_status kamx_read_restart_log(kamx_model m, uint8_t *log_dev, kamx_stream stream) {
+    if (!m || !log_dev) return fail(KAMX_EINVAL, "NULL argument");
+    if (!m->d_rlog) return fail(KAMX_ESTATE, "restart logging was not enabled (params.log_restarts)");
+    K_TRY(check_device());
+    HIP_TRY(hipMemcpyAsync(log_dev, m->d_rlog, (size_t)m->n_worlds * m->rlog_stride, hipMemcpyDeviceToDevice,
+                           reinterpret_cast<hipStream_t>(stream)));
+    return KAMX_OK;
+}
+
+kamx_status kamx_read_torques(kamx_model m, float *torque_dev, kamx_stream stream) {
+    if (!m || !torque_dev) return fail(KAMX_EINVAL, "NULL argument");
+    K_TRY(check_device());
+    if (m->nj > 0)
+        HIP_TRY(hipMemcpyAsync(torque_dev, m->d_tau, sizeof(float) * m->nj, hipMemcpyDeviceToDevice,
+                               reinterpret_cast<hipStream_t>(stream)));
+    return KAMX_OK;
+}
+
+kamx_status kamx_read_contacts(kamx_model m, kamx_contact *contacts_dev, int32_t *counts_dev, kamx_stream stream) {
+    if (!m) return fail(KAMX_EINVAL, "model is NULL");
+    K_TRY(check_device());
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (contacts_dev)
+        HIP_TRY(hipMemcpyAsync(contacts_dev, m->d_contacts_out, sizeof(kamx_contact) * m->n_worlds * kMaxContacts,
+                               hipMemcpyDeviceToDevice, s));
+    if (counts_dev)
+        HIP_TRY(hipMemcpyAsync(counts_dev, m->d_ncontacts, sizeof(int32_t) * m->n_worlds, hipMemcpyDeviceToDevice, s));
+    return KAMX_OK;
+}
+
+kamx_status kamx_reset_count(kamx_model m, int64_t *count, kamx_stream stream) {
+    if (!m || !count) return fail(KAMX_EINVAL, "NULL argument");
+    K_TRY(check_device());
+    std::vector<int32_t> h(m->n_worlds);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    HIP_TRY(hipMemcpyAsync(h.data(), m->d_reset_count, sizeof(int32_t) * m->n_worlds, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    int64_t c = 0;
+    for (int32_t v : h) c += v;
+    *count = c;
+    return KAMX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,113 @@
+// Internal layouts shared by the HIP kernels and the host runtime of libkamx.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/kamx.h"
+
+namespace kamx {
+
+constexpr int kMaxBodies = KAMX_MAX_BODIES_PER_WORLD;
+constexpr int kMaxJoints = KAMX_MAX_JOINTS_PER_WORLD;
+constexpr int kMaxContacts = KAMX_MAX_CONTACTS_PER_WORLD;
+constexpr int kMaxRows = KAMX_MAX_ROWS_PER_WORLD;
+constexpr int kJointFloats = 24;  // frame_a 7, frame_b 7, lo, hi, kp, kd, ref, pad
+
+// row kinds
+constexpr int kRowBilateral = 0;
+constexpr int kRowLimit = 1;
+constexpr int kRowNormal = 2;
+constexpr int kRowTangent = 3;
+
+// joint flag bits (jint[4*j+3])
+constexpr int kJointActuated = 1;
+constexpr int kJointLimited = 2;
+
+// Per-world table (one 64-byte record per world).
+struct WorldInfo {
+    int32_t b0, nb;         // global first body, body count
+    int32_t j0, nj;         // global first joint, joint count
+    int32_t p0, np;         // global first probe, probe count
+    int32_t nlim;           // limited joints
+    int32_t row_base;       // first row of the world in row-indexed buffers
+    int32_t row_cap;        // row capacity (joint + limit + 3 * contact capacity)
+    int32_t contact_cap;    // contact capacity
+    int32_t reset_body;     // world-local body index, or -1
+    int32_t pad[5];
+};
+
+struct SolverParams {
+    float dt, gx, gy, gz;
+    float eta, rho_bil, rho_c, eps;
+    int32_t max_iters, fixed_iters, accel;
+    float restart_factor;
+    int32_t precond;
+    float baumgarte;
+    int32_t warmstart;
+    float contact_margin;
+    float torque_sigma;
+    uint32_t seed_lo, seed_hi;
+    float reset_height;
+    int32_t log_restarts;
+};
+
+struct StepArgs {
+    const WorldInfo *worlds;
+    const int32_t *bucket_worlds;  // worlds handled by this launch
+    int32_t n_bucket_worlds;
+    // bodies
+    const float *mass;     // [nb]
+    const float *inertia;  // [nb*3] principal moments
+    float *q;              // [nb*7]
+    float *u;              // [nb*6]
+    const float *q0;       // reset state
+    const float *u0;
+    // joints
+    const int32_t *jint;   // [nj*4]: type, local a, local b (-1 world), flags
+    const float *jf;       // [nj*kJointFloats]
+    const float *ext_tau;  // [nj] or null
+    // probes
+    const int32_t *pbody;  // [np] local body
+    const float *pf;       // [np*4]: point, mu
+    // explicit contacts
+    const kamx_contact *contacts;  // null: use probes
+    const int32_t *coff;           // [n_worlds+1]
+    // outputs and caches
+    float *lambda;          // [rows] impulses of the last step (physical)
+    const float *lambda_ext;  // [rows] external warm start
+    int32_t *keys;          // [n_worlds*kMaxContacts] contact keys of the last step
+    int32_t *iters;
+    float *resid;           // [n_worlds*4]
+    int32_t *status;
+    int32_t *rows;          // active rows per world
+    uint8_t *rlog;          // [n_worlds*max_iters] or null
+    float *tau_out;         // [nj]
+    kamx_contact *contacts_out;  // [n_worlds*kMaxContacts]
+    int32_t *ncontacts_out;      // [n_worlds]
+    int32_t *reset_count;        // [n_worlds]
+    SolverParams p;
+    uint32_t step_index;
+};
+
+// Packed lower-triangular storage with every row padded to a multiple of 4
+// floats (so rows can be read as float4): offset of row i.
+__host__ __device__ inline int tri_row_offset(int i) {
+    int a = i >> 2, b = i & 3;
+    return 4 * (a + 1) * (2 * a + b);
+}
+
+// Shared-memory footprint (floats) of the fused step kernel for a row bucket.
+__host__ __device__ inline int body_floats() { return 32 * kMaxBodies; }
+__host__ __device__ inline int joint_floats() { return 16 * kMaxJoints; }  // tau, Jc[12], a, b, type|flags
+__host__ __device__ inline int contact_floats() { return 12 * kMaxContacts; }  // point, normal, gap, mu, a, b, key, slot
+__host__ __device__ inline int row_floats(int mc) { return 17 * mc; }
+__host__ __device__ inline int vec_floats(int mc) { return 15 * mc; }
+__host__ __device__ inline int bodyw_floats() { return 2 * 6 * kMaxBodies; }  // FP64 [6][kMaxBodies]
+__host__ __device__ inline int inc_floats(int mc) { return ((kMaxBodies + 1 + 2 * mc) + 3) & ~3; }
+__host__ __device__ inline int smem_floats(int mc) {
+    return body_floats() + joint_floats() + contact_floats() + row_floats(mc) + vec_floats(mc) +
+           tri_row_offset(mc) + 64 + bodyw_floats() + inc_floats(mc);
+}
+
+}  // namespace kamx

@@ -1,0 +1,1231 @@
+// Fused per-world time step on gfx950: one workgroup advances one world.
+//
+// Everything a world needs -- body state, joint frames, contact rows, the
+// preconditioned Delassus matrix, its factor and the ADMM vectors -- lives in
+// LDS for the whole step, so HBM sees only the per-world inputs and outputs.
+// Thread i owns constraint row i (and the block that starts at row i: one
+// row for joints and limits, three rows for a contact).
+//
+// Steps (Tsounis et al. 2026):
+//   bodies: R(q), M^-1 applied in the body frame, Newton-Euler forces with
+//           gyroscopic term and joint actuation (Sec. 3, Eq. 1);
+//   rows:   joint / limit / contact Jacobians and Baumgarte bias (Sec. 3);
+//   D~:     D = J M^-1 J^T (Eq. 4) scaled by the Jacobi preconditioner
+//           (Sec. 4.1), shifted by eta + rho (Alg. 1 step 1);
+//   factor: Cholesky once per step, then the explicit inverse of the factor,
+//           so every iteration's solve is two parallel triangular mat-vecs
+//           instead of two serial substitution sweeps;
+//   PADMM:  Alg. 1 steps 4-10 with Nesterov restart (Sec. 4.1);
+//   output: lambda = P y, u+ = u_f + M^-1 J^T lambda, SO(3) exponential map.
+#include <math.h>
+
+#include "kamx_internal.h"
+
+namespace kamx {
+
+// ---------------------------------------------------------------------------
+// small device math
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__device__ inline void rot_of_quat(const T q[4], T R[9]) {
+    T x = q[0], y = q[1], z = q[2], w = q[3];
+    R[0] = T(1) - T(2) * (y * y + z * z);
+    R[1] = T(2) * (x * y - z * w);
+    R[2] = T(2) * (x * z + y * w);
+    R[3] = T(2) * (x * y + z * w);
+    R[4] = T(1) - T(2) * (x * x + z * z);
+    R[5] = T(2) * (y * z - x * w);
+    R[6] = T(2) * (x * z - y * w);
+    R[7] = T(2) * (y * z + x * w);
+    R[8] = T(1) - T(2) * (x * x + y * y);
+}
+
+template <typename T>
+__device__ inline void qprod(const T p[4], const T q[4], T r[4]) {
+    r[0] = p[3] * q[0] + p[0] * q[3] + p[1] * q[2] - p[2] * q[1];
+    r[1] = p[3] * q[1] - p[0] * q[2] + p[1] * q[3] + p[2] * q[0];
+    r[2] = p[3] * q[2] + p[0] * q[1] - p[1] * q[0] + p[2] * q[3];
+    r[3] = p[3] * q[3] - p[0] * q[0] - p[1] * q[1] - p[2] * q[2];
+}
+
+template <typename T>
+__device__ inline void cross(const T a[3], const T b[3], T c[3]) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+template <typename T>
+__device__ inline T dot3(const T a[3], const T b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+template <typename T>
+__device__ inline void mv3(const T R[9], const T v[3], T o[3]) {
+    o[0] = R[0] * v[0] + R[1] * v[1] + R[2] * v[2];
+    o[1] = R[3] * v[0] + R[4] * v[1] + R[5] * v[2];
+    o[2] = R[6] * v[0] + R[7] * v[1] + R[8] * v[2];
+}
+
+template <typename T>
+__device__ inline void mtv3(const T R[9], const T v[3], T o[3]) {
+    o[0] = R[0] * v[0] + R[3] * v[1] + R[6] * v[2];
+    o[1] = R[1] * v[0] + R[4] * v[1] + R[7] * v[2];
+    o[2] = R[2] * v[0] + R[5] * v[1] + R[8] * v[2];
+}
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).
+__device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+    for (int r = 0; r < 10; ++r) {
+        uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// A standard normal for (world, step, slot) by Box-Muller on two 24-bit
+// uniforms (u1 in (0, 1], u2 in [0, 1)).
+__device__ inline float noise_normal(uint32_t seed_lo, uint32_t seed_hi, uint32_t world, uint32_t step,
+                                     uint32_t slot) {
+    uint32_t c[4] = {world, step, slot, 0u};
+    philox4x32_10(c, seed_lo, seed_hi);
+    const float inv = 1.0f / 16777216.0f;
+    float u1 = ((float)(c[0] >> 8) + 1.0f) * inv;
+    float u2 = (float)(c[1] >> 8) * inv;
+    return sqrtf(-2.0f * logf(u1)) * cosf(6.28318530717958647692f * u2);
+}
+
+// Orthonormal tangents completing a unit normal (Duff et al., JCGT 2017).
+__device__ inline void tangents(const float n[3], float t1[3], float t2[3]) {
+    float sg = n[2] >= 0.f ? 1.f : -1.f;
+    float a = -1.f / (sg + n[2]);
+    float b = n[0] * n[1] * a;
+    t1[0] = 1.f + sg * n[0] * n[0] * a;
+    t1[1] = sg * b;
+    t1[2] = -sg * n[0];
+    t2[0] = b;
+    t2[1] = sg + n[1] * n[1] * a;
+    t2[2] = -n[1];
+}
+
+// Projection on the Coulomb cone K_mu = {|l_t| <= mu l_n}.
+__device__ inline void proj_cone(float mu, float w0, float w1, float w2, float &o0, float &o1, float &o2) {
+    float tn = sqrtf(w1 * w1 + w2 * w2);
+    if (tn <= mu * w0) {
+        o0 = w0;
+        o1 = w1;
+        o2 = w2;
+    } else if (mu * tn <= -w0) {
+        o0 = o1 = o2 = 0.f;
+    } else {
+        float ln = (mu * tn + w0) / (1.f + mu * mu);
+        float s = tn > 0.f ? mu * ln / tn : 0.f;
+        o0 = ln;
+        o1 = s * w1;
+        o2 = s * w2;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// LDS views
+// ---------------------------------------------------------------------------
+
+// body fields [field][kMaxBodies]
+enum { BQ = 0, BU = 7, BUF = 13, BR = 19, BII = 28, BIM = 31 };
+// joint fields [field][kMaxJoints]
+enum { JTAU = 0, JC = 1, JA = 13, JB = 14, JTF = 15 };
+// contact fields [field][kMaxContacts]
+enum { CP = 0, CN = 3, CGAP = 6, CMU = 7, CA = 8, CB = 9, CKEY = 10 };
+// row fields [field][MC]
+enum { RJ = 0, RBIAS = 12, RMU = 13, RIA = 14, RIB = 15, RKIND = 16 };
+// vector fields [field][MC]
+enum { VP = 0, VRHO, VVT, VX, VYH, VZH, VYP, VZP, VRHS, VT, VXN, VWS, VAUX, VCOL, VDX };
+
+struct Lds {
+    float *b, *j, *c, *r, *v, *A, *red;
+    double *wb;          // [6][kMaxBodies] FP64 body work vector
+    int *inc_off;        // [kMaxBodies + 1] body -> row incidence offsets
+    int *inc_list;       // [2 * MC] (row << 1) | side
+    int mc;
+    __device__ float &bf(int f, int i) const { return b[f * kMaxBodies + i]; }
+    __device__ float &jfld(int f, int i) const { return j[f * kMaxJoints + i]; }
+    __device__ float &cf(int f, int i) const { return c[f * kMaxContacts + i]; }
+    __device__ float &rf(int f, int i) const { return r[f * mc + i]; }
+    __device__ int &ri(int f, int i) const { return reinterpret_cast<int *>(r)[f * mc + i]; }
+    __device__ float *vec(int f) const { return v + f * mc; }
+};
+
+// world-frame rotation of a body (from LDS)
+__device__ inline void body_rot(const Lds &L, int b, float R[9]) {
+    for (int k = 0; k < 9; ++k) R[k] = L.bf(BR + k, b);
+}
+
+// o = M_b^-1 [lin; ang], applied in the body frame: lin / m, R (I^-1 (R^T ang))
+__device__ inline void apply_minv(const Lds &L, int b, const float in[6], float out[6]) {
+    float im = L.bf(BIM, b);
+    out[0] = in[0] * im;
+    out[1] = in[1] * im;
+    out[2] = in[2] * im;
+    float R[9], t[3], s[3];
+    body_rot(L, b, R);
+    mtv3(R, in + 3, t);
+    t[0] *= L.bf(BII + 0, b);
+    t[1] *= L.bf(BII + 1, b);
+    t[2] *= L.bf(BII + 2, b);
+    mv3(R, t, s);
+    out[3] = s[0];
+    out[4] = s[1];
+    out[5] = s[2];
+}
+
+// Joint geometry: anchors, lever arms and frame rotations of both sides.
+// Evaluated in FP64: the Baumgarte bias multiplies the position-level
+// constraint value by beta / dt, so FP32 rounding of near-cancelling anchor
+// offsets and near-orthogonal axis products (about 1e-7 absolute) would
+// become velocity errors of order 1e-5.  J and everything downstream stay
+// FP32.
+struct JointGeo {
+    double pa[3], pb[3], ra[3], rb[3], Ra[9], Rb[9];
+};
+
+__device__ inline void joint_geo(const Lds &L, const float *jf, int la, int lb, JointGeo &g) {
+    double Rbody[9], t[3], qq[4], qb[4], fr[4], c[3];
+    for (int k = 0; k < 4; ++k) qb[k] = L.bf(BQ + 3 + k, la);
+    rot_of_quat(qb, Rbody);
+    for (int k = 0; k < 3; ++k) c[k] = jf[k];
+    mv3(Rbody, c, t);
+    for (int k = 0; k < 3; ++k) {
+        g.ra[k] = L.bf(BQ + k, la);
+        g.pa[k] = g.ra[k] + t[k];
+    }
+    for (int k = 0; k < 4; ++k) fr[k] = jf[3 + k];
+    qprod(qb, fr, qq);
+    rot_of_quat(qq, g.Ra);
+    for (int k = 0; k < 4; ++k) fr[k] = jf[10 + k];
+    if (lb >= 0) {
+        for (int k = 0; k < 4; ++k) qb[k] = L.bf(BQ + 3 + k, lb);
+        rot_of_quat(qb, Rbody);
+        for (int k = 0; k < 3; ++k) c[k] = jf[7 + k];
+        mv3(Rbody, c, t);
+        for (int k = 0; k < 3; ++k) {
+            g.rb[k] = L.bf(BQ + k, lb);
+            g.pb[k] = g.rb[k] + t[k];
+        }
+        qprod(qb, fr, qq);
+        rot_of_quat(qq, g.Rb);
+    } else {
+        for (int k = 0; k < 3; ++k) {
+            g.rb[k] = 0.0;
+            g.pb[k] = jf[7 + k];
+        }
+        rot_of_quat(fr, g.Rb);
+    }
+}
+
+__device__ inline void col(const double R[9], int k, double c[3]) {
+    c[0] = R[k];
+    c[1] = R[3 + k];
+    c[2] = R[6 + k];
+}
+
+// Joint coordinate and its Jacobian (6-vectors for sides a and b).
+__device__ inline double joint_coord(int type, const JointGeo &g, float Ja[6], float Jb[6]) {
+    double Xb[3], Yb[3], Zb[3], Ya[3];
+    col(g.Rb, 0, Xb);
+    col(g.Rb, 1, Yb);
+    col(g.Rb, 2, Zb);
+    col(g.Ra, 1, Ya);
+    if (type == KAMX_REVOLUTE) {
+        for (int k = 0; k < 3; ++k) {
+            Ja[k] = 0.f;
+            Jb[k] = 0.f;
+            Ja[3 + k] = (float)Xb[k];
+            Jb[3 + k] = (float)-Xb[k];
+        }
+        return atan2(dot3(Ya, Zb), dot3(Ya, Yb));
+    }
+    double d[3], la[3], lb[3], c[3];
+    for (int k = 0; k < 3; ++k) {
+        d[k] = g.pa[k] - g.pb[k];
+        la[k] = g.pa[k] - g.ra[k];
+        lb[k] = g.pa[k] - g.rb[k];
+    }
+    cross(la, Xb, c);
+    for (int k = 0; k < 3; ++k) {
+        Ja[k] = (float)Xb[k];
+        Ja[3 + k] = (float)c[k];
+    }
+    cross(lb, Xb, c);
+    for (int k = 0; k < 3; ++k) {
+        Jb[k] = (float)-Xb[k];
+        Jb[3 + k] = (float)-c[k];
+    }
+    return dot3(d, Xb);
+}
+
+__device__ inline void put_row(const Lds &L, int r, const float Ja[6], int la, const float Jb[6], int lb, float f,
+                               int kind, float mu, const SolverParams &P) {
+    for (int k = 0; k < 6; ++k) {
+        L.rf(RJ + k, r) = Ja[k];
+        L.rf(RJ + 6 + k, r) = lb >= 0 ? Jb[k] : 0.f;
+    }
+    L.ri(RIA, r) = la;
+    L.ri(RIB, r) = lb;
+    L.ri(RKIND, r) = kind;
+    L.rf(RMU, r) = mu;
+    float bias = 0.f;
+    float inv_dt = 1.f / P.dt;
+    if (kind == kRowBilateral) bias = P.baumgarte * f * inv_dt;
+    else if (kind == kRowLimit || kind == kRowNormal) bias = (f >= 0.f ? f : P.baumgarte * f) * inv_dt;
+    L.rf(RBIAS, r) = bias;
+}
+
+// Rows of joint j (5 rows from r0), Sec. 3 bilateral constraints; geometry
+// and constraint values in FP64, rows stored in FP32.
+__device__ inline void put_row6(const Lds &L, int r, const double Ja[6], int la, const double Jb[6], int lb, double f,
+                                int kind, const SolverParams &P) {
+    float fa[6], fb[6];
+    for (int k = 0; k < 6; ++k) {
+        fa[k] = (float)Ja[k];
+        fb[k] = (float)Jb[k];
+    }
+    put_row(L, r, fa, la, fb, lb, (float)f, kind, 0.f, P);
+}
+
+__device__ inline void joint_rows(const Lds &L, int type, const JointGeo &g, int la, int lb, int r0,
+                                  const SolverParams &P) {
+    double Xa[3], Ya[3], Yb[3], Zb[3];
+    col(g.Ra, 0, Xa);
+    col(g.Ra, 1, Ya);
+    col(g.Rb, 1, Yb);
+    col(g.Rb, 2, Zb);
+    double arm_a[3], arm_b[3], d[3];
+    for (int k = 0; k < 3; ++k) {
+        arm_a[k] = g.pa[k] - g.ra[k];
+        arm_b[k] = g.pb[k] - g.rb[k];
+        d[k] = g.pa[k] - g.pb[k];
+    }
+    double Ja[6], Jb[6], c[3];
+    if (type == KAMX_REVOLUTE) {
+        for (int e = 0; e < 3; ++e) {
+            double ek[3] = {0.0, 0.0, 0.0};
+            ek[e] = 1.0;
+            cross(arm_a, ek, c);
+            for (int k = 0; k < 3; ++k) {
+                Ja[k] = ek[k];
+                Ja[3 + k] = c[k];
+            }
+            cross(arm_b, ek, c);
+            for (int k = 0; k < 3; ++k) {
+                Jb[k] = -ek[k];
+                Jb[3 + k] = -c[k];
+            }
+            put_row6(L, r0 + e, Ja, la, Jb, lb, d[e], kRowBilateral, P);
+        }
+        const double *T[2] = {Yb, Zb};
+        for (int e = 0; e < 2; ++e) {
+            cross(Xa, T[e], c);
+            for (int k = 0; k < 3; ++k) {
+                Ja[k] = 0.0;
+                Ja[3 + k] = c[k];
+                Jb[k] = 0.0;
+                Jb[3 + k] = -c[k];
+            }
+            put_row6(L, r0 + 3 + e, Ja, la, Jb, lb, dot3(Xa, T[e]), kRowBilateral, P);
+        }
+    } else {
+        double lever_b[3];
+        for (int k = 0; k < 3; ++k) lever_b[k] = g.pa[k] - g.rb[k];
+        const double *T[2] = {Yb, Zb};
+        for (int e = 0; e < 2; ++e) {
+            cross(arm_a, T[e], c);
+            for (int k = 0; k < 3; ++k) {
+                Ja[k] = T[e][k];
+                Ja[3 + k] = c[k];
+            }
+            cross(lever_b, T[e], c);
+            for (int k = 0; k < 3; ++k) {
+                Jb[k] = -T[e][k];
+                Jb[3 + k] = -c[k];
+            }
+            put_row6(L, r0 + e, Ja, la, Jb, lb, dot3(d, T[e]), kRowBilateral, P);
+        }
+        const double *U[3] = {Xa, Xa, Ya};
+        const double *V[3] = {Yb, Zb, Zb};
+        for (int e = 0; e < 3; ++e) {
+            cross(U[e], V[e], c);
+            for (int k = 0; k < 3; ++k) {
+                Ja[k] = 0.0;
+                Ja[3 + k] = c[k];
+                Jb[k] = 0.0;
+                Jb[3 + k] = -c[k];
+            }
+            put_row6(L, r0 + 2 + e, Ja, la, Jb, lb, dot3(U[e], V[e]), kRowBilateral, P);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// block-wide reductions (fixed order: butterfly within a wave, then waves in
+// index order), results uniform across the workgroup
+// ---------------------------------------------------------------------------
+
+template <int NT>
+__device__ inline void reduce4(float &m0, float &m1, float &m2, float &s3, float *red) {
+    for (int off = 32; off > 0; off >>= 1) {
+        float o0 = __shfl_xor(m0, off, 64);
+        float o1 = __shfl_xor(m1, off, 64);
+        float o2 = __shfl_xor(m2, off, 64);
+        float o3 = __shfl_xor(s3, off, 64);
+        m0 = (o0 > m0 || o0 != o0) ? o0 : m0;
+        m1 = (o1 > m1 || o1 != o1) ? o1 : m1;
+        m2 = (o2 > m2 || o2 != o2) ? o2 : m2;
+        s3 = s3 + o3;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[4 * wave + 0] = m0;
+        red[4 * wave + 1] = m1;
+        red[4 * wave + 2] = m2;
+        red[4 * wave + 3] = s3;
+    }
+    __syncthreads();
+    m0 = red[0];
+    m1 = red[1];
+    m2 = red[2];
+    s3 = red[3];
+    for (int k = 1; k < NT / 64; ++k) {
+        float a = red[4 * k], b = red[4 * k + 1], c = red[4 * k + 2];
+        m0 = (a > m0 || a != a) ? a : m0;
+        m1 = (b > m1 || b != b) ? b : m1;
+        m2 = (c > m2 || c != c) ? c : m2;
+        s3 = s3 + red[4 * k + 3];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// matrix-free preconditioned Delassus product out = P J M^-1 J^T P x (Eq. 4),
+// accumulated in FP64 over the two 6-blocks of every row: bodies gather
+// their incident rows (fixed row order), rows then read their two bodies.
+// Costs O(rows) instead of O(rows^2); used for the refinement residual of
+// every x-update and for the dual residual.
+// ---------------------------------------------------------------------------
+
+template <int NT>
+__device__ inline void delassus_apply(const Lds &L, int m, int nb, const float *vp, const float *x, float *out) {
+    const int tid = threadIdx.x;
+    for (int b = tid; b < nb; b += NT) {
+        double g[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int k = L.inc_off[b]; k < L.inc_off[b + 1]; ++k) {
+            int e = L.inc_list[k];
+            int r = e >> 1, side = e & 1;
+            double xr = (double)vp[r] * (double)x[r];
+            for (int c = 0; c < 6; ++c) g[c] += (double)L.rf(RJ + 6 * side + c, r) * xr;
+        }
+        double im = L.bf(BIM, b);
+        double R[9], t[3], s[3];
+        for (int c = 0; c < 9; ++c) R[c] = L.bf(BR + c, b);
+        mtv3(R, g + 3, t);
+        for (int c = 0; c < 3; ++c) t[c] *= (double)L.bf(BII + c, b);
+        mv3(R, t, s);
+        for (int c = 0; c < 3; ++c) {
+            L.wb[c * kMaxBodies + b] = g[c] * im;
+            L.wb[(3 + c) * kMaxBodies + b] = s[c];
+        }
+    }
+    __syncthreads();
+    for (int r = tid; r < m; r += NT) {
+        int ia = L.ri(RIA, r), ib = L.ri(RIB, r);
+        double acc = 0.0;
+        for (int c = 0; c < 6; ++c) acc += (double)L.rf(RJ + c, r) * L.wb[c * kMaxBodies + ia];
+        if (ib >= 0)
+            for (int c = 0; c < 6; ++c) acc += (double)L.rf(RJ + 6 + c, r) * L.wb[c * kMaxBodies + ib];
+        out[r] = (float)(acc * (double)vp[r]);
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// the fused step kernel
+// ---------------------------------------------------------------------------
+
+template <int MC, int NT>
+__global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
+    extern __shared__ float4 smem4[];
+    float *sm = reinterpret_cast<float *>(smem4);
+    __shared__ int s_int[8];
+    const int tid = threadIdx.x;
+    const int w = a.bucket_worlds[blockIdx.x];
+    const WorldInfo W = a.worlds[w];
+    const SolverParams &P = a.p;
+
+    Lds L;
+    L.mc = MC;
+    L.b = sm;
+    L.j = L.b + body_floats();
+    L.c = L.j + joint_floats();
+    L.r = L.c + contact_floats();
+    L.v = L.r + row_floats(MC);
+    L.A = L.v + vec_floats(MC);
+    L.red = L.A + tri_row_offset(MC);
+    L.wb = reinterpret_cast<double *>(L.red + 64);
+    L.inc_off = reinterpret_cast<int *>(L.red + 64 + bodyw_floats());
+    L.inc_list = L.inc_off + kMaxBodies + 1;
+    float *A = L.A;
+
+    const int nb = W.nb, nj = W.nj;
+
+    // ---- reset: a world whose reset body fell below the threshold restarts
+    if (tid == 0) {
+        int rs = 0;
+        if (W.reset_body >= 0) {
+            float z = a.q[7 * (W.b0 + W.reset_body) + 2];
+            rs = z < P.reset_height;
+        }
+        s_int[0] = rs;
+        if (rs) a.reset_count[w] += 1;
+    }
+    __syncthreads();
+    const int reset = s_int[0];
+
+    // ---- bodies: state, rotation, inverse mass properties
+    for (int b = tid; b < nb; b += NT) {
+        int gb = W.b0 + b;
+        const float *qs = reset ? a.q0 : a.q;
+        const float *us = reset ? a.u0 : a.u;
+        float q[7];
+        for (int k = 0; k < 7; ++k) q[k] = qs[7 * gb + k];
+        for (int k = 0; k < 7; ++k) L.bf(BQ + k, b) = q[k];
+        for (int k = 0; k < 6; ++k) L.bf(BU + k, b) = us[6 * gb + k];
+        float R[9];
+        rot_of_quat(q + 3, R);
+        for (int k = 0; k < 9; ++k) L.bf(BR + k, b) = R[k];
+        for (int k = 0; k < 3; ++k) L.bf(BII + k, b) = 1.f / a.inertia[3 * gb + k];
+        L.bf(BIM, b) = 1.f / a.mass[gb];
+    }
+    __syncthreads();
+
+    // ---- joints: coordinate, rate and actuation (generalized force along
+    //      the coordinate: external + PD + noise)
+    for (int j = tid; j < nj; j += NT) {
+        int gj = W.j0 + j;
+        int type = a.jint[4 * gj], la = a.jint[4 * gj + 1], lb = a.jint[4 * gj + 2], fl = a.jint[4 * gj + 3];
+        const float *jf = a.jf + kJointFloats * gj;
+        JointGeo g;
+        joint_geo(L, jf, la, lb, g);
+        float Ja[6], Jb[6];
+        float c = (float)joint_coord(type, g, Ja, Jb);
+        float rate = 0.f;
+        for (int k = 0; k < 6; ++k) rate += Ja[k] * L.bf(BU + k, la);
+        if (lb >= 0)
+            for (int k = 0; k < 6; ++k) rate += Jb[k] * L.bf(BU + k, lb);
+        float tau = a.ext_tau ? a.ext_tau[gj] : 0.f;
+        float kp = jf[16], kd = jf[17], ref = jf[18];
+        if (kp != 0.f || kd != 0.f) tau += kp * (ref - c) - kd * rate;
+        if ((fl & kJointActuated) && P.torque_sigma != 0.f)
+            tau += P.torque_sigma * noise_normal(P.seed_lo, P.seed_hi, (uint32_t)w, a.step_index, (uint32_t)j);
+        L.jfld(JTAU, j) = tau;
+        for (int k = 0; k < 6; ++k) {
+            L.jfld(JC + k, j) = Ja[k];
+            L.jfld(JC + 6 + k, j) = Jb[k];
+        }
+        reinterpret_cast<int *>(L.j)[JA * kMaxJoints + j] = la;
+        reinterpret_cast<int *>(L.j)[JB * kMaxJoints + j] = lb;
+        reinterpret_cast<int *>(L.j)[JTF * kMaxJoints + j] = type | (fl << 4);
+        a.tau_out[gj] = tau;
+    }
+    __syncthreads();
+
+    // ---- free velocity of every body: u_f = u + dt M^-1 h
+    for (int b = tid; b < nb; b += NT) {
+        float m = 1.f / L.bf(BIM, b);
+        float h[6];
+        h[0] = m * P.gx;
+        h[1] = m * P.gy;
+        h[2] = m * P.gz;
+        // gyroscopic -w x (I_w w), I_w w evaluated in the body frame
+        float R[9], w3[3], t[3], Iw[3], gyro[3];
+        body_rot(L, b, R);
+        for (int k = 0; k < 3; ++k) w3[k] = L.bf(BU + 3 + k, b);
+        mtv3(R, w3, t);
+        for (int k = 0; k < 3; ++k) t[k] /= L.bf(BII + k, b);
+        mv3(R, t, Iw);
+        cross(w3, Iw, gyro);
+        h[3] = -gyro[0];
+        h[4] = -gyro[1];
+        h[5] = -gyro[2];
+        const int *ja = reinterpret_cast<const int *>(L.j) + JA * kMaxJoints;
+        const int *jb = reinterpret_cast<const int *>(L.j) + JB * kMaxJoints;
+        for (int j = 0; j < nj; ++j) {
+            float tau = L.jfld(JTAU, j);
+            if (tau == 0.f) continue;
+            if (ja[j] == b)
+                for (int k = 0; k < 6; ++k) h[k] += tau * L.jfld(JC + k, j);
+            if (jb[j] == b)
+                for (int k = 0; k < 6; ++k) h[k] += tau * L.jfld(JC + 6 + k, j);
+        }
+        float dv[6];
+        apply_minv(L, b, h, dv);
+        for (int k = 0; k < 6; ++k) L.bf(BUF + k, b) = L.bf(BU + k, b) + P.dt * dv[k];
+    }
+
+    // ---- contacts: explicit list, or probes below the margin (compacted in
+    //      probe order by a wave ballot)
+    int *cint = reinterpret_cast<int *>(L.c);
+    if (a.contacts) {
+        int c0 = a.coff[w];
+        int n = a.coff[w + 1] - c0;
+        if (n > W.contact_cap) n = W.contact_cap;
+        if (n < 0) n = 0;
+        if (tid == 0) s_int[1] = n;
+        for (int c = tid; c < n; c += NT) {
+            kamx_contact ct = a.contacts[c0 + c];
+            int la = ct.body_a - W.b0;
+            int lb = ct.body_b < 0 ? -1 : ct.body_b - W.b0;
+            bool ok = la >= 0 && la < nb && lb < nb;
+            for (int k = 0; k < 3; ++k) {
+                L.cf(CP + k, c) = ct.point[k];
+                L.cf(CN + k, c) = ct.normal[k];
+            }
+            L.cf(CGAP, c) = ct.gap;
+            L.cf(CMU, c) = ct.mu;
+            // an invalid body index turns the contact into an inert row pair
+            cint[CA * kMaxContacts + c] = ok ? la : 0;
+            cint[CB * kMaxContacts + c] = ok ? lb : -1;
+            if (!ok) L.cf(CGAP, c) = 1e30f;
+            cint[CKEY * kMaxContacts + c] = ct.key;
+        }
+    } else if (tid < 64) {
+        int k = tid;
+        bool act = false;
+        float pw[3] = {0.f, 0.f, 0.f};
+        int lbod = 0;
+        float mu = 0.f;
+        if (k < W.np) {
+            int gp = W.p0 + k;
+            lbod = a.pbody[gp];
+            float pl[3] = {a.pf[4 * gp], a.pf[4 * gp + 1], a.pf[4 * gp + 2]};
+            mu = a.pf[4 * gp + 3];
+            // world point in FP64 (its height is the gap, which enters the
+            // bias divided by dt), then rounded to FP32
+            double qd[4], Rd[9], pld[3] = {pl[0], pl[1], pl[2]}, td[3];
+            for (int e = 0; e < 4; ++e) qd[e] = L.bf(BQ + 3 + e, lbod);
+            rot_of_quat(qd, Rd);
+            mv3(Rd, pld, td);
+            for (int e = 0; e < 3; ++e) pw[e] = (float)((double)L.bf(BQ + e, lbod) + td[e]);
+            act = pw[2] < P.contact_margin;
+        }
+        unsigned long long mask = __ballot(act);
+        int slot = __popcll(mask & ((1ull << k) - 1ull));
+        if (act && slot < W.contact_cap) {
+            for (int e = 0; e < 3; ++e) L.cf(CP + e, slot) = pw[e];
+            L.cf(CN + 0, slot) = 0.f;
+            L.cf(CN + 1, slot) = 0.f;
+            L.cf(CN + 2, slot) = 1.f;
+            L.cf(CGAP, slot) = pw[2];
+            L.cf(CMU, slot) = mu;
+            cint[CA * kMaxContacts + slot] = lbod;
+            cint[CB * kMaxContacts + slot] = -1;
+            cint[CKEY * kMaxContacts + slot] = k;
+        }
+        if (k == 0) {
+            int n = __popcll(mask);
+            s_int[1] = n < W.contact_cap ? n : W.contact_cap;
+        }
+    }
+    __syncthreads();
+    const int nc = s_int[1];
+    const int row_lim0 = 5 * nj;
+    const int row_c0 = 5 * nj + W.nlim;
+    const int m = row_c0 + 3 * nc;
+
+    // ---- constraint rows
+    for (int j = tid; j < nj; j += NT) {
+        int gj = W.j0 + j;
+        int type = a.jint[4 * gj], la = a.jint[4 * gj + 1], lb = a.jint[4 * gj + 2], fl = a.jint[4 * gj + 3];
+        const float *jf = a.jf + kJointFloats * gj;
+        JointGeo g;
+        joint_geo(L, jf, la, lb, g);
+        joint_rows(L, type, g, la, lb, 5 * j, P);
+        if (fl & kJointLimited) {
+            int rank = 0;
+            const int *tf = reinterpret_cast<const int *>(L.j) + JTF * kMaxJoints;
+            for (int k = 0; k < j; ++k) rank += (tf[k] >> 4) & kJointLimited ? 1 : 0;
+            float Ja[6], Jb[6];
+            double c = joint_coord(type, g, Ja, Jb);
+            double lo = jf[14], hi = jf[15];
+            bool use_lo;
+            if (isnan(hi)) use_lo = true;
+            else if (isnan(lo)) use_lo = false;
+            else use_lo = (c - lo) <= (hi - c);
+            float sg = use_lo ? 1.f : -1.f;
+            float gval = (float)(use_lo ? c - lo : hi - c);
+            for (int k = 0; k < 6; ++k) {
+                Ja[k] *= sg;
+                Jb[k] *= sg;
+            }
+            put_row(L, row_lim0 + rank, Ja, la, Jb, lb, gval, kRowLimit, 0.f, P);
+        }
+    }
+    for (int c = tid; c < nc; c += NT) {
+        float p[3], n[3], t1[3], t2[3];
+        for (int k = 0; k < 3; ++k) {
+            p[k] = L.cf(CP + k, c);
+            n[k] = L.cf(CN + k, c);
+        }
+        tangents(n, t1, t2);
+        const float *dirs[3] = {n, t1, t2};
+        int la = cint[CA * kMaxContacts + c], lb = cint[CB * kMaxContacts + c];
+        float arm_a[3], arm_b[3] = {0.f, 0.f, 0.f};
+        for (int k = 0; k < 3; ++k) {
+            arm_a[k] = p[k] - L.bf(BQ + k, la);
+            if (lb >= 0) arm_b[k] = p[k] - L.bf(BQ + k, lb);
+        }
+        for (int e = 0; e < 3; ++e) {
+            float Ja[6], Jb[6], cc[3];
+            cross(arm_a, dirs[e], cc);
+            for (int k = 0; k < 3; ++k) {
+                Ja[k] = dirs[e][k];
+                Ja[3 + k] = cc[k];
+            }
+            cross(arm_b, dirs[e], cc);
+            for (int k = 0; k < 3; ++k) {
+                Jb[k] = -dirs[e][k];
+                Jb[3 + k] = -cc[k];
+            }
+            put_row(L, row_c0 + 3 * c + e, Ja, la, Jb, lb, e == 0 ? L.cf(CGAP, c) : 0.f,
+                    e == 0 ? kRowNormal : kRowTangent, L.cf(CMU, c), P);
+        }
+    }
+    __syncthreads();
+
+    // ---- W = M^-1 J^T for both sides of every row (in the vector region)
+    float *Wv = L.v;  // [12][MC]
+    for (int r = tid; r < m; r += NT) {
+        for (int s = 0; s < 2; ++s) {
+            int b = L.ri(s ? RIB : RIA, r);
+            float in[6], out[6];
+            for (int k = 0; k < 6; ++k) in[k] = L.rf(RJ + 6 * s + k, r);
+            if (b >= 0) apply_minv(L, b, in, out);
+            else
+                for (int k = 0; k < 6; ++k) out[k] = 0.f;
+            for (int k = 0; k < 6; ++k) Wv[(6 * s + k) * MC + r] = out[k];
+        }
+    }
+    __syncthreads();
+
+    // ---- D = J M^-1 J^T, packed lower triangle (rows padded to 4 floats)
+    const int i = tid;
+    if (i < m) {
+        float Ji[12];
+        for (int k = 0; k < 12; ++k) Ji[k] = L.rf(RJ + k, i);
+        int ia = L.ri(RIA, i), ib = L.ri(RIB, i);
+        float *Ri = A + tri_row_offset(i);
+        for (int j = 0; j <= i; ++j) {
+            int ja = L.ri(RIA, j), jb = L.ri(RIB, j);
+            float acc = 0.f;
+            if (ia == ja)
+                for (int k = 0; k < 6; ++k) acc += Ji[k] * Wv[k * MC + j];
+            if (ia == jb && jb >= 0)
+                for (int k = 0; k < 6; ++k) acc += Ji[k] * Wv[(6 + k) * MC + j];
+            if (ib >= 0 && ib == ja)
+                for (int k = 0; k < 6; ++k) acc += Ji[6 + k] * Wv[k * MC + j];
+            if (ib >= 0 && ib == jb)
+                for (int k = 0; k < 6; ++k) acc += Ji[6 + k] * Wv[(6 + k) * MC + j];
+            Ri[j] = acc;
+        }
+        for (int j = i + 1; j < ((i + 4) & ~3); ++j) Ri[j] = 0.f;
+    }
+    __syncthreads();
+
+    // ---- preconditioner (Sec. 4.1): per row, one scalar per contact block
+    float *vp = L.vec(VP), *vrho = L.vec(VRHO), *vvt = L.vec(VVT);
+    // the vector region held W until now: clear it (pads must read as 0)
+    float pi_reg = 1.f;
+    {
+        float p_own[3] = {1.f, 1.f, 1.f};
+        int kind = i < m ? L.ri(RKIND, i) : -1;
+        if (i < m && P.precond) {
+            if (kind == kRowNormal) {
+                float t = (A[tri_row_offset(i) + i] + A[tri_row_offset(i + 1) + i + 1] + A[tri_row_offset(i + 2) + i + 2]) *
+                          (1.f / 3.f);
+                float s = t > 0.f ? 1.f / sqrtf(t) : 1.f;
+                p_own[0] = p_own[1] = p_own[2] = s;
+            } else if (kind != kRowTangent) {
+                float t = A[tri_row_offset(i) + i];
+                p_own[0] = t > 0.f ? 1.f / sqrtf(t) : 1.f;
+            }
+        }
+        __syncthreads();  // every thread has read W / D diagonals
+        for (int k = tid; k < vec_floats(MC); k += NT) L.v[k] = 0.f;
+        __syncthreads();
+        if (i < m) {
+            if (kind == kRowNormal) {
+                vp[i] = vp[i + 1] = vp[i + 2] = p_own[0];
+            } else if (kind != kRowTangent) {
+                vp[i] = p_own[0];
+            }
+            vrho[i] = kind == kRowBilateral ? P.rho_bil : P.rho_c;
+        }
+        __syncthreads();
+        if (i < m) pi_reg = vp[i];
+    }
+    // scale D, add the shift, and form v~_f = P (J u_f + v*)
+    if (i < m) {
+        float *Ri = A + tri_row_offset(i);
+        for (int j = 0; j <= i; ++j) Ri[j] *= pi_reg * vp[j];
+        Ri[i] += P.eta + vrho[i];
+        float v = L.rf(RBIAS, i);
+        int ia = L.ri(RIA, i), ib = L.ri(RIB, i);
+        for (int k = 0; k < 6; ++k) v += L.rf(RJ + k, i) * L.bf(BUF + k, ia);
+        if (ib >= 0)
+            for (int k = 0; k < 6; ++k) v += L.rf(RJ + 6 + k, i) * L.bf(BUF + k, ib);
+        vvt[i] = pi_reg * v;
+    }
+    __syncthreads();
+
+    // ---- body -> row incidence lists (CSR, rows in increasing order)
+    for (int b = tid; b < nb; b += NT) {
+        int cnt = 0;
+        for (int r = 0; r < m; ++r) cnt += (L.ri(RIA, r) == b) + (L.ri(RIB, r) == b);
+        L.inc_off[b + 1] = cnt;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        L.inc_off[0] = 0;
+        for (int b = 0; b < nb; ++b) L.inc_off[b + 1] += L.inc_off[b];
+    }
+    __syncthreads();
+    for (int b = tid; b < nb; b += NT) {
+        int k = L.inc_off[b];
+        for (int r = 0; r < m; ++r) {
+            if (L.ri(RIA, r) == b) L.inc_list[k++] = r << 1;
+            if (L.ri(RIB, r) == b) L.inc_list[k++] = (r << 1) | 1;
+        }
+    }
+    __syncthreads();
+
+    // ---- warm start (Alg. 1 step 2; Sec. 4.1): y = x = Pi_K(lambda_ws / p),
+    //      z = v~(y) + Gamma(v~(y)) on unilateral rows, 0 on bilateral rows
+    float *vx = L.vec(VX), *vyh = L.vec(VYH), *vzh = L.vec(VZH), *vyp = L.vec(VYP), *vzp = L.vec(VZP);
+    float *vrhs = L.vec(VRHS), *vt = L.vec(VT), *vxn = L.vec(VXN), *vws = L.vec(VWS), *vaux = L.vec(VAUX);
+    float *vcol = L.vec(VCOL), *vdx = L.vec(VDX);
+    const int wmode = reset ? KAMX_WARM_COLD : P.warmstart;
+    const int kind_i = i < m ? L.ri(RKIND, i) : -1;
+    const bool owner = i < m && kind_i != kRowTangent;
+    const int blk = kind_i == kRowNormal ? 3 : 1;
+    if (wmode != KAMX_WARM_COLD) {
+        if (i < m) {
+            float lw = 0.f;
+            if (wmode == KAMX_WARM_EXTERNAL) {
+                lw = a.lambda_ext[W.row_base + i];
+            } else if (i < row_c0) {
+                lw = a.lambda[W.row_base + i];
+            } else {
+                // previous-step cache matched by contact key
+                int c = (i - row_c0) / 3, e = (i - row_c0) % 3;
+                int key = cint[CKEY * kMaxContacts + c];
+                int nprev = a.ncontacts_out[w];
+                for (int k = 0; k < nprev && k < kMaxContacts; ++k)
+                    if (a.keys[w * kMaxContacts + k] == key) {
+                        lw = a.lambda[W.row_base + row_c0 + 3 * k + e];
+                        break;
+                    }
+            }
+            vws[i] = isfinite(lw) ? lw / vp[i] : 0.f;
+        }
+        __syncthreads();
+        if (owner) {
+            if (kind_i == kRowNormal) {
+                float o0, o1, o2;
+                proj_cone(L.rf(RMU, i), vws[i], vws[i + 1], vws[i + 2], o0, o1, o2);
+                vyp[i] = o0;
+                vyp[i + 1] = o1;
+                vyp[i + 2] = o2;
+            } else if (kind_i == kRowLimit) {
+                vyp[i] = fmaxf(vws[i], 0.f);
+            } else {
+                vyp[i] = vws[i];
+            }
+        }
+        __syncthreads();
+        delassus_apply<NT>(L, m, nb, vp, vyp, vdx);  // D~ y0 (x0 = y0)
+        if (owner) {
+            float v0 = vdx[i] + vvt[i];
+            if (kind_i == kRowNormal) {
+                float v1 = vdx[i + 1] + vvt[i + 1], v2 = vdx[i + 2] + vvt[i + 2];
+                vzp[i] = v0 + L.rf(RMU, i) * sqrtf(v1 * v1 + v2 * v2);
+                vzp[i + 1] = v1;
+                vzp[i + 2] = v2;
+            } else if (kind_i == kRowLimit) {
+                vzp[i] = v0;
+            } else {
+                vzp[i] = 0.f;
+            }
+            for (int e = 0; e < blk; ++e) {
+                vx[i + e] = vyp[i + e];
+                vyh[i + e] = vyp[i + e];
+                vzh[i + e] = vzp[i + e];
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- Cholesky of D~ + diag(eta + rho), in place (Alg. 1 step 1)
+    if (tid == 0) s_int[2] = 0;
+    for (int j = 0; j < m; ++j) {
+        if (i >= j && i < m) {
+            const float *Ri = A + tri_row_offset(i);
+            const float *Rj = A + tri_row_offset(j);
+            float acc = Ri[j];
+            int k = 0;
+            for (; k + 4 <= j; k += 4) {
+                float4 x4 = *reinterpret_cast<const float4 *>(Ri + k);
+                float4 y4 = *reinterpret_cast<const float4 *>(Rj + k);
+                acc -= x4.x * y4.x;
+                acc -= x4.y * y4.y;
+                acc -= x4.z * y4.z;
+                acc -= x4.w * y4.w;
+            }
+            for (; k < j; ++k) acc -= Ri[k] * Rj[k];
+            vcol[i] = acc;
+        }
+        __syncthreads();
+        float d = vcol[j];
+        if (!(d > 0.f) || !isfinite(d)) {
+            if (tid == 0) s_int[2] = 1;
+            break;
+        }
+        float ljj = sqrtf(d);
+        if (i == j) A[tri_row_offset(i) + j] = ljj;
+        else if (i > j && i < m) A[tri_row_offset(i) + j] = vcol[i] / ljj;
+        __syncthreads();
+    }
+    __syncthreads();
+    const int factor_fail = s_int[2];
+
+    // ---- explicit inverse of the factor, in place: X = L^-1
+    if (!factor_fail) {
+        for (int j = m - 1; j >= 0; --j) {
+            float ljj = A[tri_row_offset(j) + j];
+            if (i < MC) vcol[i] = (i > j && i < m) ? A[tri_row_offset(i) + j] : 0.f;
+            __syncthreads();
+            float inv = 1.f / ljj;
+            if (i > j && i < m) {
+                const float *Ri = A + tri_row_offset(i);
+                int k0 = (j + 1) & ~3;
+                int k1 = (i + 4) & ~3;
+                float acc = 0.f;
+                for (int k = k0; k < k1; k += 4) {
+                    float4 x4 = *reinterpret_cast<const float4 *>(Ri + k);
+                    float4 c4 = *reinterpret_cast<const float4 *>(vcol + k);
+                    acc += x4.x * c4.x;
+                    acc += x4.y * c4.y;
+                    acc += x4.z * c4.z;
+                    acc += x4.w * c4.w;
+                }
+                A[tri_row_offset(i) + j] = -acc * inv;
+            } else if (i == j) {
+                A[tri_row_offset(i) + j] = inv;
+            }
+            __syncthreads();
+        }
+    }
+
+    // ---- PADMM (Alg. 1 steps 3-10).  The x-update of step 5 is computed as
+    //      x + X^T X (rhs - (D~ + eta + rho) x): one refinement step from the
+    //      previous iterate with the FP32 factor inverse and an FP64
+    //      matrix-free residual, so the fixed point solves the linear system
+    //      to the accuracy of the residual, not to cond(D~) times FP32 epsilon.
+    const float eta = P.eta;
+    const float rho_i = i < m ? vrho[i] : 1.f;
+    const float mu_i = i < m ? L.rf(RMU, i) : 0.f;
+    float a_k = 1.f, c_prev = INFINITY;
+    int it = 0, status = 0;
+    float rp = 0.f, rd = 0.f, rc = 0.f, rncp = 0.f;
+    const int N = P.fixed_iters > 0 ? P.fixed_iters : P.max_iters;
+    if (factor_fail) {
+        status = KAMX_WORLD_FACTOR_FAIL;
+        rp = rd = rc = rncp = NAN;
+        if (i < m) vyp[i] = 0.f;
+    } else {
+        if (wmode == KAMX_WARM_COLD && i < m) {
+            vx[i] = vyh[i] = vzh[i] = vyp[i] = vzp[i] = vdx[i] = 0.f;
+        }
+        bool converged = false;
+        float s_own = 0.f;
+        __syncthreads();
+        for (it = 1; it <= N; ++it) {
+            // steps 4-5: rhs = -v~_f - Gamma(z^) + eta x + rho y^ + z^, and its
+            // residual against the current x
+            if (owner) {
+                s_own = kind_i == kRowNormal ? mu_i * sqrtf(vzh[i + 1] * vzh[i + 1] + vzh[i + 2] * vzh[i + 2]) : 0.f;
+                for (int e = 0; e < blk; ++e) {
+                    float rr = e == 0 ? rho_i : vrho[i + e];
+                    float xe = vx[i + e];
+                    float rhs = -vvt[i + e] - (e == 0 ? s_own : 0.f) + eta * xe + rr * vyh[i + e] + vzh[i + e];
+                    vrhs[i + e] = rhs - (vdx[i + e] + (eta + rr) * xe);
+                }
+            }
+            __syncthreads();
+            // t = X r (rows of X)
+            if (i < m) {
+                const float *Ri = A + tri_row_offset(i);
+                float acc = 0.f;
+                int k1 = (i + 4) & ~3;
+                for (int k = 0; k < k1; k += 4) {
+                    float4 x4 = *reinterpret_cast<const float4 *>(Ri + k);
+                    float4 r4 = *reinterpret_cast<const float4 *>(vrhs + k);
+                    acc += x4.x * r4.x;
+                    acc += x4.y * r4.y;
+                    acc += x4.z * r4.z;
+                    acc += x4.w * r4.w;
+                }
+                vt[i] = acc;
+            }
+            __syncthreads();
+            // x_new = x + X^T t (columns of X)
+            if (i < m) {
+                float acc = 0.f;
+                for (int r = (i & ~63); r < m; ++r)
+                    if (r >= i) acc += A[tri_row_offset(r) + i] * vt[r];
+                vxn[i] = vx[i] + acc;
+            }
+            __syncthreads();
+            // v~ - v~_f = D~ x_new (matrix-free, FP64 accumulation)
+            delassus_apply<NT>(L, m, nb, vp, vxn, vdx);
+            // steps 6-7 and the residuals of step 9 (block owners)
+            float lrp = 0.f, lrd = 0.f, lrc = 0.f, lcc = 0.f;
+            float yb[3], zb[3];
+            if (owner) {
+                float xn[3], zh[3], yh[3], rr[3], vv[3];
+                for (int e = 0; e < blk; ++e) {
+                    xn[e] = vxn[i + e];
+                    zh[e] = vzh[i + e];
+                    yh[e] = vyh[i + e];
+                    rr[e] = e == 0 ? rho_i : vrho[i + e];
+                    vv[e] = vdx[i + e] + vvt[i + e];
+                }
+                if (kind_i == kRowNormal) {
+                    proj_cone(mu_i, xn[0] - zh[0] / rr[0], xn[1] - zh[1] / rr[1], xn[2] - zh[2] / rr[2], yb[0], yb[1],
+                              yb[2]);
+                } else if (kind_i == kRowLimit) {
+                    yb[0] = fmaxf(xn[0] - zh[0] / rr[0], 0.f);
+                } else {
+                    yb[0] = xn[0] - zh[0] / rr[0];
+                }
+                for (int e = 0; e < blk; ++e) {
+                    zb[e] = zh[e] - rr[e] * (xn[e] - yb[e]);
+                    lrp = fmaxf(lrp, fabsf(xn[e] - yb[e]));
+                    float dy = yb[e] - yh[e], dz = zb[e] - zh[e];
+                    lcc += rr[e] * dy * dy + dz * dz / rr[e];
+                }
+                float g = kind_i == kRowNormal ? mu_i * sqrtf(vv[1] * vv[1] + vv[2] * vv[2]) : 0.f;
+                for (int e = 0; e < blk; ++e) {
+                    float d = vv[e] + (e == 0 ? g : 0.f) - zb[e];
+                    lrd = fmaxf(lrd, fabsf(d));
+                    if (d != d) lrd = d;
+                }
+                if (kind_i == kRowNormal) lrc = fabsf(yb[0] * (vv[0] + g) + yb[1] * vv[1] + yb[2] * vv[2]);
+                else if (kind_i == kRowLimit) lrc = fabsf(yb[0] * vv[0]);
+                if (lrp != lrp || lcc != lcc) lrp = NAN;
+            }
+            reduce4<NT>(lrp, lrd, lrc, lcc, L.red);
+            rp = lrp;
+            rd = lrd;
+            rc = lrc;
+            // step 8: Nesterov with adaptive restart
+            int restart = 0;
+            float beta = 0.f;
+            if (P.accel) {
+                restart = !(lcc < P.restart_factor * c_prev);
+                if (!restart) {
+                    float a_next = 0.5f * (1.f + sqrtf(1.f + 4.f * a_k * a_k));
+                    beta = (a_k - 1.f) / a_next;
+                    a_k = a_next;
+                    c_prev = lcc;
+                } else {
+                    a_k = 1.f;
+                    c_prev = c_prev / P.restart_factor;
+                }
+            }
+            if (owner) {
+                for (int e = 0; e < blk; ++e) {
+                    float yo = vyp[i + e], zo = vzp[i + e];
+                    if (!P.accel) {
+                        vyh[i + e] = yb[e];
+                        vzh[i + e] = zb[e];
+                    } else if (!restart) {
+                        vyh[i + e] = yb[e] + beta * (yb[e] - yo);
+                        vzh[i + e] = zb[e] + beta * (zb[e] - zo);
+                    } else {
+                        vyh[i + e] = yo;
+                        vzh[i + e] = zo;
+                    }
+                    vx[i + e] = vxn[i + e];
+                    vyp[i + e] = yb[e];
+                    vzp[i + e] = zb[e];
+                }
+            }
+            if (tid == 0 && a.rlog && P.log_restarts && it <= P.max_iters)
+                a.rlog[(size_t)w * P.max_iters + (it - 1)] = (uint8_t)restart;
+            if (!(isfinite(rp) && isfinite(rd) && isfinite(rc))) {
+                status = KAMX_WORLD_NONFINITE;
+                break;
+            }
+            if (P.fixed_iters <= 0 && rp < P.eps && rd < P.eps && rc < P.eps) {
+                converged = true;
+                break;
+            }
+        }
+        if (it > N) it = N;
+        if (P.fixed_iters <= 0 && !converged && status == 0) status = KAMX_WORLD_MAXITER;
+        __syncthreads();
+        // natural-map residual of the NCP at the returned y (Eq. 3)
+        delassus_apply<NT>(L, m, nb, vp, vyp, vaux);
+        float lncp = 0.f;
+        if (owner) {
+            float v[3], o[3], y[3], nm[3];
+            for (int e = 0; e < blk; ++e) {
+                v[e] = vaux[i + e] + vvt[i + e];
+                y[e] = vyp[i + e];
+            }
+            float g = kind_i == kRowNormal ? mu_i * sqrtf(v[1] * v[1] + v[2] * v[2]) : 0.f;
+            for (int e = 0; e < blk; ++e) nm[e] = y[e] - (v[e] + (e == 0 ? g : 0.f));
+            if (kind_i == kRowNormal) proj_cone(mu_i, nm[0], nm[1], nm[2], o[0], o[1], o[2]);
+            else if (kind_i == kRowLimit) o[0] = fmaxf(nm[0], 0.f);
+            else o[0] = nm[0];
+            for (int e = 0; e < blk; ++e) lncp = fmaxf(lncp, fabsf(y[e] - o[e]));
+        }
+        float l1 = 0.f, l2 = 0.f, l3 = 0.f;
+        reduce4<NT>(lncp, l1, l2, l3, L.red);
+        rncp = lncp;
+    }
+    __syncthreads();
+
+    // ---- outputs: lambda = P y (Alg. 1 step 11), stats, caches
+    if (i < W.row_cap) {
+        float lam = 0.f;
+        if (i < m) lam = vp[i] * vyp[i];
+        a.lambda[W.row_base + i] = lam;
+        if (i < m) vaux[i] = lam;
+    }
+    if (tid == 0) {
+        a.iters[w] = it;
+        a.status[w] = status;
+        a.rows[w] = m;
+        a.resid[4 * w + 0] = rp;
+        a.resid[4 * w + 1] = rd;
+        a.resid[4 * w + 2] = rc;
+        a.resid[4 * w + 3] = rncp;
+        a.ncontacts_out[w] = nc;
+    }
+    for (int c = tid; c < nc; c += NT) {
+        kamx_contact ct;
+        ct.body_a = cint[CA * kMaxContacts + c] + W.b0;
+        int lb = cint[CB * kMaxContacts + c];
+        ct.body_b = lb >= 0 ? lb + W.b0 : -1;
+        for (int k = 0; k < 3; ++k) {
+            ct.point[k] = L.cf(CP + k, c);
+            ct.normal[k] = L.cf(CN + k, c);
+        }
+        ct.gap = L.cf(CGAP, c);
+        ct.mu = L.cf(CMU, c);
+        ct.key = cint[CKEY * kMaxContacts + c];
+        a.contacts_out[w * kMaxContacts + c] = ct;
+        a.keys[w * kMaxContacts + c] = ct.key;
+    }
+    __syncthreads();
+
+    // ---- u+ = u_f + M^-1 J^T lambda (FP64 accumulation over the incident
+    //      rows: light links carry large, nearly cancelling impulses), then
+    //      poses by the exponential map
+    for (int b = tid; b < nb; b += NT) {
+        double imp[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int k = L.inc_off[b]; k < L.inc_off[b + 1]; ++k) {
+            int e = L.inc_list[k];
+            int r = e >> 1, side = e & 1;
+            double lam = (double)vp[r] * (double)vyp[r];
+            if (factor_fail) lam = 0.0;
+            for (int c = 0; c < 6; ++c) imp[c] += (double)L.rf(RJ + 6 * side + c, r) * lam;
+        }
+        double R[9], t[3], sv[3];
+        for (int c = 0; c < 9; ++c) R[c] = L.bf(BR + c, b);
+        mtv3(R, imp + 3, t);
+        for (int c = 0; c < 3; ++c) t[c] *= (double)L.bf(BII + c, b);
+        mv3(R, t, sv);
+        double im = L.bf(BIM, b);
+        float un[6];
+        for (int c = 0; c < 3; ++c) {
+            un[c] = (float)((double)L.bf(BUF + c, b) + imp[c] * im);
+            un[3 + c] = (float)((double)L.bf(BUF + 3 + c, b) + sv[c]);
+        }
+        int gb = W.b0 + b;
+        for (int k = 0; k < 6; ++k) a.u[6 * gb + k] = un[k];
+        float q[4], dq[4] = {0.f, 0.f, 0.f, 1.f}, qn[4];
+        for (int k = 0; k < 4; ++k) q[k] = L.bf(BQ + 3 + k, b);
+        for (int k = 0; k < 3; ++k) a.q[7 * gb + k] = L.bf(BQ + k, b) + P.dt * un[k];
+        float wn = sqrtf(un[3] * un[3] + un[4] * un[4] + un[5] * un[5]);
+        if (wn > 0.f) {
+            float half = 0.5f * P.dt * wn;
+            float sh = sinf(half) / wn;
+            dq[0] = un[3] * sh;
+            dq[1] = un[4] * sh;
+            dq[2] = un[5] * sh;
+            dq[3] = cosf(half);
+        }
+        qprod(dq, q, qn);
+        float nn = 1.f / sqrtf(qn[0] * qn[0] + qn[1] * qn[1] + qn[2] * qn[2] + qn[3] * qn[3]);
+        for (int k = 0; k < 4; ++k) a.q[7 * gb + 3 + k] = qn[k] * nn;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launch table
+// ---------------------------------------------------------------------------
+
+template <int MC>
+static hipError_t launch_mc(const StepArgs &args, int n, hipStream_t stream) {
+    constexpr int NT = MC <= 64 ? 64 : ((MC + 63) / 64) * 64;
+    size_t bytes = sizeof(float) * (size_t)smem_floats(MC);
+    static bool configured = false;
+    if (!configured) {
+        hipError_t e = hipFuncSetAttribute((const void *)step_kernel<MC, NT>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+        configured = true;
+    }
+    hipLaunchKernelGGL((step_kernel<MC, NT>), dim3(n), dim3(NT), bytes, stream, args);
+    return hipGetLastError();
+}
+
+int bucket_capacity(int rows) {
+    static const int caps[] = {32, 64, 96, 128, 160, 192, 224};
+    for (int c : caps)
+        if (rows <= c) return c;
+    return -1;
+}
+
+hipError_t launch_step(const StepArgs &args, int mc, int n, hipStream_t stream) {
+    switch (mc) {
+    case 32: return launch_mc<32>(args, n, stream);
+    case 64: return launch_mc<64>(args, n, stream);
+    case 96: return launch_mc<96>(args, n, stream);
+    case 128: return launch_mc<128>(args, n, stream);
+    case 160: return launch_mc<160>(args, n, stream);
+    case 192: return launch_mc<192>(args, n, stream);
+    case 224: return launch_mc<224>(args, n, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+size_t step_smem_bytes(int mc) { return sizeof(float) * (size_t)smem_floats(mc); }
+
+}  // namespace kamx

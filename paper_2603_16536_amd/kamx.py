@@ -1,0 +1,356 @@
+"""Python binding of libkamx (ctypes): argument marshalling only.
+
+Every step of the solver runs in the HIP kernels of ``libkamx.so``; this
+module builds descriptor arrays from a :class:`scenes.Scene`, hands torch
+device pointers and streams to the C entry points, and wraps the results as
+torch tensors.  It fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import math
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libkamx.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+WORLD_OK, WORLD_MAXITER, WORLD_NONFINITE, WORLD_FACTOR_FAIL = 0, 1, 2, 4
+WARM_COLD, WARM_PREVIOUS, WARM_EXTERNAL = 0, 1, 2
+MAX_CONTACTS_PER_WORLD = 64
+
+
+class kamx_params(C.Structure):
+    _fields_ = [
+        ("dt", C.c_float), ("gravity", C.c_float * 3), ("eta", C.c_float), ("rho_bilateral", C.c_float),
+        ("rho_contact", C.c_float), ("eps", C.c_float), ("max_iters", C.c_int32), ("fixed_iters", C.c_int32),
+        ("accel", C.c_int32), ("restart_factor", C.c_float), ("precond", C.c_int32), ("baumgarte", C.c_float),
+        ("warmstart", C.c_int32), ("contact_margin", C.c_float), ("torque_sigma", C.c_float),
+        ("seed", C.c_uint64), ("reset_height", C.c_float), ("log_restarts", C.c_int32),
+    ]
+
+
+class kamx_body_desc(C.Structure):
+    _fields_ = [("world", C.c_int32), ("mass", C.c_float), ("inertia", C.c_float * 3)]
+
+
+class kamx_joint_desc(C.Structure):
+    _fields_ = [
+        ("type", C.c_int32), ("world", C.c_int32), ("body_a", C.c_int32), ("body_b", C.c_int32),
+        ("frame_a", C.c_float * 7), ("frame_b", C.c_float * 7), ("limit_lo", C.c_float), ("limit_hi", C.c_float),
+        ("kp", C.c_float), ("kd", C.c_float), ("ref", C.c_float), ("actuated", C.c_int32),
+    ]
+
+
+class kamx_probe_desc(C.Structure):
+    _fields_ = [("world", C.c_int32), ("body", C.c_int32), ("point", C.c_float * 3), ("mu", C.c_float)]
+
+
+CONTACT_DTYPE = np.dtype([("body_a", "<i4"), ("body_b", "<i4"), ("point", "<f4", 3), ("normal", "<f4", 3),
+                          ("gap", "<f4"), ("mu", "<f4"), ("key", "<i4")])
+assert CONTACT_DTYPE.itemsize == 44
+
+_lib = None
+
+
+def lib():
+    """Load libkamx.so; raises if it is missing (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64p = C.c_void_p, C.c_int32, C.POINTER(C.c_int64)
+        L.kamx_default_params.argtypes = [C.POINTER(kamx_params)]
+        L.kamx_default_params.restype = None
+        L.kamx_last_error.restype = C.c_char_p
+        L.kamx_model_create.argtypes = [C.POINTER(kamx_body_desc), i32, C.POINTER(kamx_joint_desc), i32,
+                                        C.POINTER(kamx_probe_desc), i32, C.POINTER(C.c_int32), i32, i32,
+                                        C.POINTER(kamx_params), C.POINTER(vp)]
+        L.kamx_model_destroy.argtypes = [vp]
+        L.kamx_set_params.argtypes = [vp, C.POINTER(kamx_params)]
+        L.kamx_model_info.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.kamx_state_upload.argtypes = [vp, vp, vp, i32, vp]
+        L.kamx_state_download.argtypes = [vp, vp, vp, vp]
+        L.kamx_contacts_upload.argtypes = [vp, vp, C.POINTER(C.c_int32), vp]
+        L.kamx_set_external.argtypes = [vp, vp, vp]
+        L.kamx_set_warmstart.argtypes = [vp, vp, vp]
+        L.kamx_step.argtypes = [vp, i32, vp]
+        L.kamx_read_impulses.argtypes = [vp, vp, vp]
+        L.kamx_read_stats.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.kamx_read_restart_log.argtypes = [vp, vp, vp]
+        L.kamx_read_torques.argtypes = [vp, vp, vp]
+        L.kamx_read_contacts.argtypes = [vp, vp, vp, vp]
+        L.kamx_reset_count.argtypes = [vp, i64p, vp]
+        for name in ("kamx_model_create", "kamx_model_destroy", "kamx_set_params", "kamx_model_info",
+                     "kamx_state_upload", "kamx_state_download", "kamx_contacts_upload", "kamx_set_external",
+                     "kamx_set_warmstart", "kamx_step", "kamx_read_impulses", "kamx_read_stats",
+                     "kamx_read_restart_log", "kamx_read_torques", "kamx_read_contacts", "kamx_reset_count"):
+            getattr(L, name).restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+class KamxError(RuntimeError):
+    pass
+
+
+def _check(status):
+    if status != OK:
+        raise KamxError(f"kamx error {status}: {lib().kamx_last_error().decode()}")
+
+
+def default_params():
+    p = kamx_params()
+    lib().kamx_default_params(C.byref(p))
+    return p
+
+
+def make_params(**kw):
+    """A kamx_params struct: library defaults overridden by keyword values
+    (gravity given as a 3-sequence)."""
+    p = default_params()
+    for k, v in kw.items():
+        if k == "gravity":
+            for e in range(3):
+                p.gravity[e] = float(v[e])
+        elif not hasattr(p, k):
+            raise KeyError(k)
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def contacts_tensor(scene, device):
+    """The scene's explicit contacts as a device byte tensor of kamx_contact
+    records plus host world offsets."""
+    n = scene.n_contacts
+    arr = np.zeros(max(n, 1), CONTACT_DTYPE)
+    if n:
+        arr["body_a"] = scene.contact_body[:, 0]
+        arr["body_b"] = scene.contact_body[:, 1]
+        arr["point"] = scene.contact_point
+        arr["normal"] = scene.contact_normal
+        arr["gap"] = scene.contact_gap
+        arr["mu"] = scene.contact_mu
+        arr["key"] = scene.contact_key
+    dev = torch.from_numpy(arr.view(np.uint8).copy()).to(device)
+    off = scene.contact_offsets().astype(np.int32)
+    return dev, off
+
+
+def decode_contacts(byte_tensor):
+    a = byte_tensor.detach().cpu().numpy().view(CONTACT_DTYPE)
+    return a
+
+
+class Model:
+    """A batch of worlds on one GPU.
+
+    ``scene``: a scenes.Scene; ``params``: keyword overrides of the library
+    defaults; ``max_contacts``: capacity for explicit contacts per world
+    (0 = probe contacts only); ``pd``: optional (kp, kd) for the actuated
+    joints, driven toward their coordinate in the initial pose
+    (``refs`` gives those coordinates; without it ref = 0)."""
+
+    def __init__(self, scene, params=None, max_contacts=0, pd=None, refs=None, device="cuda:0"):
+        self.device = torch.device(device)
+        self.scene = scene
+        self.n_worlds = scene.n_worlds
+        nb, nj, np_ = scene.n_bodies, scene.n_joints, int(scene.probe_body.shape[0])
+        B = (kamx_body_desc * max(nb, 1))()
+        for k in range(nb):
+            B[k].world = int(scene.body_world[k])
+            B[k].mass = float(scene.body_mass[k])
+            for e in range(3):
+                B[k].inertia[e] = float(scene.body_inertia[k, e])
+        J = (kamx_joint_desc * max(nj, 1))()
+        for k in range(nj):
+            J[k].type = int(scene.joint_type[k])
+            J[k].world = int(scene.joint_world[k])
+            J[k].body_a = int(scene.joint_body[k, 0])
+            J[k].body_b = int(scene.joint_body[k, 1])
+            for e in range(7):
+                J[k].frame_a[e] = float(scene.joint_frame[k, e])
+                J[k].frame_b[e] = float(scene.joint_frame[k, 7 + e])
+            J[k].limit_lo = float(scene.joint_limit[k, 0])
+            J[k].limit_hi = float(scene.joint_limit[k, 1])
+            act = int(scene.joint_actuated[k])
+            J[k].actuated = act
+            if pd is not None and act:
+                J[k].kp, J[k].kd = float(pd[0]), float(pd[1])
+                J[k].ref = float(refs[k]) if refs is not None else 0.0
+        Pr = (kamx_probe_desc * max(np_, 1))()
+        for k in range(np_):
+            Pr[k].world = int(scene.probe_world[k])
+            Pr[k].body = int(scene.probe_body[k])
+            for e in range(3):
+                Pr[k].point[e] = float(scene.probe_point[k, e])
+            Pr[k].mu = float(scene.probe_mu[k])
+        rb = (C.c_int32 * self.n_worlds)()
+        if scene.reset_body.size == self.n_worlds:
+            for w in range(self.n_worlds):
+                rb[w] = int(scene.reset_body[w])
+        else:
+            for w in range(self.n_worlds):
+                rb[w] = -1
+        kw = dict(dt=scene.dt, gravity=scene.gravity)
+        if scene.reset_height > -1e29:
+            kw["reset_height"] = scene.reset_height
+        kw.update(params or {})
+        self.params = make_params(**kw)
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().kamx_model_create(B, nb, J, nj, Pr, np_, rb, self.n_worlds, int(max_contacts),
+                                           C.byref(self.params), C.byref(h)))
+        self.handle = h
+        nbo, njo, rows, nbk = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        offs = (C.c_int32 * (self.n_worlds + 1))()
+        _check(lib().kamx_model_info(h, C.byref(nbo), C.byref(njo), C.byref(rows), C.byref(nbk), offs))
+        self.n_bodies, self.n_joints = nbo.value, njo.value
+        self.rows_capacity, self.n_buckets = rows.value, nbk.value
+        self.row_offsets = np.array(offs[:], dtype=np.int64)
+        self._keep = []
+        self.upload_state(scene.q, scene.u, as_reset_state=True)
+
+    # -- lifetime ------------------------------------------------------------
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().kamx_model_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- inputs --------------------------------------------------------------
+    def set_params(self, **kw):
+        for k, v in kw.items():
+            if k == "gravity":
+                for e in range(3):
+                    self.params.gravity[e] = float(v[e])
+            else:
+                setattr(self.params, k, v)
+        _check(lib().kamx_set_params(self.handle, C.byref(self.params)))
+
+    def upload_state(self, q, u, as_reset_state=False, stream=None):
+        qt = torch.as_tensor(np.asarray(q, np.float32) if not torch.is_tensor(q) else q,
+                             dtype=torch.float32, device=self.device).contiguous()
+        ut = torch.as_tensor(np.asarray(u, np.float32) if not torch.is_tensor(u) else u,
+                             dtype=torch.float32, device=self.device).contiguous()
+        _check(lib().kamx_state_upload(self.handle, _ptr(qt), _ptr(ut), int(as_reset_state), _stream(stream)))
+        self._keep.append((qt, ut))
+        torch.cuda.current_stream(self.device).synchronize()
+        self._keep.clear()
+
+    def upload_contacts(self, scene=None, stream=None):
+        """Use the scene's explicit contacts (or probes again when scene is None)."""
+        if scene is None:
+            _check(lib().kamx_contacts_upload(self.handle, None, None, _stream(stream)))
+            self._contacts = None
+            return
+        dev, off = contacts_tensor(scene, self.device)
+        offs = (C.c_int32 * (self.n_worlds + 1))(*[int(x) for x in off])
+        _check(lib().kamx_contacts_upload(self.handle, _ptr(dev), offs, _stream(stream)))
+        self._contacts = dev
+
+    def set_external(self, tau=None, stream=None):
+        if tau is None:
+            self._ext = None
+            _check(lib().kamx_set_external(self.handle, None, _stream(stream)))
+            return
+        t = torch.as_tensor(tau, dtype=torch.float32, device=self.device).contiguous()
+        self._ext = t
+        _check(lib().kamx_set_external(self.handle, _ptr(t), _stream(stream)))
+
+    def set_warmstart(self, lam, stream=None):
+        t = torch.as_tensor(lam, dtype=torch.float32, device=self.device).contiguous()
+        _check(lib().kamx_set_warmstart(self.handle, _ptr(t), _stream(stream)))
+        torch.cuda.current_stream(self.device).synchronize()
+
+    # -- stepping ------------------------------------------------------------
+    def step(self, n=1, stream=None):
+        _check(lib().kamx_step(self.handle, int(n), _stream(stream)))
+
+    # -- outputs -------------------------------------------------------------
+    def state(self, stream=None):
+        q = torch.empty((self.n_bodies, 7), dtype=torch.float32, device=self.device)
+        u = torch.empty((self.n_bodies, 6), dtype=torch.float32, device=self.device)
+        _check(lib().kamx_state_download(self.handle, _ptr(q), _ptr(u), _stream(stream)))
+        return q, u
+
+    def impulses(self, stream=None):
+        lam = torch.empty(max(self.rows_capacity, 1), dtype=torch.float32, device=self.device)
+        _check(lib().kamx_read_impulses(self.handle, _ptr(lam), _stream(stream)))
+        return lam[: self.rows_capacity]
+
+    def stats(self, stream=None):
+        n = self.n_worlds
+        it = torch.empty(n, dtype=torch.int32, device=self.device)
+        res = torch.empty((n, 4), dtype=torch.float32, device=self.device)
+        st = torch.empty(n, dtype=torch.int32, device=self.device)
+        rows = torch.empty(n, dtype=torch.int32, device=self.device)
+        _check(lib().kamx_read_stats(self.handle, _ptr(it), _ptr(res), _ptr(st), _ptr(rows), _stream(stream)))
+        return dict(iters=it, resid=res, status=st, rows=rows)
+
+    def restart_log(self, stream=None):
+        t = torch.empty((self.n_worlds, self.params.max_iters), dtype=torch.uint8, device=self.device)
+        _check(lib().kamx_read_restart_log(self.handle, _ptr(t), _stream(stream)))
+        return t
+
+    def torques(self, stream=None):
+        t = torch.empty(max(self.n_joints, 1), dtype=torch.float32, device=self.device)
+        _check(lib().kamx_read_torques(self.handle, _ptr(t), _stream(stream)))
+        return t[: self.n_joints]
+
+    def contacts(self, stream=None):
+        raw = torch.empty(self.n_worlds * MAX_CONTACTS_PER_WORLD * CONTACT_DTYPE.itemsize, dtype=torch.uint8,
+                          device=self.device)
+        cnt = torch.empty(self.n_worlds, dtype=torch.int32, device=self.device)
+        _check(lib().kamx_read_contacts(self.handle, _ptr(raw), _ptr(cnt), _stream(stream)))
+        return raw, cnt
+
+    def reset_count(self, stream=None):
+        c = C.c_int64()
+        _check(lib().kamx_reset_count(self.handle, C.byref(c), _stream(stream)))
+        return c.value
+
+
+def contacts_to_scene(scene, raw, counts):
+    """A copy of ``scene`` whose explicit contacts are the ones the library
+    used in its last step (for feeding the same rows to a reference)."""
+    recs = decode_contacts(raw).reshape(scene.n_worlds, MAX_CONTACTS_PER_WORLD)
+    counts = counts.detach().cpu().numpy()
+    cw, cb, cp, cn, cg, cm, ck = [], [], [], [], [], [], []
+    for w in range(scene.n_worlds):
+        for k in range(int(counts[w])):
+            r = recs[w, k]
+            cw.append(w)
+            cb.append((r["body_a"], r["body_b"]))
+            cp.append(r["point"])
+            cn.append(r["normal"])
+            cg.append(r["gap"])
+            cm.append(r["mu"])
+            ck.append(r["key"])
+    n = len(cw)
+    return scene.replace(
+        contact_world=np.array(cw, np.int32), contact_body=np.array(cb, np.int32).reshape(n, 2),
+        contact_point=np.array(cp, np.float64).reshape(n, 3), contact_normal=np.array(cn, np.float64).reshape(n, 3),
+        contact_gap=np.array(cg, np.float64), contact_mu=np.array(cm, np.float64), contact_key=np.array(ck, np.int32))

@@ -235,7 +235,11 @@ class Scene:
         s.contact_gap = self.contact_gap[c0:c1].copy()
         s.contact_mu = self.contact_mu[c0:c1].copy()
         s.contact_key = self.contact_key[c0:c1].copy()
-        s.reset_body = self.reset_body[w:w + 1].copy() if self.reset_body.size else np.zeros(0, np.int32)
+        if self.reset_body.size:
+            rbw = int(self.reset_body[w])
+            s.reset_body = np.array([rbw - b0 if rbw >= 0 else -1], np.int32)
+        else:
+            s.reset_body = np.zeros(0, np.int32)
         s.gravity = self.gravity
         s.dt = self.dt
         return s
@@ -278,7 +282,7 @@ def concat(scenes, gravity=None, dt=None, reset_height=None):
         cm.append(s.contact_mu)
         ck.append(s.contact_key)
         if s.reset_body.size:
-            rb.append(s.reset_body + nb)
+            rb.append(np.where(s.reset_body >= 0, s.reset_body + nb, -1))
         else:
             rb.append(np.full(s.n_worlds, -1, np.int32))
         nb += s.n_bodies

@@ -1,0 +1,119 @@
+"""Helpers shared by the GPU parity tests: run the library and the FP64
+oracle on the same single-step state and compare them the way the parity
+contract states (per world, relative to the world's largest value with a
+floor of 1e-6 m g dt)."""
+import numpy as np
+
+import oracle
+from paper_2603_16536_amd import kamx, scenes
+
+
+def oracle_params(p: "kamx.kamx_params", **over):
+    P = oracle.Params(dt=p.dt, gravity=tuple(p.gravity), eta=p.eta, rho_bil=p.rho_bilateral, rho_c=p.rho_contact,
+                      eps=p.eps, max_iters=p.max_iters, fixed_iters=p.fixed_iters, accel=p.accel,
+                      restart_factor=p.restart_factor, precond=p.precond, baumgarte=p.baumgarte)
+    return P.replace(**over)
+
+
+def gpu_step(scene, params, explicit_contacts=True, ext=None, max_contacts=None, warm=None):
+    """One step of every world on the GPU.  Returns numpy outputs and the
+    scene with the contacts the library actually used."""
+    import torch
+
+    mc = max_contacts if max_contacts is not None else (
+        int(np.bincount(scene.contact_world, minlength=scene.n_worlds).max()) if explicit_contacts and scene.n_contacts else 0)
+    model = kamx.Model(scene, params=params, max_contacts=mc)
+    if explicit_contacts:
+        model.upload_contacts(scene)
+    if ext is not None:
+        model.set_external(ext)
+    if warm is not None:
+        model.set_warmstart(warm)
+    model.step(1)
+    torch.cuda.synchronize()
+    q, u = (t.cpu().numpy().astype(np.float64) for t in model.state())
+    st = {k: v.cpu().numpy() for k, v in model.stats().items()}
+    out = dict(q=q, u=u, lam=model.impulses().cpu().numpy().astype(np.float64), row_offsets=model.row_offsets,
+               torques=model.torques().cpu().numpy().astype(np.float64), **st)
+    if model.params.log_restarts:
+        out["restart_log"] = model.restart_log().cpu().numpy()
+    raw, cnt = model.contacts()
+    out["used_scene"] = kamx.contacts_to_scene(scene, raw, cnt)
+    model.close()
+    return out
+
+
+def world_mass(scene):
+    return np.bincount(scene.body_world, weights=scene.body_mass, minlength=scene.n_worlds)
+
+
+def compare_world(scene, params, g, w, replay=True, oracle_over=None):
+    """Replay world w in the oracle with the GPU's iteration count and
+    restart decisions; return the relative errors of u+, J^T lambda per body
+    and lambda, plus the oracle's FP64 NCP residual of the GPU impulses."""
+    sub = g["used_scene"].subset([w])
+    qw = None
+    b0, b1 = scene.body_offsets()[w], scene.body_offsets()[w + 1]
+    iters = int(g["iters"][w])
+    over = dict(oracle_over or {})
+    if replay:
+        over["fixed_iters"] = max(iters, 1)
+    P = oracle_params(params, **over)
+    log = g["restart_log"][w:w + 1, :max(iters, 1)] if replay and "restart_log" in g else None
+    tau = g["torques"][scene.joint_offsets()[w]:scene.joint_offsets()[w + 1]]
+    ref = oracle.step(sub, P, joint_torque=tau, replay_log=log)
+    S = oracle.world_system(sub, P, 0, joint_torque=tau)
+    m = S["J"].shape[0]
+    r0 = int(g["row_offsets"][w])
+    lam_g = g["lam"][r0:r0 + m]
+    assert np.all(g["lam"][r0 + m:int(g["row_offsets"][w + 1])] == 0.0)
+    floor_imp = 1e-6 * world_mass(scene)[w] * 9.81 * params.dt
+    floor_vel = 1e-6 * 9.81 * params.dt
+    u_g = g["u"][b0:b1].reshape(-1)
+    u_o = ref["u"].reshape(-1)
+    imp_g = S["J"].T @ lam_g
+    imp_o = S["J"].T @ ref["lam"]
+    e_u = np.abs(u_g - u_o).max() / max(np.abs(u_o).max(), floor_vel)
+    e_imp = np.abs(imp_g - imp_o).max() / max(np.abs(imp_o).max(), floor_imp)
+    e_lam = np.abs(lam_g - ref["lam"]).max() / max(np.abs(ref["lam"]).max(), floor_imp)
+    # FP64 natural-map residual of the GPU impulses (preconditioned units)
+    D, vf, kind, mu = S["D"], S["vf"], S["kind"], S["mu"]
+    p = np.ones(m)
+    if params.precond:
+        p = 1.0 / np.sqrt(np.maximum(np.diag(D), 1e-300))
+        for i in range(m):
+            if kind[i] == oracle.ROW_NORMAL:
+                p[i:i + 3] = 1.0 / np.sqrt(np.trace(D[i:i + 3, i:i + 3]) / 3.0)
+    lt = lam_g / p
+    v = p * (D @ lam_g + vf)
+    r_ncp = ncp_natural_residual(lt, v, kind, mu)
+    return dict(e_u=e_u, e_imp=e_imp, e_lam=e_lam, r_ncp=r_ncp, ref=ref, m=m, iters=iters)
+
+
+def ncp_natural_residual(lt, v, kind, mu):
+    """|| l - Pi_K(l - (v + Gamma(v))) ||_inf."""
+    w = v.copy()
+    out = 0.0
+    i = 0
+    m = len(lt)
+    while i < m:
+        if kind[i] == oracle.ROW_NORMAL:
+            w[i] += mu[i] * np.hypot(v[i + 1], v[i + 2])
+            o = oracle.project_block(2, mu[i], lt[i:i + 3] - w[i:i + 3])
+            out = max(out, np.abs(lt[i:i + 3] - o).max())
+            i += 3
+        elif kind[i] == oracle.ROW_LIMIT:
+            out = max(out, abs(lt[i] - max(lt[i] - w[i], 0.0)))
+            i += 1
+        else:
+            out = max(out, abs(w[i]))
+            i += 1
+    return out
+
+
+def biped_refs(scene):
+    """Joint coordinates of the initial pose (PD references)."""
+    refs = np.zeros(scene.n_joints)
+    for j in range(scene.n_joints):
+        refs[j] = oracle.joint_coordinate(scene, scene.q, j)[0]
+    return refs
