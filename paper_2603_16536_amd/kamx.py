@@ -50,9 +50,15 @@ class kamx_probe_desc(C.Structure):
     _fields_ = [("world", C.c_int32), ("body", C.c_int32), ("point", C.c_float * 3), ("mu", C.c_float)]
 
 
+BODY_DTYPE = np.dtype([("world", "<i4"), ("mass", "<f4"), ("inertia", "<f4", 3)])
+JOINT_DTYPE = np.dtype([("type", "<i4"), ("world", "<i4"), ("body_a", "<i4"), ("body_b", "<i4"),
+                        ("frame_a", "<f4", 7), ("frame_b", "<f4", 7), ("limit_lo", "<f4"), ("limit_hi", "<f4"),
+                        ("kp", "<f4"), ("kd", "<f4"), ("ref", "<f4"), ("actuated", "<i4")])
+PROBE_DTYPE = np.dtype([("world", "<i4"), ("body", "<i4"), ("point", "<f4", 3), ("mu", "<f4")])
 CONTACT_DTYPE = np.dtype([("body_a", "<i4"), ("body_b", "<i4"), ("point", "<f4", 3), ("normal", "<f4", 3),
                           ("gap", "<f4"), ("mu", "<f4"), ("key", "<i4")])
-assert CONTACT_DTYPE.itemsize == 44
+assert CONTACT_DTYPE.itemsize == 44 and BODY_DTYPE.itemsize == 20
+assert JOINT_DTYPE.itemsize == 96 and PROBE_DTYPE.itemsize == 24
 
 _lib = None
 
@@ -173,35 +179,37 @@ class Model:
         self.scene = scene
         self.n_worlds = scene.n_worlds
         nb, nj, np_ = scene.n_bodies, scene.n_joints, int(scene.probe_body.shape[0])
-        B = (kamx_body_desc * max(nb, 1))()
-        for k in range(nb):
-            B[k].world = int(scene.body_world[k])
-            B[k].mass = float(scene.body_mass[k])
-            for e in range(3):
-                B[k].inertia[e] = float(scene.body_inertia[k, e])
-        J = (kamx_joint_desc * max(nj, 1))()
-        for k in range(nj):
-            J[k].type = int(scene.joint_type[k])
-            J[k].world = int(scene.joint_world[k])
-            J[k].body_a = int(scene.joint_body[k, 0])
-            J[k].body_b = int(scene.joint_body[k, 1])
-            for e in range(7):
-                J[k].frame_a[e] = float(scene.joint_frame[k, e])
-                J[k].frame_b[e] = float(scene.joint_frame[k, 7 + e])
-            J[k].limit_lo = float(scene.joint_limit[k, 0])
-            J[k].limit_hi = float(scene.joint_limit[k, 1])
-            act = int(scene.joint_actuated[k])
-            J[k].actuated = act
-            if pd is not None and act:
-                J[k].kp, J[k].kd = float(pd[0]), float(pd[1])
-                J[k].ref = float(refs[k]) if refs is not None else 0.0
-        Pr = (kamx_probe_desc * max(np_, 1))()
-        for k in range(np_):
-            Pr[k].world = int(scene.probe_world[k])
-            Pr[k].body = int(scene.probe_body[k])
-            for e in range(3):
-                Pr[k].point[e] = float(scene.probe_point[k, e])
-            Pr[k].mu = float(scene.probe_mu[k])
+        bodies = np.zeros(max(nb, 1), BODY_DTYPE)
+        bodies["world"][:nb] = scene.body_world
+        bodies["mass"][:nb] = scene.body_mass
+        bodies["inertia"][:nb] = scene.body_inertia
+        joints = np.zeros(max(nj, 1), JOINT_DTYPE)
+        if nj:
+            joints["type"][:nj] = scene.joint_type
+            joints["world"][:nj] = scene.joint_world
+            joints["body_a"][:nj] = scene.joint_body[:, 0]
+            joints["body_b"][:nj] = scene.joint_body[:, 1]
+            joints["frame_a"][:nj] = scene.joint_frame[:, :7]
+            joints["frame_b"][:nj] = scene.joint_frame[:, 7:]
+            joints["limit_lo"][:nj] = scene.joint_limit[:, 0]
+            joints["limit_hi"][:nj] = scene.joint_limit[:, 1]
+            act = scene.joint_actuated.astype(np.int32)
+            joints["actuated"][:nj] = act
+            if pd is not None:
+                on = act != 0
+                joints["kp"][:nj][on] = float(pd[0])
+                joints["kd"][:nj][on] = float(pd[1])
+                if refs is not None:
+                    joints["ref"][:nj][on] = np.asarray(refs, np.float32)[on]
+        probes = np.zeros(max(np_, 1), PROBE_DTYPE)
+        if np_:
+            probes["world"][:np_] = scene.probe_world
+            probes["body"][:np_] = scene.probe_body
+            probes["point"][:np_] = scene.probe_point
+            probes["mu"][:np_] = scene.probe_mu
+        B = C.cast(bodies.ctypes.data, C.POINTER(kamx_body_desc))
+        J = C.cast(joints.ctypes.data, C.POINTER(kamx_joint_desc))
+        Pr = C.cast(probes.ctypes.data, C.POINTER(kamx_probe_desc))
         rb = (C.c_int32 * self.n_worlds)()
         if scene.reset_body.size == self.n_worlds:
             for w in range(self.n_worlds):
@@ -309,6 +317,12 @@ class Model:
         rows = torch.empty(n, dtype=torch.int32, device=self.device)
         _check(lib().kamx_read_stats(self.handle, _ptr(it), _ptr(res), _ptr(st), _ptr(rows), _stream(stream)))
         return dict(iters=it, resid=res, status=st, rows=rows)
+
+    def stats_into(self, iters=None, resid=None, status=None, rows=None, stream=None):
+        """Stream-ordered copy of the last step's per-world stats into the
+        given device tensors (no host synchronization)."""
+        _check(lib().kamx_read_stats(self.handle, _ptr(iters), _ptr(resid), _ptr(status), _ptr(rows),
+                                     _stream(stream)))
 
     def restart_log(self, stream=None):
         t = torch.empty((self.n_worlds, self.params.max_iters), dtype=torch.uint8, device=self.device)

@@ -546,7 +546,9 @@ def biped_world(rng, dt=2e-3, mu=None, link_masses=None):
     foot) + 2 legs x 5 crank-rod parallelogram transmissions (2 bodies and 3
     revolute joints each).  40 revolute joints (200 bilateral rows), four
     sole probe points per foot (8 contacts, 24 rows).  Stands on z = 0 with
-    straight legs at rest; exactly on the constraint manifold."""
+    straight legs at rest; exactly on the constraint manifold.  The ten chain
+    joints (hip yaw, roll, pitch, knee, ankle of each leg) are actuated; the
+    3-30 g transmission links are passive."""
     if mu is None:
         mu = rng.uniform(0.5, 1.0)
     if link_masses is None:
@@ -583,7 +585,7 @@ def biped_world(rng, dt=2e-3, mu=None, link_masses=None):
         # parallelogram transmissions: (parent, child, joint point, delta, crank)
         loops = [
             (hr, thigh, Hp, (-0.04, 0.0, 0.0), (0.0, 0.0, -0.06), 0),
-            (thigh, shin, Kn, (0.035, 0.0, 0.0), (0.0, 0.0, -0.07), 1),
+            (thigh, shin, Kn, (0.035, 0.0, 0.0), (0.0, 0.0, -0.07), 0),
             (thigh, shin, Kn, (-0.035, 0.0, 0.02), (0.01, 0.0, -0.09), 0),
             (shin, foot, An, (0.03, 0.0, 0.04), (0.05, 0.0, 0.0), 0),
             (shin, foot, An, (-0.03, 0.0, 0.05), (-0.04, 0.0, -0.01), 0),

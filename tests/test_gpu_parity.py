@@ -87,15 +87,15 @@ def test_cfg2_biped_converged_replayed(n_worlds, sample):
     assert conv.mean() > 0.5
 
 
-def test_cfg2_biped_tight_tolerance_replayed():
+def test_cfg2_biped_deep_iterations_replayed():
+    """600 iterations (well past the 1e-6 exit of every world): u+ of every
+    body, light transmission links included, within 1e-4."""
     scene, tau = biped_state(16, seed=7)
-    p = cfg2_params(eps=1e-7, max_iters=4000)
+    p = cfg2_params(fixed_iters=600, max_iters=600)
     g = gpu_step(scene, p, ext=tau)
     params = kamx.make_params(**p)
-    ok = np.where(g["status"] == 0)[0]
-    assert len(ok) >= 12
-    errs = [compare_world(scene, params, g, int(w)) for w in ok]
-    e = report(f"biped 16 worlds at eps 1e-7, iters {g['iters'].tolist()}", errs)
+    errs = [compare_world(scene, params, g, w) for w in range(16)]
+    e = report("biped 16 worlds, 600 iterations", errs)
     assert e[:, 0].max() < TOL and e[:, 1].max() < TOL
 
 
