@@ -95,7 +95,7 @@ def run_gpu(n_worlds, steps, warmup, warmstart):
     return out
 
 
-def cpu_baseline(min_seconds=10.0, n_worlds=256, max_steps=8):
+def cpu_baseline(min_seconds=12.0, n_worlds=512, max_steps=60):
     """The FP64 oracle on the host cores: the same biped workload (PD +
     noise torques, probe contacts refreshed every step, cold start to 1e-6),
     a bounded sample of worlds and steps."""
@@ -159,7 +159,7 @@ def contacts_from_probes(scene, q, margin):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=60)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--worlds", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")

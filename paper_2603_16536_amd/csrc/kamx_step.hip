@@ -418,26 +418,51 @@ __device__ inline void reduce4(float &m0, float &m1, float &m2, float &s3, float
 // every x-update and for the dual residual.
 // ---------------------------------------------------------------------------
 
+// Sum over the four lanes of an aligned quad (fixed butterfly order).
+__device__ inline float quad_sum(float v) {
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    return v;
+}
+__device__ inline double quad_sum(double v) {
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    return v;
+}
+
+__device__ inline float dot4(const float *a, const float *b) {
+    float4 x = *reinterpret_cast<const float4 *>(a);
+    float4 y = *reinterpret_cast<const float4 *>(b);
+    return x.x * y.x + x.y * y.y + x.z * y.z + x.w * y.w;
+}
+
 template <int NT>
 __device__ inline void delassus_apply(const Lds &L, int m, int nb, const float *vp, const float *x, float *out) {
     const int tid = threadIdx.x;
-    for (int b = tid; b < nb; b += NT) {
+    // bodies: four threads per body split its incident rows
+    {
+        const int b = tid >> 2, q = tid & 3;
         double g[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        for (int k = L.inc_off[b]; k < L.inc_off[b + 1]; ++k) {
-            int e = L.inc_list[k];
-            int r = e >> 1, side = e & 1;
-            double xr = (double)vp[r] * (double)x[r];
-            for (int c = 0; c < 6; ++c) g[c] += (double)L.rf(RJ + 6 * side + c, r) * xr;
+        if (b < nb) {
+            for (int k = L.inc_off[b] + q; k < L.inc_off[b + 1]; k += 4) {
+                int e = L.inc_list[k];
+                int r = e >> 1, side = e & 1;
+                double xr = (double)vp[r] * (double)x[r];
+                for (int c = 0; c < 6; ++c) g[c] += (double)L.rf(RJ + 6 * side + c, r) * xr;
+            }
         }
-        double im = L.bf(BIM, b);
-        double R[9], t[3], s[3];
-        for (int c = 0; c < 9; ++c) R[c] = L.bf(BR + c, b);
-        mtv3(R, g + 3, t);
-        for (int c = 0; c < 3; ++c) t[c] *= (double)L.bf(BII + c, b);
-        mv3(R, t, s);
-        for (int c = 0; c < 3; ++c) {
-            L.wb[c * kMaxBodies + b] = g[c] * im;
-            L.wb[(3 + c) * kMaxBodies + b] = s[c];
+        for (int c = 0; c < 6; ++c) g[c] = quad_sum(g[c]);
+        if (b < nb && q == 0) {
+            double im = L.bf(BIM, b);
+            double R[9], t[3], s[3];
+            for (int c = 0; c < 9; ++c) R[c] = L.bf(BR + c, b);
+            mtv3(R, g + 3, t);
+            for (int c = 0; c < 3; ++c) t[c] *= (double)L.bf(BII + c, b);
+            mv3(R, t, s);
+            for (int c = 0; c < 3; ++c) {
+                L.wb[c * kMaxBodies + b] = g[c] * im;
+                L.wb[(3 + c) * kMaxBodies + b] = s[c];
+            }
         }
     }
     __syncthreads();
@@ -878,25 +903,23 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
         __syncthreads();
     }
 
-    // ---- Cholesky of D~ + diag(eta + rho), in place (Alg. 1 step 1)
+    // ---- Cholesky of D~ + diag(eta + rho), in place (Alg. 1 step 1).
+    //      Left-looking by columns; four threads per row split each dot product.
+    const int si = tid >> 2, sq = tid & 3;
     if (tid == 0) s_int[2] = 0;
     for (int j = 0; j < m; ++j) {
-        if (i >= j && i < m) {
-            const float *Ri = A + tri_row_offset(i);
+        float acc = 0.f;
+        const bool act = si >= j && si < m;
+        if (act) {
+            const float *Ri = A + tri_row_offset(si);
             const float *Rj = A + tri_row_offset(j);
-            float acc = Ri[j];
-            int k = 0;
-            for (; k + 4 <= j; k += 4) {
-                float4 x4 = *reinterpret_cast<const float4 *>(Ri + k);
-                float4 y4 = *reinterpret_cast<const float4 *>(Rj + k);
-                acc -= x4.x * y4.x;
-                acc -= x4.y * y4.y;
-                acc -= x4.z * y4.z;
-                acc -= x4.w * y4.w;
-            }
-            for (; k < j; ++k) acc -= Ri[k] * Rj[k];
-            vcol[i] = acc;
+            const int nch = j >> 2;
+            for (int c = sq; c < nch; c += 4) acc += dot4(Ri + 4 * c, Rj + 4 * c);
+            if (sq == 0)
+                for (int k = 4 * nch; k < j; ++k) acc += Ri[k] * Rj[k];
         }
+        acc = quad_sum(acc);
+        if (act && sq == 0) vcol[si] = A[tri_row_offset(si) + j] - acc;
         __syncthreads();
         float d = vcol[j];
         if (!(d > 0.f) || !isfinite(d)) {
@@ -904,36 +927,34 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
             break;
         }
         float ljj = sqrtf(d);
-        if (i == j) A[tri_row_offset(i) + j] = ljj;
-        else if (i > j && i < m) A[tri_row_offset(i) + j] = vcol[i] / ljj;
+        if (sq == 0) {
+            if (si == j) A[tri_row_offset(si) + j] = ljj;
+            else if (si > j && si < m) A[tri_row_offset(si) + j] = vcol[si] / ljj;
+        }
         __syncthreads();
     }
     __syncthreads();
     const int factor_fail = s_int[2];
 
-    // ---- explicit inverse of the factor, in place: X = L^-1
+    // ---- explicit inverse of the factor, in place: X = L^-1 (columns from
+    //      the last one; four threads per row split each dot product)
     if (!factor_fail) {
         for (int j = m - 1; j >= 0; --j) {
             float ljj = A[tri_row_offset(j) + j];
-            if (i < MC) vcol[i] = (i > j && i < m) ? A[tri_row_offset(i) + j] : 0.f;
+            if (tid < MC) vcol[tid] = (tid > j && tid < m) ? A[tri_row_offset(tid) + j] : 0.f;
             __syncthreads();
             float inv = 1.f / ljj;
-            if (i > j && i < m) {
-                const float *Ri = A + tri_row_offset(i);
-                int k0 = (j + 1) & ~3;
-                int k1 = (i + 4) & ~3;
-                float acc = 0.f;
-                for (int k = k0; k < k1; k += 4) {
-                    float4 x4 = *reinterpret_cast<const float4 *>(Ri + k);
-                    float4 c4 = *reinterpret_cast<const float4 *>(vcol + k);
-                    acc += x4.x * c4.x;
-                    acc += x4.y * c4.y;
-                    acc += x4.z * c4.z;
-                    acc += x4.w * c4.w;
-                }
-                A[tri_row_offset(i) + j] = -acc * inv;
-            } else if (i == j) {
-                A[tri_row_offset(i) + j] = inv;
+            float acc = 0.f;
+            const bool act = si > j && si < m;
+            if (act) {
+                const float *Ri = A + tri_row_offset(si);
+                const int c0 = (j + 1) >> 2, c1 = (si + 4) >> 2;
+                for (int c = c0 + sq; c < c1; c += 4) acc += dot4(Ri + 4 * c, vcol + 4 * c);
+            }
+            acc = quad_sum(acc);
+            if (sq == 0) {
+                if (act) A[tri_row_offset(si) + j] = -acc * inv;
+                else if (si == j) A[tri_row_offset(si) + j] = inv;
             }
             __syncthreads();
         }
@@ -975,28 +996,29 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
                 }
             }
             __syncthreads();
-            // t = X r (rows of X)
-            if (i < m) {
-                const float *Ri = A + tri_row_offset(i);
+            // t = X r (rows of X), four threads per row
+            {
                 float acc = 0.f;
-                int k1 = (i + 4) & ~3;
-                for (int k = 0; k < k1; k += 4) {
-                    float4 x4 = *reinterpret_cast<const float4 *>(Ri + k);
-                    float4 r4 = *reinterpret_cast<const float4 *>(vrhs + k);
-                    acc += x4.x * r4.x;
-                    acc += x4.y * r4.y;
-                    acc += x4.z * r4.z;
-                    acc += x4.w * r4.w;
+                if (si < m) {
+                    const float *Ri = A + tri_row_offset(si);
+                    const int nch = (si + 4) >> 2;
+                    for (int c = sq; c < nch; c += 4) acc += dot4(Ri + 4 * c, vrhs + 4 * c);
                 }
-                vt[i] = acc;
+                acc = quad_sum(acc);
+                if (si < m && sq == 0) vt[si] = acc;
             }
             __syncthreads();
-            // x_new = x + X^T t (columns of X)
-            if (i < m) {
+            // x_new = x + X^T t (columns of X); the 16 columns of a wave walk
+            // the same rows so their reads are consecutive
+            {
                 float acc = 0.f;
-                for (int r = (i & ~63); r < m; ++r)
-                    if (r >= i) acc += A[tri_row_offset(r) + i] * vt[r];
-                vxn[i] = vx[i] + acc;
+                if (si < m) {
+                    const int r0 = si & ~15;
+                    for (int r = r0 + sq; r < m; r += 4)
+                        if (r >= si) acc += A[tri_row_offset(r) + si] * vt[r];
+                }
+                acc = quad_sum(acc);
+                if (si < m && sq == 0) vxn[si] = vx[si] + acc;
             }
             __syncthreads();
             // v~ - v~_f = D~ x_new (matrix-free, FP64 accumulation)
@@ -1193,7 +1215,7 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
 
 template <int MC>
 static hipError_t launch_mc(const StepArgs &args, int n, hipStream_t stream) {
-    constexpr int NT = MC <= 64 ? 64 : ((MC + 63) / 64) * 64;
+    constexpr int NT = 4 * ((MC + 63) / 64) * 64 > 1024 ? 1024 : 4 * ((MC + 63) / 64) * 64;
     size_t bytes = sizeof(float) * (size_t)smem_floats(MC);
     static bool configured = false;
     if (!configured) {
