@@ -164,6 +164,9 @@ def main():
     ap.add_argument("--worlds", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-previous", action="store_true", help="skip the previous-step warm-start run")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="after the run, copy a 256 MiB buffer once (a plain copy kernel of known traffic "
+                         "for scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); worlds are independent, "
@@ -220,6 +223,13 @@ def main():
             "iters_mean": round(float(pit.mean()), 1), "iters_p50": float(np.percentile(pit, 50)),
             "iters_p99": float(np.percentile(pit, 99)),
             "converged_fraction": round(float((prev["status"] == 0).mean()), 5)}
+    if args.calibrate_copy:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        result["copy_calibration_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4}
     if not args.no_cpu:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline()

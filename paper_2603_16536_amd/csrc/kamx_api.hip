@@ -3,6 +3,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -71,6 +72,7 @@ struct kamx_model_s {
     float *d_tau = nullptr;
     kamx_contact *d_contacts_out = nullptr;
     int32_t *d_ncontacts = nullptr, *d_reset_count = nullptr;
+    uint64_t *d_phase_clk = nullptr;  // debug phase stamps (enabled by KAMX_PHASE_CLOCK)
 };
 
 template <typename T>
@@ -340,6 +342,7 @@ kamx_status kamx_model_create(const kamx_body_desc *bodies, int32_t nb, const ka
     M_TRY(dalloc(m, &m->d_ncontacts, n_worlds));
     M_TRY(dalloc(m, &m->d_reset_count, n_worlds));
     M_TRY(ensure_rlog(m));
+    if (getenv("KAMX_PHASE_CLOCK")) M_TRY(dalloc(m, &m->d_phase_clk, 8 * (size_t)n_worlds));
 
     auto up = [&](void *dst, const void *src, size_t bytes) -> kamx_status {
         hipError_t e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
@@ -499,6 +502,7 @@ kamx_status kamx_step(kamx_model m, int32_t nsteps, kamx_stream stream) {
     a.contacts_out = m->d_contacts_out;
     a.ncontacts_out = m->d_ncontacts;
     a.reset_count = m->d_reset_count;
+    a.phase_clk = m->d_phase_clk;
     a.p = to_solver(m->params);
     for (int k = 0; k < nsteps; ++k) {
         a.step_index = m->step_index++;
@@ -560,6 +564,14 @@ kamx_status kamx_read_contacts(kamx_model m, kamx_contact *contacts_dev, int32_t
                                hipMemcpyDeviceToDevice, s));
     if (counts_dev)
         HIP_TRY(hipMemcpyAsync(counts_dev, m->d_ncontacts, sizeof(int32_t) * m->n_worlds, hipMemcpyDeviceToDevice, s));
+    return KAMX_OK;
+}
+
+kamx_status kamx_read_phase_clock(kamx_model m, uint64_t *clk_dev, kamx_stream stream) {
+    if (!m || !clk_dev) return fail(KAMX_EINVAL, "NULL argument");
+    if (!m->d_phase_clk) return fail(KAMX_ESTATE, "phase clock not enabled (set KAMX_PHASE_CLOCK before model create)");
+    HIP_TRY(hipMemcpyAsync(clk_dev, m->d_phase_clk, sizeof(uint64_t) * 8 * m->n_worlds, hipMemcpyDeviceToDevice,
+                           reinterpret_cast<hipStream_t>(stream)));
     return KAMX_OK;
 }
 

@@ -86,6 +86,7 @@ struct StepArgs {
     kamx_contact *contacts_out;  // [n_worlds*kMaxContacts]
     int32_t *ncontacts_out;      // [n_worlds]
     int32_t *reset_count;        // [n_worlds]
+    uint64_t *phase_clk;         // [n_worlds*8] phase time stamps, or null
     SolverParams p;
     uint32_t step_index;
 };

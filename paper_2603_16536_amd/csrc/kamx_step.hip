@@ -418,16 +418,17 @@ __device__ inline void reduce4(float &m0, float &m1, float &m2, float &s3, float
 // every x-update and for the dual residual.
 // ---------------------------------------------------------------------------
 
-// Sum over the four lanes of an aligned quad (fixed butterfly order).
-__device__ inline float quad_sum(float v) {
-    v += __shfl_xor(v, 1, 64);
-    v += __shfl_xor(v, 2, 64);
+// Sum over the TPR lanes that share a row (fixed butterfly order).
+template <int TPR, typename T>
+__device__ inline T group_sum(T v) {
+    if (TPR >= 2) v += __shfl_xor(v, 1, 64);
+    if (TPR >= 4) v += __shfl_xor(v, 2, 64);
     return v;
 }
-__device__ inline double quad_sum(double v) {
-    v += __shfl_xor(v, 1, 64);
-    v += __shfl_xor(v, 2, 64);
-    return v;
+
+// Broadcast a lane's value to the whole wave (lane index uniform).
+__device__ inline float rdlane(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
 __device__ inline float dot4(const float *a, const float *b) {
@@ -436,22 +437,22 @@ __device__ inline float dot4(const float *a, const float *b) {
     return x.x * y.x + x.y * y.y + x.z * y.z + x.w * y.w;
 }
 
-template <int NT>
+template <int NT, int TPR>
 __device__ inline void delassus_apply(const Lds &L, int m, int nb, const float *vp, const float *x, float *out) {
     const int tid = threadIdx.x;
     // bodies: four threads per body split its incident rows
     {
-        const int b = tid >> 2, q = tid & 3;
+        const int b = tid / TPR, q = tid % TPR;
         double g[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         if (b < nb) {
-            for (int k = L.inc_off[b] + q; k < L.inc_off[b + 1]; k += 4) {
+            for (int k = L.inc_off[b] + q; k < L.inc_off[b + 1]; k += TPR) {
                 int e = L.inc_list[k];
                 int r = e >> 1, side = e & 1;
                 double xr = (double)vp[r] * (double)x[r];
                 for (int c = 0; c < 6; ++c) g[c] += (double)L.rf(RJ + 6 * side + c, r) * xr;
             }
         }
-        for (int c = 0; c < 6; ++c) g[c] = quad_sum(g[c]);
+        for (int c = 0; c < 6; ++c) g[c] = group_sum<TPR>(g[c]);
         if (b < nb && q == 0) {
             double im = L.bf(BIM, b);
             double R[9], t[3], s[3];
@@ -481,7 +482,7 @@ __device__ inline void delassus_apply(const Lds &L, int m, int nb, const float *
 // the fused step kernel
 // ---------------------------------------------------------------------------
 
-template <int MC, int NT>
+template <int MC, int NT, int TPR>
 __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
     extern __shared__ float4 smem4[];
     float *sm = reinterpret_cast<float *>(smem4);
@@ -507,6 +508,7 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
 
     const int nb = W.nb, nj = W.nj;
 
+    if (a.phase_clk && tid == 0) a.phase_clk[8 * w + 0] = wall_clock64();
     // ---- reset: a world whose reset body fell below the threshold restarts
     if (tid == 0) {
         int rs = 0;
@@ -746,6 +748,7 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
     }
     __syncthreads();
 
+    if (a.phase_clk && tid == 0) a.phase_clk[8 * w + 1] = wall_clock64();
     // ---- D = J M^-1 J^T, packed lower triangle (rows padded to 4 floats)
     const int i = tid;
     if (i < m) {
@@ -753,20 +756,35 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
         for (int k = 0; k < 12; ++k) Ji[k] = L.rf(RJ + k, i);
         int ia = L.ri(RIA, i), ib = L.ri(RIB, i);
         float *Ri = A + tri_row_offset(i);
-        for (int j = 0; j <= i; ++j) {
-            int ja = L.ri(RIA, j), jb = L.ri(RIB, j);
-            float acc = 0.f;
-            if (ia == ja)
-                for (int k = 0; k < 6; ++k) acc += Ji[k] * Wv[k * MC + j];
-            if (ia == jb && jb >= 0)
-                for (int k = 0; k < 6; ++k) acc += Ji[k] * Wv[(6 + k) * MC + j];
-            if (ib >= 0 && ib == ja)
-                for (int k = 0; k < 6; ++k) acc += Ji[6 + k] * Wv[k * MC + j];
-            if (ib >= 0 && ib == jb)
-                for (int k = 0; k < 6; ++k) acc += Ji[6 + k] * Wv[(6 + k) * MC + j];
-            Ri[j] = acc;
+        for (int j0 = 0; j0 <= i; j0 += 8) {
+            float out[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int j = j0 + u;
+                float acc = 0.f;
+                if (j <= i) {
+                    int ja = L.ri(RIA, j), jb = L.ri(RIB, j);
+                    if (ia == ja)
+                        for (int k = 0; k < 6; ++k) acc += Ji[k] * Wv[k * MC + j];
+                    if (ia == jb && jb >= 0)
+                        for (int k = 0; k < 6; ++k) acc += Ji[k] * Wv[(6 + k) * MC + j];
+                    if (ib >= 0 && ib == ja)
+                        for (int k = 0; k < 6; ++k) acc += Ji[6 + k] * Wv[k * MC + j];
+                    if (ib >= 0 && ib == jb)
+                        for (int k = 0; k < 6; ++k) acc += Ji[6 + k] * Wv[(6 + k) * MC + j];
+                }
+                out[u] = acc;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (j0 + u <= i) Ri[j0 + u] = out[u];
         }
         for (int j = i + 1; j < ((i + 4) & ~3); ++j) Ri[j] = 0.f;
+    } else if (i < ((m + 15) & ~15)) {
+        // rows up to the next multiple of 16 are identity rows, so the
+        // factorization can work on whole 16x16 tiles
+        float *Ri = A + tri_row_offset(i);
+        for (int j = 0; j < ((i + 4) & ~3); ++j) Ri[j] = j == i ? 1.f : 0.f;
     }
     __syncthreads();
 
@@ -816,6 +834,7 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
     }
     __syncthreads();
 
+    if (a.phase_clk && tid == 0) a.phase_clk[8 * w + 2] = wall_clock64();
     // ---- body -> row incidence lists (CSR, rows in increasing order)
     for (int b = tid; b < nb; b += NT) {
         int cnt = 0;
@@ -881,7 +900,7 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
             }
         }
         __syncthreads();
-        delassus_apply<NT>(L, m, nb, vp, vyp, vdx);  // D~ y0 (x0 = y0)
+        delassus_apply<NT, TPR>(L, m, nb, vp, vyp, vdx);  // D~ y0 (x0 = y0)
         if (owner) {
             float v0 = vdx[i] + vvt[i];
             if (kind_i == kRowNormal) {
@@ -903,39 +922,138 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
         __syncthreads();
     }
 
-    // ---- Cholesky of D~ + diag(eta + rho), in place (Alg. 1 step 1).
-    //      Left-looking by columns; four threads per row split each dot product.
-    const int si = tid >> 2, sq = tid & 3;
-    if (tid == 0) s_int[2] = 0;
-    for (int j = 0; j < m; ++j) {
-        float acc = 0.f;
-        const bool act = si >= j && si < m;
-        if (act) {
-            const float *Ri = A + tri_row_offset(si);
-            const float *Rj = A + tri_row_offset(j);
-            const int nch = j >> 2;
-            for (int c = sq; c < nch; c += 4) acc += dot4(Ri + 4 * c, Rj + 4 * c);
-            if (sq == 0)
-                for (int k = 4 * nch; k < j; ++k) acc += Ri[k] * Rj[k];
-        }
-        acc = quad_sum(acc);
-        if (act && sq == 0) vcol[si] = A[tri_row_offset(si) + j] - acc;
+    if (a.phase_clk && tid == 0) a.phase_clk[8 * w + 3] = wall_clock64();
+    // ---- Cholesky of D~ + diag(eta + rho), in place (Alg. 1 step 1):
+    //      right-looking over 16x16 tiles.  Wave 0 factors the diagonal tile
+    //      in registers (lane r holds row r) and also forms its inverse; the
+    //      panel below is multiplied by that inverse; the trailing tiles get
+    //      a rank-16 update computed in 4x4 register micro-tiles.
+    const int si = tid / TPR, sq = tid % TPR;
+    {
+        const int T = (m + 15) >> 4;
+        float *Xs = L.red;  // 16x16 inverse of the current diagonal factor tile (red + wb are free here)
+        if (tid == 0) s_int[2] = 0;
         __syncthreads();
-        float d = vcol[j];
-        if (!(d > 0.f) || !isfinite(d)) {
-            if (tid == 0) s_int[2] = 1;
-            break;
+        for (int K = 0; K < T; ++K) {
+            const int k0 = 16 * K;
+            if (tid < 64) {
+                const int r = tid;
+                float a[16];
+                const float *Rr = A + tri_row_offset(k0 + (r & 15)) + k0;
+#pragma unroll
+                for (int c = 0; c < 16; ++c) a[c] = (r < 16 && c <= r) ? Rr[c] : 0.f;
+                bool ok = true;
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                    float d = rdlane(a[k], k);
+                    ok = ok && (d > 0.f) && isfinite(d);
+                    float lkk = sqrtf(d), il = 1.f / lkk;
+                    if (r == k) a[k] = lkk;
+                    else if (r > k) a[k] *= il;
+#pragma unroll
+                    for (int j = k + 1; j < 16; ++j) {
+                        float ljk = rdlane(a[k], j);
+                        if (r >= j) a[j] -= a[k] * ljk;
+                    }
+                }
+                // column r of the tile's inverse (forward substitution)
+                float xc[16];
+#pragma unroll
+                for (int rr = 0; rr < 16; ++rr) {
+                    float acc = (r == rr) ? 1.f : 0.f;
+#pragma unroll
+                    for (int kk = 0; kk < rr; ++kk) acc -= rdlane(a[kk], rr) * xc[kk];
+                    xc[rr] = acc / rdlane(a[rr], rr);
+                }
+                if (r < 16) {
+                    float *Rw = A + tri_row_offset(k0 + r) + k0;
+#pragma unroll
+                    for (int c = 0; c < 16; ++c)
+                        if (c <= r) Rw[c] = a[c];
+#pragma unroll
+                    for (int rr = 0; rr < 16; ++rr) Xs[16 * rr + r] = xc[rr];  // zero above the diagonal
+                }
+                if (!ok && r == 0) s_int[2] = 1;
+            }
+            __syncthreads();
+            if (s_int[2]) break;
+            // panel: L_IK = A_IK Xkk^T for the tiles I below the diagonal
+            const int nI = T - K - 1;
+            constexpr int PR = ((MC / 16 - 1) * 256 + NT - 1) / NT;
+            float pres[PR];
+            int pe[PR];
+#pragma unroll
+            for (int rd = 0; rd < PR; ++rd) {
+                int e = tid + rd * NT;
+                pe[rd] = e;
+                pres[rd] = 0.f;
+                if (e < nI * 256) {
+                    int I = K + 1 + (e >> 8), rr = (e >> 4) & 15, cc = e & 15;
+                    const float *Ar = A + tri_row_offset(16 * I + rr) + k0;
+                    const float *Xr = Xs + 16 * cc;
+                    float acc = 0.f;
+#pragma unroll
+                    for (int ch = 0; ch < 4; ++ch) acc += dot4(Ar + 4 * ch, Xr + 4 * ch);
+                    pres[rd] = acc;
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int rd = 0; rd < PR; ++rd) {
+                int e = pe[rd];
+                if (e < nI * 256) {
+                    int I = K + 1 + (e >> 8), rr = (e >> 4) & 15, cc = e & 15;
+                    A[tri_row_offset(16 * I + rr) + k0 + cc] = pres[rd];
+                }
+            }
+            __syncthreads();
+            // trailing update A_IJ -= L_IK L_JK^T, K < J <= I
+            const int npair = nI * (nI + 1) / 2;
+            for (int t = tid; t < 16 * npair; t += NT) {
+                int p = t >> 4, mt = t & 15, mr = mt >> 2, mc = mt & 3;
+                int Ii = (int)((sqrtf(8.f * (float)p + 1.f) - 1.f) * 0.5f);
+                while ((Ii + 1) * (Ii + 2) / 2 <= p) ++Ii;
+                while (Ii * (Ii + 1) / 2 > p) --Ii;
+                int Jj = p - Ii * (Ii + 1) / 2;
+                int I = K + 1 + Ii, J = K + 1 + Jj;
+                if (I == J && mc > mr) continue;
+                const int r0 = 16 * I + 4 * mr, c0 = 16 * J + 4 * mc;
+                float acc[4][4];
+#pragma unroll
+                for (int x = 0; x < 4; ++x)
+#pragma unroll
+                    for (int y = 0; y < 4; ++y) acc[x][y] = 0.f;
+#pragma unroll
+                for (int ch = 0; ch < 4; ++ch) {
+                    float4 lr[4], lc[4];
+#pragma unroll
+                    for (int x = 0; x < 4; ++x)
+                        lr[x] = *reinterpret_cast<const float4 *>(A + tri_row_offset(r0 + x) + k0 + 4 * ch);
+#pragma unroll
+                    for (int y = 0; y < 4; ++y)
+                        lc[y] = *reinterpret_cast<const float4 *>(A + tri_row_offset(c0 + y) + k0 + 4 * ch);
+#pragma unroll
+                    for (int x = 0; x < 4; ++x)
+#pragma unroll
+                        for (int y = 0; y < 4; ++y)
+                            acc[x][y] += lr[x].x * lc[y].x + lr[x].y * lc[y].y + lr[x].z * lc[y].z + lr[x].w * lc[y].w;
+                }
+                const bool diag = (I == J) && (mc == mr);
+#pragma unroll
+                for (int x = 0; x < 4; ++x) {
+                    float *dst = A + tri_row_offset(r0 + x) + c0;
+#pragma unroll
+                    for (int y = 0; y < 4; ++y)
+                        if (!diag || y <= x) dst[y] -= acc[x][y];
+                }
+            }
+            __syncthreads();
         }
-        float ljj = sqrtf(d);
-        if (sq == 0) {
-            if (si == j) A[tri_row_offset(si) + j] = ljj;
-            else if (si > j && si < m) A[tri_row_offset(si) + j] = vcol[si] / ljj;
-        }
-        __syncthreads();
     }
     __syncthreads();
     const int factor_fail = s_int[2];
 
+    if (a.phase_clk && tid == 0) a.phase_clk[8 * w + 4] = wall_clock64();
     // ---- explicit inverse of the factor, in place: X = L^-1 (columns from
     //      the last one; four threads per row split each dot product)
     if (!factor_fail) {
@@ -949,9 +1067,18 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
             if (act) {
                 const float *Ri = A + tri_row_offset(si);
                 const int c0 = (j + 1) >> 2, c1 = (si + 4) >> 2;
-                for (int c = c0 + sq; c < c1; c += 4) acc += dot4(Ri + 4 * c, vcol + 4 * c);
+                float a1 = 0.f, a2 = 0.f, a3 = 0.f;
+                int c = c0 + sq;
+                for (; c + 3 * TPR < c1; c += 4 * TPR) {
+                    acc += dot4(Ri + 4 * c, vcol + 4 * c);
+                    a1 += dot4(Ri + 4 * (c + TPR), vcol + 4 * (c + TPR));
+                    a2 += dot4(Ri + 4 * (c + 2 * TPR), vcol + 4 * (c + 2 * TPR));
+                    a3 += dot4(Ri + 4 * (c + 3 * TPR), vcol + 4 * (c + 3 * TPR));
+                }
+                for (; c < c1; c += TPR) acc += dot4(Ri + 4 * c, vcol + 4 * c);
+                acc = (acc + a1) + (a2 + a3);
             }
-            acc = quad_sum(acc);
+            acc = group_sum<TPR>(acc);
             if (sq == 0) {
                 if (act) A[tri_row_offset(si) + j] = -acc * inv;
                 else if (si == j) A[tri_row_offset(si) + j] = inv;
@@ -960,6 +1087,7 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
         }
     }
 
+    if (a.phase_clk && tid == 0) a.phase_clk[8 * w + 5] = wall_clock64();
     // ---- PADMM (Alg. 1 steps 3-10).  The x-update of step 5 is computed as
     //      x + X^T X (rhs - (D~ + eta + rho) x): one refinement step from the
     //      previous iterate with the FP32 factor inverse and an FP64
@@ -996,33 +1124,52 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
                 }
             }
             __syncthreads();
-            // t = X r (rows of X), four threads per row
+            // t = X r (rows of X), TPR threads per row, 4 independent chains
             {
-                float acc = 0.f;
+                float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
                 if (si < m) {
                     const float *Ri = A + tri_row_offset(si);
                     const int nch = (si + 4) >> 2;
-                    for (int c = sq; c < nch; c += 4) acc += dot4(Ri + 4 * c, vrhs + 4 * c);
+                    int c = sq;
+                    for (; c + 3 * TPR < nch; c += 4 * TPR) {
+                        a0 += dot4(Ri + 4 * c, vrhs + 4 * c);
+                        a1 += dot4(Ri + 4 * (c + TPR), vrhs + 4 * (c + TPR));
+                        a2 += dot4(Ri + 4 * (c + 2 * TPR), vrhs + 4 * (c + 2 * TPR));
+                        a3 += dot4(Ri + 4 * (c + 3 * TPR), vrhs + 4 * (c + 3 * TPR));
+                    }
+                    for (; c < nch; c += TPR) a0 += dot4(Ri + 4 * c, vrhs + 4 * c);
                 }
-                acc = quad_sum(acc);
+                float acc = group_sum<TPR>((a0 + a1) + (a2 + a3));
                 if (si < m && sq == 0) vt[si] = acc;
             }
             __syncthreads();
-            // x_new = x + X^T t (columns of X); the 16 columns of a wave walk
-            // the same rows so their reads are consecutive
+            // x_new = x + X^T t (columns of X); the columns of a wave walk the
+            // same rows so their reads are consecutive; loads are issued for
+            // every row of the walk (in bounds) and masked, four chains
             {
-                float acc = 0.f;
+                float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
                 if (si < m) {
-                    const int r0 = si & ~15;
-                    for (int r = r0 + sq; r < m; r += 4)
-                        if (r >= si) acc += A[tri_row_offset(r) + si] * vt[r];
+                    const int r0 = si & ~(64 / TPR - 1);
+                    int r = r0 + sq;
+                    for (; r + 3 * TPR < m; r += 4 * TPR) {
+                        float x0 = A[tri_row_offset(r) + si], x1 = A[tri_row_offset(r + TPR) + si];
+                        float x2 = A[tri_row_offset(r + 2 * TPR) + si], x3 = A[tri_row_offset(r + 3 * TPR) + si];
+                        a0 += (r >= si ? x0 : 0.f) * vt[r];
+                        a1 += (r + TPR >= si ? x1 : 0.f) * vt[r + TPR];
+                        a2 += (r + 2 * TPR >= si ? x2 : 0.f) * vt[r + 2 * TPR];
+                        a3 += (r + 3 * TPR >= si ? x3 : 0.f) * vt[r + 3 * TPR];
+                    }
+                    for (; r < m; r += TPR) {
+                        float x0 = A[tri_row_offset(r) + si];
+                        a0 += (r >= si ? x0 : 0.f) * vt[r];
+                    }
                 }
-                acc = quad_sum(acc);
+                float acc = group_sum<TPR>((a0 + a1) + (a2 + a3));
                 if (si < m && sq == 0) vxn[si] = vx[si] + acc;
             }
             __syncthreads();
             // v~ - v~_f = D~ x_new (matrix-free, FP64 accumulation)
-            delassus_apply<NT>(L, m, nb, vp, vxn, vdx);
+            delassus_apply<NT, TPR>(L, m, nb, vp, vxn, vdx);
             // steps 6-7 and the residuals of step 9 (block owners)
             float lrp = 0.f, lrd = 0.f, lrc = 0.f, lcc = 0.f;
             float yb[3], zb[3];
@@ -1111,7 +1258,7 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
         if (P.fixed_iters <= 0 && !converged && status == 0) status = KAMX_WORLD_MAXITER;
         __syncthreads();
         // natural-map residual of the NCP at the returned y (Eq. 3)
-        delassus_apply<NT>(L, m, nb, vp, vyp, vaux);
+        delassus_apply<NT, TPR>(L, m, nb, vp, vyp, vaux);
         float lncp = 0.f;
         if (owner) {
             float v[3], o[3], y[3], nm[3];
@@ -1132,6 +1279,7 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
     }
     __syncthreads();
 
+    if (a.phase_clk && tid == 0) a.phase_clk[8 * w + 6] = wall_clock64();
     // ---- outputs: lambda = P y (Alg. 1 step 11), stats, caches
     if (i < W.row_cap) {
         float lam = 0.f;
@@ -1207,6 +1355,8 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
         float nn = 1.f / sqrtf(qn[0] * qn[0] + qn[1] * qn[1] + qn[2] * qn[2] + qn[3] * qn[3]);
         for (int k = 0; k < 4; ++k) a.q[7 * gb + 3 + k] = qn[k] * nn;
     }
+    __syncthreads();
+    if (a.phase_clk && tid == 0) a.phase_clk[8 * w + 7] = wall_clock64();
 }
 
 // ---------------------------------------------------------------------------
@@ -1215,16 +1365,19 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
 
 template <int MC>
 static hipError_t launch_mc(const StepArgs &args, int n, hipStream_t stream) {
-    constexpr int NT = 4 * ((MC + 63) / 64) * 64 > 1024 ? 1024 : 4 * ((MC + 63) / 64) * 64;
+    // threads per row: 4 for small worlds; 2 for the large buckets, where the
+    // register budget of 1024-thread groups (128 VGPRs) would spill
+    constexpr int TPR = MC >= 160 ? 2 : 4;
+    constexpr int NT = TPR * ((MC + 63) / 64) * 64;
     size_t bytes = sizeof(float) * (size_t)smem_floats(MC);
     static bool configured = false;
     if (!configured) {
-        hipError_t e = hipFuncSetAttribute((const void *)step_kernel<MC, NT>,
+        hipError_t e = hipFuncSetAttribute((const void *)step_kernel<MC, NT, TPR>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         if (e != hipSuccess) return e;
         configured = true;
     }
-    hipLaunchKernelGGL((step_kernel<MC, NT>), dim3(n), dim3(NT), bytes, stream, args);
+    hipLaunchKernelGGL((step_kernel<MC, NT, TPR>), dim3(n), dim3(NT), bytes, stream, args);
     return hipGetLastError();
 }
 

@@ -93,10 +93,12 @@ def lib():
         L.kamx_read_torques.argtypes = [vp, vp, vp]
         L.kamx_read_contacts.argtypes = [vp, vp, vp, vp]
         L.kamx_reset_count.argtypes = [vp, i64p, vp]
+        L.kamx_read_phase_clock.argtypes = [vp, vp, vp]
         for name in ("kamx_model_create", "kamx_model_destroy", "kamx_set_params", "kamx_model_info",
                      "kamx_state_upload", "kamx_state_download", "kamx_contacts_upload", "kamx_set_external",
                      "kamx_set_warmstart", "kamx_step", "kamx_read_impulses", "kamx_read_stats",
-                     "kamx_read_restart_log", "kamx_read_torques", "kamx_read_contacts", "kamx_reset_count"):
+                     "kamx_read_restart_log", "kamx_read_torques", "kamx_read_contacts", "kamx_reset_count",
+                     "kamx_read_phase_clock"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -340,6 +342,11 @@ class Model:
         cnt = torch.empty(self.n_worlds, dtype=torch.int32, device=self.device)
         _check(lib().kamx_read_contacts(self.handle, _ptr(raw), _ptr(cnt), _stream(stream)))
         return raw, cnt
+
+    def phase_clock(self, stream=None):
+        t = torch.empty((self.n_worlds, 8), dtype=torch.int64, device=self.device)
+        _check(lib().kamx_read_phase_clock(self.handle, _ptr(t), _stream(stream)))
+        return t
 
     def reset_count(self, stream=None):
         c = C.c_int64()
