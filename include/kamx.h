@@ -244,9 +244,12 @@ kamx_status kamx_read_contacts(kamx_model m, kamx_contact *contacts_dev, int32_t
  * synchronizes the stream). */
 kamx_status kamx_reset_count(kamx_model m, int64_t *count, kamx_stream stream);
 
-/* Diagnostic: wall-clock stamps (device ticks) at eight phase boundaries of
- * the last step of every world into clk_dev [n_worlds*8] (setup, rows,
- * Delassus, warm start, factor, inverse, iterations, end).  Only available
+/* Diagnostic: wall-clock stamps (device ticks) of the last step of every
+ * world into clk_dev [n_worlds*16]: entries 0-7 at the phase boundaries
+ * (start, Delassus, warm start, factor, inverse, iterations, outputs, end),
+ * entries 8-13 the ticks spent in the iteration sub-phases (right-hand side,
+ * forward mat-vec, transposed mat-vec, body gather, projections and
+ * residuals, updates).  Only available
  * when the environment variable KAMX_PHASE_CLOCK was set at model creation;
  * otherwise ESTATE. */
 kamx_status kamx_read_phase_clock(kamx_model m, uint64_t *clk_dev, kamx_stream stream);

@@ -342,7 +342,7 @@ kamx_status kamx_model_create(const kamx_body_desc *bodies, int32_t nb, const ka
     M_TRY(dalloc(m, &m->d_ncontacts, n_worlds));
     M_TRY(dalloc(m, &m->d_reset_count, n_worlds));
     M_TRY(ensure_rlog(m));
-    if (getenv("KAMX_PHASE_CLOCK")) M_TRY(dalloc(m, &m->d_phase_clk, 8 * (size_t)n_worlds));
+    if (getenv("KAMX_PHASE_CLOCK")) M_TRY(dalloc(m, &m->d_phase_clk, 16 * (size_t)n_worlds));
 
     auto up = [&](void *dst, const void *src, size_t bytes) -> kamx_status {
         hipError_t e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
@@ -570,7 +570,7 @@ kamx_status kamx_read_contacts(kamx_model m, kamx_contact *contacts_dev, int32_t
 kamx_status kamx_read_phase_clock(kamx_model m, uint64_t *clk_dev, kamx_stream stream) {
     if (!m || !clk_dev) return fail(KAMX_EINVAL, "NULL argument");
     if (!m->d_phase_clk) return fail(KAMX_ESTATE, "phase clock not enabled (set KAMX_PHASE_CLOCK before model create)");
-    HIP_TRY(hipMemcpyAsync(clk_dev, m->d_phase_clk, sizeof(uint64_t) * 8 * m->n_worlds, hipMemcpyDeviceToDevice,
+    HIP_TRY(hipMemcpyAsync(clk_dev, m->d_phase_clk, sizeof(uint64_t) * 16 * m->n_worlds, hipMemcpyDeviceToDevice,
                            reinterpret_cast<hipStream_t>(stream)));
     return KAMX_OK;
 }

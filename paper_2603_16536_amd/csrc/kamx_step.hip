@@ -437,44 +437,72 @@ __device__ inline float dot4(const float *a, const float *b) {
     return x.x * y.x + x.y * y.y + x.z * y.z + x.w * y.w;
 }
 
+// Body gather of the matrix-free product: g_b = sum over the rows incident
+// to body b of J_{r,b}^T p_r x_r, one thread per (body, component), FP64,
+// rows in increasing order.  Ends with a barrier.
 template <int NT, int TPR>
-__device__ inline void delassus_apply(const Lds &L, int m, int nb, const float *vp, const float *x, float *out) {
+__device__ inline void delassus_gather(const Lds &L, int nb, const float *vp, const float *x) {
     const int tid = threadIdx.x;
-    // bodies: four threads per body split its incident rows
-    {
-        const int b = tid / TPR, q = tid % TPR;
-        double g[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        if (b < nb) {
-            for (int k = L.inc_off[b] + q; k < L.inc_off[b + 1]; k += TPR) {
-                int e = L.inc_list[k];
-                int r = e >> 1, side = e & 1;
-                double xr = (double)vp[r] * (double)x[r];
-                for (int c = 0; c < 6; ++c) g[c] += (double)L.rf(RJ + 6 * side + c, r) * xr;
-            }
+    for (int t = tid; t < 6 * nb; t += NT) {
+        const int b = t / 6, c = t - 6 * (t / 6);
+        double g0 = 0.0, g1 = 0.0;
+        int k = L.inc_off[b];
+        const int k1 = L.inc_off[b + 1];
+        for (; k + 1 < k1; k += 2) {
+            int e0 = L.inc_list[k], e1 = L.inc_list[k + 1];
+            int r0 = e0 >> 1, r1 = e1 >> 1;
+            g0 += (double)L.rf(RJ + 6 * (e0 & 1) + c, r0) * ((double)vp[r0] * (double)x[r0]);
+            g1 += (double)L.rf(RJ + 6 * (e1 & 1) + c, r1) * ((double)vp[r1] * (double)x[r1]);
         }
-        for (int c = 0; c < 6; ++c) g[c] = group_sum<TPR>(g[c]);
-        if (b < nb && q == 0) {
-            double im = L.bf(BIM, b);
-            double R[9], t[3], s[3];
-            for (int c = 0; c < 9; ++c) R[c] = L.bf(BR + c, b);
-            mtv3(R, g + 3, t);
-            for (int c = 0; c < 3; ++c) t[c] *= (double)L.bf(BII + c, b);
-            mv3(R, t, s);
-            for (int c = 0; c < 3; ++c) {
-                L.wb[c * kMaxBodies + b] = g[c] * im;
-                L.wb[(3 + c) * kMaxBodies + b] = s[c];
-            }
+        if (k < k1) {
+            int e0 = L.inc_list[k];
+            int r0 = e0 >> 1;
+            g0 += (double)L.rf(RJ + 6 * (e0 & 1) + c, r0) * ((double)vp[r0] * (double)x[r0]);
         }
+        L.wb[c * kMaxBodies + b] = g0 + g1;
     }
     __syncthreads();
-    for (int r = tid; r < m; r += NT) {
-        int ia = L.ri(RIA, r), ib = L.ri(RIB, r);
-        double acc = 0.0;
-        for (int c = 0; c < 6; ++c) acc += (double)L.rf(RJ + c, r) * L.wb[c * kMaxBodies + ia];
-        if (ib >= 0)
-            for (int c = 0; c < 6; ++c) acc += (double)L.rf(RJ + 6 + c, r) * L.wb[c * kMaxBodies + ib];
-        out[r] = (float)(acc * (double)vp[r]);
+}
+
+// w = M_b^-1 g_b in FP64 (body frame: R diag(I^-1) R^T for the angular part)
+__device__ inline void body_minv64(const Lds &L, int b, double w[6]) {
+    double g[6];
+    for (int c = 0; c < 6; ++c) g[c] = L.wb[c * kMaxBodies + b];
+    double im = L.bf(BIM, b);
+    double R[9], t[3], s[3];
+    for (int c = 0; c < 9; ++c) R[c] = L.bf(BR + c, b);
+    mtv3(R, g + 3, t);
+    for (int c = 0; c < 3; ++c) t[c] *= (double)L.bf(BII + c, b);
+    mv3(R, t, s);
+    for (int c = 0; c < 3; ++c) {
+        w[c] = g[c] * im;
+        w[3 + c] = s[c];
     }
+}
+
+// Row r of the product after a gather, given w_a, w_b = M^-1 g of its bodies.
+__device__ inline float delassus_row_w(const Lds &L, const float *vp, int r, const double wa[6], const double wbv[6],
+                                       bool has_b) {
+    double a0 = 0.0, a1 = 0.0;
+    for (int c = 0; c < 6; ++c) a0 += (double)L.rf(RJ + c, r) * wa[c];
+    if (has_b)
+        for (int c = 0; c < 6; ++c) a1 += (double)L.rf(RJ + 6 + c, r) * wbv[c];
+    return (float)((a0 + a1) * (double)vp[r]);
+}
+
+__device__ inline float delassus_row(const Lds &L, const float *vp, int r) {
+    int ia = L.ri(RIA, r), ib = L.ri(RIB, r);
+    double wa[6], wbv[6];
+    body_minv64(L, ia, wa);
+    if (ib >= 0) body_minv64(L, ib, wbv);
+    return delassus_row_w(L, vp, r, wa, wbv, ib >= 0);
+}
+
+// Full product out = D~ x (gather, then every row).  Ends with a barrier.
+template <int NT, int TPR>
+__device__ inline void delassus_apply(const Lds &L, int m, int nb, const float *vp, const float *x, float *out) {
+    delassus_gather<NT, TPR>(L, nb, vp, x);
+    for (int r = threadIdx.x; r < m; r += NT) out[r] = delassus_row(L, vp, r);
     __syncthreads();
 }
 
@@ -508,7 +536,7 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
 
     const int nb = W.nb, nj = W.nj;
 
-    if (a.phase_clk && tid == 0) a.phase_clk[8 * w + 0] = wall_clock64();
+    if (a.phase_clk && tid == 0) a.phase_clk[16 * w + 0] = wall_clock64();
     // ---- reset: a world whose reset body fell below the threshold restarts
     if (tid == 0) {
         int rs = 0;
@@ -733,6 +761,43 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
     }
     __syncthreads();
 
+    // ---- body -> row incidence lists (CSR, rows in increasing order), one
+    //      wave per body at a time, compacted with ballots
+    {
+        constexpr int NWAVE = NT / 64;
+        const int lane = tid & 63, wave = tid >> 6;
+        for (int b = wave; b < nb; b += NWAVE) {
+            int cnt = 0;
+            for (int r0 = 0; r0 < m; r0 += 64) {
+                int r = r0 + lane;
+                bool f = r < m && (L.ri(RIA, r) == b || L.ri(RIB, r) == b);
+                cnt += __popcll(__ballot(f));
+            }
+            if (lane == 0) L.inc_off[b + 1] = cnt;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            L.inc_off[0] = 0;
+            for (int b = 0; b < nb; ++b) L.inc_off[b + 1] += L.inc_off[b];
+        }
+        __syncthreads();
+        for (int b = wave; b < nb; b += NWAVE) {
+            int base = L.inc_off[b];
+            for (int r0 = 0; r0 < m; r0 += 64) {
+                int r = r0 + lane;
+                int side = -1;
+                if (r < m) {
+                    if (L.ri(RIA, r) == b) side = 0;
+                    else if (L.ri(RIB, r) == b) side = 1;
+                }
+                unsigned long long msk = __ballot(side >= 0);
+                if (side >= 0) L.inc_list[base + __popcll(msk & ((1ull << lane) - 1ull))] = (r << 1) | side;
+                base += __popcll(msk);
+            }
+        }
+        __syncthreads();
+    }
+
     // ---- W = M^-1 J^T for both sides of every row (in the vector region)
     float *Wv = L.v;  // [12][MC]
     for (int r = tid; r < m; r += NT) {
@@ -748,83 +813,96 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
     }
     __syncthreads();
 
-    if (a.phase_clk && tid == 0) a.phase_clk[8 * w + 1] = wall_clock64();
-    // ---- D = J M^-1 J^T, packed lower triangle (rows padded to 4 floats)
+    if (a.phase_clk && tid == 0) a.phase_clk[16 * w + 1] = wall_clock64();
+    // ---- Jacobi scales (Sec. 4.1) from the diagonal D_ii = J_i . W_i: per
+    //      row for bilateral and limit rows, one scalar per contact block
     const int i = tid;
+    float *vp = L.vec(VP), *vrho = L.vec(VRHO), *vvt = L.vec(VVT);
+    float *tdiag = L.vec(VCOL), *tp = L.vec(VAUX);  // free fields above W
+    const int kind_row = i < m ? L.ri(RKIND, i) : -1;
     if (i < m) {
-        float Ji[12];
-        for (int k = 0; k < 12; ++k) Ji[k] = L.rf(RJ + k, i);
-        int ia = L.ri(RIA, i), ib = L.ri(RIB, i);
-        float *Ri = A + tri_row_offset(i);
-        for (int j0 = 0; j0 <= i; j0 += 8) {
-            float out[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int j = j0 + u;
-                float acc = 0.f;
-                if (j <= i) {
-                    int ja = L.ri(RIA, j), jb = L.ri(RIB, j);
-                    if (ia == ja)
-                        for (int k = 0; k < 6; ++k) acc += Ji[k] * Wv[k * MC + j];
-                    if (ia == jb && jb >= 0)
-                        for (int k = 0; k < 6; ++k) acc += Ji[k] * Wv[(6 + k) * MC + j];
-                    if (ib >= 0 && ib == ja)
-                        for (int k = 0; k < 6; ++k) acc += Ji[6 + k] * Wv[k * MC + j];
-                    if (ib >= 0 && ib == jb)
-                        for (int k = 0; k < 6; ++k) acc += Ji[6 + k] * Wv[(6 + k) * MC + j];
-                }
-                out[u] = acc;
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-                if (j0 + u <= i) Ri[j0 + u] = out[u];
-        }
-        for (int j = i + 1; j < ((i + 4) & ~3); ++j) Ri[j] = 0.f;
-    } else if (i < ((m + 15) & ~15)) {
-        // rows up to the next multiple of 16 are identity rows, so the
-        // factorization can work on whole 16x16 tiles
-        float *Ri = A + tri_row_offset(i);
-        for (int j = 0; j < ((i + 4) & ~3); ++j) Ri[j] = j == i ? 1.f : 0.f;
+        float dsum = 0.f;
+        for (int k = 0; k < 12; ++k) dsum += L.rf(RJ + k, i) * Wv[k * MC + i];
+        tdiag[i] = dsum;
     }
     __syncthreads();
-
-    // ---- preconditioner (Sec. 4.1): per row, one scalar per contact block
-    float *vp = L.vec(VP), *vrho = L.vec(VRHO), *vvt = L.vec(VVT);
-    // the vector region held W until now: clear it (pads must read as 0)
-    float pi_reg = 1.f;
-    {
-        float p_own[3] = {1.f, 1.f, 1.f};
-        int kind = i < m ? L.ri(RKIND, i) : -1;
-        if (i < m && P.precond) {
-            if (kind == kRowNormal) {
-                float t = (A[tri_row_offset(i) + i] + A[tri_row_offset(i + 1) + i + 1] + A[tri_row_offset(i + 2) + i + 2]) *
-                          (1.f / 3.f);
-                float s = t > 0.f ? 1.f / sqrtf(t) : 1.f;
-                p_own[0] = p_own[1] = p_own[2] = s;
-            } else if (kind != kRowTangent) {
-                float t = A[tri_row_offset(i) + i];
-                p_own[0] = t > 0.f ? 1.f / sqrtf(t) : 1.f;
-            }
-        }
-        __syncthreads();  // every thread has read W / D diagonals
-        for (int k = tid; k < vec_floats(MC); k += NT) L.v[k] = 0.f;
-        __syncthreads();
-        if (i < m) {
-            if (kind == kRowNormal) {
-                vp[i] = vp[i + 1] = vp[i + 2] = p_own[0];
-            } else if (kind != kRowTangent) {
-                vp[i] = p_own[0];
-            }
-            vrho[i] = kind == kRowBilateral ? P.rho_bil : P.rho_c;
-        }
-        __syncthreads();
-        if (i < m) pi_reg = vp[i];
-    }
-    // scale D, add the shift, and form v~_f = P (J u_f + v*)
     if (i < m) {
-        float *Ri = A + tri_row_offset(i);
-        for (int j = 0; j <= i; ++j) Ri[j] *= pi_reg * vp[j];
-        Ri[i] += P.eta + vrho[i];
+        if (kind_row == kRowNormal) {
+            float t = (tdiag[i] + tdiag[i + 1] + tdiag[i + 2]) * (1.f / 3.f);
+            float sc = (P.precond && t > 0.f) ? 1.f / sqrtf(t) : 1.f;
+            tp[i] = tp[i + 1] = tp[i + 2] = sc;
+        } else if (kind_row != kRowTangent) {
+            float t = tdiag[i];
+            tp[i] = (P.precond && t > 0.f) ? 1.f / sqrtf(t) : 1.f;
+        }
+    }
+    __syncthreads();
+    const float pi_reg = i < m ? tp[i] : 1.f;
+
+    // ---- D~ = P J M^-1 J^T P + diag(eta + rho), packed lower triangle (rows
+    //      padded to 4 floats).  Zero-fill, then every nonzero pair (i >= j)
+    //      is formed once, by the first body the two rows share: the pairs of
+    //      each body's incidence list are spread evenly over the threads.
+    {
+        const int Mp = (m + 15) & ~15;
+        const int n4 = tri_row_offset(Mp) >> 2;
+        for (int k = tid; k < n4; k += NT) reinterpret_cast<float4 *>(A)[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+        int *toff = reinterpret_cast<int *>(L.red);  // [nb + 1] pair-task offsets (red/wb free here)
+        if (tid == 0) {
+            toff[0] = 0;
+            for (int b = 0; b < nb; ++b) {
+                int kb = L.inc_off[b + 1] - L.inc_off[b];
+                toff[b + 1] = toff[b] + kb * (kb + 1) / 2;
+            }
+        }
+        __syncthreads();
+        if (i >= m && i < Mp) A[tri_row_offset(i) + i] = 1.f;  // identity rows up to a multiple of 16
+        const int ntask = toff[nb];
+        for (int t = tid; t < ntask; t += NT) {
+            int lo = 0, hi = nb - 1;  // body b with toff[b] <= t < toff[b+1]
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (toff[mid] <= t) lo = mid;
+                else hi = mid - 1;
+            }
+            const int b = lo;
+            const int loc = t - toff[b];
+            int u = (int)((sqrtf(8.f * (float)loc + 1.f) - 1.f) * 0.5f);
+            while ((u + 1) * (u + 2) / 2 <= loc) ++u;
+            while (u * (u + 1) / 2 > loc) --u;
+            const int v = loc - u * (u + 1) / 2;
+            const int ri_ = L.inc_list[L.inc_off[b] + u] >> 1;
+            const int rj_ = L.inc_list[L.inc_off[b] + v] >> 1;
+            const int ia = L.ri(RIA, ri_), ib = L.ri(RIB, ri_), ja = L.ri(RIA, rj_), jb = L.ri(RIB, rj_);
+            int first = 1 << 30;
+            if (ia == ja || ia == jb) first = ia;
+            if (ib >= 0 && (ib == ja || ib == jb) && ib < first) first = ib;
+            if (first != b) continue;
+            float acc = 0.f;
+            if (ia == ja)
+                for (int k = 0; k < 6; ++k) acc += L.rf(RJ + k, ri_) * Wv[k * MC + rj_];
+            if (ia == jb)
+                for (int k = 0; k < 6; ++k) acc += L.rf(RJ + k, ri_) * Wv[(6 + k) * MC + rj_];
+            if (ib >= 0 && ib == ja)
+                for (int k = 0; k < 6; ++k) acc += L.rf(RJ + 6 + k, ri_) * Wv[k * MC + rj_];
+            if (ib >= 0 && ib == jb)
+                for (int k = 0; k < 6; ++k) acc += L.rf(RJ + 6 + k, ri_) * Wv[(6 + k) * MC + rj_];
+            acc *= tp[ri_] * tp[rj_];
+            if (ri_ == rj_) {
+                const int kd = L.ri(RKIND, ri_);
+                acc += P.eta + (kd == kRowBilateral ? P.rho_bil : P.rho_c);
+            }
+            A[tri_row_offset(ri_) + rj_] = acc;
+        }
+        __syncthreads();
+    }
+    // the vector region held W and the scales until now: clear it (pads must
+    // read as 0), then store P, rho and v~_f = P (J u_f + v*)
+    for (int k = tid; k < vec_floats(MC); k += NT) L.v[k] = 0.f;
+    __syncthreads();
+    if (i < m) {
+        vp[i] = pi_reg;
+        vrho[i] = kind_row == kRowBilateral ? P.rho_bil : P.rho_c;
         float v = L.rf(RBIAS, i);
         int ia = L.ri(RIA, i), ib = L.ri(RIB, i);
         for (int k = 0; k < 6; ++k) v += L.rf(RJ + k, i) * L.bf(BUF + k, ia);
@@ -834,28 +912,7 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
     }
     __syncthreads();
 
-    if (a.phase_clk && tid == 0) a.phase_clk[8 * w + 2] = wall_clock64();
-    // ---- body -> row incidence lists (CSR, rows in increasing order)
-    for (int b = tid; b < nb; b += NT) {
-        int cnt = 0;
-        for (int r = 0; r < m; ++r) cnt += (L.ri(RIA, r) == b) + (L.ri(RIB, r) == b);
-        L.inc_off[b + 1] = cnt;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        L.inc_off[0] = 0;
-        for (int b = 0; b < nb; ++b) L.inc_off[b + 1] += L.inc_off[b];
-    }
-    __syncthreads();
-    for (int b = tid; b < nb; b += NT) {
-        int k = L.inc_off[b];
-        for (int r = 0; r < m; ++r) {
-            if (L.ri(RIA, r) == b) L.inc_list[k++] = r << 1;
-            if (L.ri(RIB, r) == b) L.inc_list[k++] = (r << 1) | 1;
-        }
-    }
-    __syncthreads();
-
+    if (a.phase_clk && tid == 0) a.phase_clk[16 * w + 2] = wall_clock64();
     // ---- warm start (Alg. 1 step 2; Sec. 4.1): y = x = Pi_K(lambda_ws / p),
     //      z = v~(y) + Gamma(v~(y)) on unilateral rows, 0 on bilateral rows
     float *vx = L.vec(VX), *vyh = L.vec(VYH), *vzh = L.vec(VZH), *vyp = L.vec(VYP), *vzp = L.vec(VZP);
@@ -922,7 +979,7 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
         __syncthreads();
     }
 
-    if (a.phase_clk && tid == 0) a.phase_clk[8 * w + 3] = wall_clock64();
+    if (a.phase_clk && tid == 0) a.phase_clk[16 * w + 3] = wall_clock64();
     // ---- Cholesky of D~ + diag(eta + rho), in place (Alg. 1 step 1):
     //      right-looking over 16x16 tiles.  Wave 0 factors the diagonal tile
     //      in registers (lane r holds row r) and also forms its inverse; the
@@ -1053,7 +1110,7 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
     __syncthreads();
     const int factor_fail = s_int[2];
 
-    if (a.phase_clk && tid == 0) a.phase_clk[8 * w + 4] = wall_clock64();
+    if (a.phase_clk && tid == 0) a.phase_clk[16 * w + 4] = wall_clock64();
     // ---- explicit inverse of the factor, in place: X = L^-1 (columns from
     //      the last one; four threads per row split each dot product)
     if (!factor_fail) {
@@ -1087,7 +1144,7 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
         }
     }
 
-    if (a.phase_clk && tid == 0) a.phase_clk[8 * w + 5] = wall_clock64();
+    if (a.phase_clk && tid == 0) a.phase_clk[16 * w + 5] = wall_clock64();
     // ---- PADMM (Alg. 1 steps 3-10).  The x-update of step 5 is computed as
     //      x + X^T X (rhs - (D~ + eta + rho) x): one refinement step from the
     //      previous iterate with the FP32 factor inverse and an FP64
@@ -1111,7 +1168,16 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
         bool converged = false;
         float s_own = 0.f;
         __syncthreads();
+        uint64_t sub[6] = {0, 0, 0, 0, 0, 0}, tmark = 0;
+        const bool timing = a.phase_clk && tid == 0;
+#define KAMX_MARK(k)                                  \
+    if (timing) {                                     \
+        uint64_t now_ = wall_clock64();               \
+        if ((k) > 0) sub[(k) - 1] += now_ - tmark;    \
+        tmark = now_;                                 \
+    }
         for (it = 1; it <= N; ++it) {
+            KAMX_MARK(0);
             // steps 4-5: rhs = -v~_f - Gamma(z^) + eta x + rho y^ + z^, and its
             // residual against the current x
             if (owner) {
@@ -1124,63 +1190,118 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
                 }
             }
             __syncthreads();
-            // t = X r (rows of X), TPR threads per row, 4 independent chains
+            KAMX_MARK(1);
+            // t = X r: rows i and m-1-i form a pair handled by four threads, so
+            // every group walks m+1 entries (balanced); two chains per row
             {
-                float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-                if (si < m) {
-                    const float *Ri = A + tri_row_offset(si);
-                    const int nch = (si + 4) >> 2;
-                    int c = sq;
-                    for (; c + 3 * TPR < nch; c += 4 * TPR) {
-                        a0 += dot4(Ri + 4 * c, vrhs + 4 * c);
-                        a1 += dot4(Ri + 4 * (c + TPR), vrhs + 4 * (c + TPR));
-                        a2 += dot4(Ri + 4 * (c + 2 * TPR), vrhs + 4 * (c + 2 * TPR));
-                        a3 += dot4(Ri + 4 * (c + 3 * TPR), vrhs + 4 * (c + 3 * TPR));
+                float a1 = 0.f, b1 = 0.f, a2 = 0.f, b2 = 0.f;
+                const int p = tid >> 2, q = tid & 3;
+                const int i1 = p, i2 = m - 1 - p;
+                if (i1 < i2 || (i1 == i2)) {
+                    if (i1 < m) {
+                        const float *R1 = A + tri_row_offset(i1);
+                        const int n1 = (i1 + 4) >> 2;
+                        int c = q;
+                        for (; c + 4 < n1; c += 8) {
+                            a1 += dot4(R1 + 4 * c, vrhs + 4 * c);
+                            b1 += dot4(R1 + 4 * (c + 4), vrhs + 4 * (c + 4));
+                        }
+                        for (; c < n1; c += 4) a1 += dot4(R1 + 4 * c, vrhs + 4 * c);
                     }
-                    for (; c < nch; c += TPR) a0 += dot4(Ri + 4 * c, vrhs + 4 * c);
-                }
-                float acc = group_sum<TPR>((a0 + a1) + (a2 + a3));
-                if (si < m && sq == 0) vt[si] = acc;
-            }
-            __syncthreads();
-            // x_new = x + X^T t (columns of X); the columns of a wave walk the
-            // same rows so their reads are consecutive; loads are issued for
-            // every row of the walk (in bounds) and masked, four chains
-            {
-                float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-                if (si < m) {
-                    const int r0 = si & ~(64 / TPR - 1);
-                    int r = r0 + sq;
-                    for (; r + 3 * TPR < m; r += 4 * TPR) {
-                        float x0 = A[tri_row_offset(r) + si], x1 = A[tri_row_offset(r + TPR) + si];
-                        float x2 = A[tri_row_offset(r + 2 * TPR) + si], x3 = A[tri_row_offset(r + 3 * TPR) + si];
-                        a0 += (r >= si ? x0 : 0.f) * vt[r];
-                        a1 += (r + TPR >= si ? x1 : 0.f) * vt[r + TPR];
-                        a2 += (r + 2 * TPR >= si ? x2 : 0.f) * vt[r + 2 * TPR];
-                        a3 += (r + 3 * TPR >= si ? x3 : 0.f) * vt[r + 3 * TPR];
-                    }
-                    for (; r < m; r += TPR) {
-                        float x0 = A[tri_row_offset(r) + si];
-                        a0 += (r >= si ? x0 : 0.f) * vt[r];
+                    if (i2 > i1 && i2 >= 0) {
+                        const float *R2 = A + tri_row_offset(i2);
+                        const int n2 = (i2 + 4) >> 2;
+                        int c = q;
+                        for (; c + 4 < n2; c += 8) {
+                            a2 += dot4(R2 + 4 * c, vrhs + 4 * c);
+                            b2 += dot4(R2 + 4 * (c + 4), vrhs + 4 * (c + 4));
+                        }
+                        for (; c < n2; c += 4) a2 += dot4(R2 + 4 * c, vrhs + 4 * c);
                     }
                 }
-                float acc = group_sum<TPR>((a0 + a1) + (a2 + a3));
-                if (si < m && sq == 0) vxn[si] = vx[si] + acc;
+                float t1 = group_sum<4>(a1 + b1), t2 = group_sum<4>(a2 + b2);
+                if (q == 0 && i1 <= i2 && i1 < m) {
+                    vt[i1] = t1;
+                    if (i2 > i1) vt[i2] = t2;
+                }
             }
             __syncthreads();
-            // v~ - v~_f = D~ x_new (matrix-free, FP64 accumulation)
-            delassus_apply<NT, TPR>(L, m, nb, vp, vxn, vdx);
+            KAMX_MARK(2);
+            // x_new = x + X^T t: columns j and m-1-j paired the same way; the
+            // 16 pairs of a wave walk the same rows (consecutive reads); loads
+            // are issued for every row of the walk (in bounds) and masked;
+            // row offsets advance incrementally, four chains per column
+            {
+                float s1 = 0.f, s2 = 0.f;
+                const int p = tid >> 2, q = tid & 3;
+                const int j1 = p, j2 = m - 1 - p;
+                const int pw = p & ~15;  // first pair of this wave
+                if (j1 <= j2 && j1 < m) {
+#pragma unroll
+                    for (int part = 0; part < 2; ++part) {
+                        const int jc = part == 0 ? j1 : j2;
+                        if (part == 1 && j2 == j1) break;
+                        int rs = part == 0 ? pw : m - 1 - (pw + 15);
+                        if (rs < 0) rs = 0;
+                        int r = rs + q;
+                        // rows r, r+4, r+8, r+12 share r & 3; offsets grow by 16a + 16 + 4b
+                        const int bq = r & 3;
+                        int aq = r >> 2;
+                        int off = tri_row_offset(r);
+                        float c0 = 0.f, c1 = 0.f, c2 = 0.f, c3 = 0.f;
+                        for (; r + 12 < m; r += 16) {
+                            const int o1 = off + 16 * aq + 16 + 4 * bq;
+                            const int o2 = o1 + 16 * (aq + 1) + 16 + 4 * bq;
+                            const int o3 = o2 + 16 * (aq + 2) + 16 + 4 * bq;
+                            float x0 = A[off + jc], x1 = A[o1 + jc], x2 = A[o2 + jc], x3 = A[o3 + jc];
+                            float v0 = vt[r], v1 = vt[r + 4], v2 = vt[r + 8], v3 = vt[r + 12];
+                            c0 += (r >= jc ? x0 : 0.f) * v0;
+                            c1 += (r + 4 >= jc ? x1 : 0.f) * v1;
+                            c2 += (r + 8 >= jc ? x2 : 0.f) * v2;
+                            c3 += (r + 12 >= jc ? x3 : 0.f) * v3;
+                            off = o3 + 16 * (aq + 3) + 16 + 4 * bq;
+                            aq += 4;
+                        }
+                        for (; r < m; r += 4) {
+                            float x0 = A[off + jc];
+                            c0 += (r >= jc ? x0 : 0.f) * vt[r];
+                            off += 16 * aq + 16 + 4 * bq;
+                            aq += 1;
+                        }
+                        if (part == 0) s1 = (c0 + c1) + (c2 + c3);
+                        else s2 = (c0 + c1) + (c2 + c3);
+                    }
+                }
+                s1 = group_sum<4>(s1);
+                s2 = group_sum<4>(s2);
+                if (q == 0 && j1 <= j2 && j1 < m) {
+                    vxn[j1] = vx[j1] + s1;
+                    if (j2 > j1) vxn[j2] = vx[j2] + s2;
+                }
+            }
+            __syncthreads();
+            KAMX_MARK(3);
+            // v~ - v~_f = D~ x_new (matrix-free, FP64): bodies gather here,
+            // each block owner evaluates its own rows below
+            delassus_gather<NT, TPR>(L, nb, vp, vxn);
+            KAMX_MARK(4);
             // steps 6-7 and the residuals of step 9 (block owners)
             float lrp = 0.f, lrd = 0.f, lrc = 0.f, lcc = 0.f;
             float yb[3], zb[3];
             if (owner) {
                 float xn[3], zh[3], yh[3], rr[3], vv[3];
+                double wa[6], wbv[6];
+                const int oa = L.ri(RIA, i), ob = L.ri(RIB, i);  // a block shares its two bodies
+                body_minv64(L, oa, wa);
+                if (ob >= 0) body_minv64(L, ob, wbv);
                 for (int e = 0; e < blk; ++e) {
+                    float dx = delassus_row_w(L, vp, i + e, wa, wbv, ob >= 0);
+                    vdx[i + e] = dx;
                     xn[e] = vxn[i + e];
                     zh[e] = vzh[i + e];
                     yh[e] = vyh[i + e];
                     rr[e] = e == 0 ? rho_i : vrho[i + e];
-                    vv[e] = vdx[i + e] + vvt[i + e];
+                    vv[e] = dx + vvt[i + e];
                 }
                 if (kind_i == kRowNormal) {
                     proj_cone(mu_i, xn[0] - zh[0] / rr[0], xn[1] - zh[1] / rr[1], xn[2] - zh[2] / rr[2], yb[0], yb[1],
@@ -1210,6 +1331,7 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
             rp = lrp;
             rd = lrd;
             rc = lrc;
+            KAMX_MARK(5);
             // step 8: Nesterov with adaptive restart
             int restart = 0;
             float beta = 0.f;
@@ -1243,6 +1365,7 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
                     vzp[i + e] = zb[e];
                 }
             }
+            KAMX_MARK(6);
             if (tid == 0 && a.rlog && P.log_restarts && it <= P.max_iters)
                 a.rlog[(size_t)w * P.max_iters + (it - 1)] = (uint8_t)restart;
             if (!(isfinite(rp) && isfinite(rd) && isfinite(rc))) {
@@ -1254,6 +1377,9 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
                 break;
             }
         }
+#undef KAMX_MARK
+        if (timing)
+            for (int k = 0; k < 6; ++k) a.phase_clk[16 * w + 8 + k] = sub[k];
         if (it > N) it = N;
         if (P.fixed_iters <= 0 && !converged && status == 0) status = KAMX_WORLD_MAXITER;
         __syncthreads();
@@ -1279,7 +1405,7 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
     }
     __syncthreads();
 
-    if (a.phase_clk && tid == 0) a.phase_clk[8 * w + 6] = wall_clock64();
+    if (a.phase_clk && tid == 0) a.phase_clk[16 * w + 6] = wall_clock64();
     // ---- outputs: lambda = P y (Alg. 1 step 11), stats, caches
     if (i < W.row_cap) {
         float lam = 0.f;
@@ -1356,7 +1482,7 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
         for (int k = 0; k < 4; ++k) a.q[7 * gb + 3 + k] = qn[k] * nn;
     }
     __syncthreads();
-    if (a.phase_clk && tid == 0) a.phase_clk[8 * w + 7] = wall_clock64();
+    if (a.phase_clk && tid == 0) a.phase_clk[16 * w + 7] = wall_clock64();
 }
 
 // ---------------------------------------------------------------------------

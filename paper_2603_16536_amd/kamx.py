@@ -344,7 +344,7 @@ class Model:
         return raw, cnt
 
     def phase_clock(self, stream=None):
-        t = torch.empty((self.n_worlds, 8), dtype=torch.int64, device=self.device)
+        t = torch.empty((self.n_worlds, 16), dtype=torch.int64, device=self.device)
         _check(lib().kamx_read_phase_clock(self.handle, _ptr(t), _stream(stream)))
         return t
 
