@@ -31,6 +31,7 @@ def biped_workload(n_worlds, seed=1002):
 CFG2 = dict(dt=2e-3, eta=1e-4, rho_bilateral=1e-4, rho_contact=0.3, eps=1e-6, max_iters=2000,
             baumgarte=0.2, contact_margin=0.02, torque_sigma=5.0, seed=1002, reset_height=0.2)
 PD = (15.0, 0.6)   # the paper's DR Legs gains (N m / rad, N m s / rad)
+TRAIN_SEED = 2002  # noise seed of the rollout that feeds training (the timed rollouts use CFG2's)
 
 
 def incidence_sq(scene, w=0):
@@ -59,13 +60,18 @@ def algorithmic_flops(rows, iters, sum_kb2):
     return m ** 3 / 3.0 + k * (2 * m * m + 30 * m) + 12.0 * sum_kb2 + 2 * m * m
 
 
-def run_gpu(n_worlds, steps, warmup, warmstart):
+def run_gpu(n_worlds, steps, warmup, warmstart, schedule, net=None, seed=None):
     import torch
     from paper_2603_16536_amd import kamx
 
     scene = biped_workload(n_worlds)
     params = dict(CFG2, warmstart=warmstart)
+    if seed is not None:
+        params["seed"] = seed
     model = kamx.Model(scene, params=params, pd=PD, refs=np.zeros(scene.n_joints))
+    model.set_schedule(schedule)
+    if net is not None:
+        model.attach_mlp(net)
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
         model.step(1)
@@ -164,6 +170,11 @@ def main():
     ap.add_argument("--worlds", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-previous", action="store_true", help="skip the previous-step warm-start run")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start run")
+    ap.add_argument("--train-steps", type=int, default=250, help="steps of the cold rollout that feeds training")
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--schedule", choices=("lpt", "index"), default="lpt",
+                    help="dispatch order inside the size bucket: longest previous solve first, or world index")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the run, copy a 256 MiB buffer once (a plain copy kernel of known traffic "
                          "for scaling HBM byte counters)")
@@ -181,7 +192,8 @@ def main():
     kamx.lib()
     print(f"[bench] cold-start rollout: {args.worlds} worlds, warmup {args.warmup}, steps {args.steps}",
           file=sys.stderr, flush=True)
-    cold = run_gpu(args.worlds, args.steps, args.warmup, kamx.WARM_COLD)
+    sched = kamx.SCHED_LPT if args.schedule == "lpt" else kamx.SCHED_INDEX
+    cold = run_gpu(args.worlds, args.steps, args.warmup, kamx.WARM_COLD, sched)
     value = args.worlds * args.steps / cold["wall_s"]
     it = cold["iters"]
     conv = float((cold["status"] == 0).mean())
@@ -204,10 +216,11 @@ def main():
         "config": {"workload": "biped-4096: 31 bodies, 40 revolute joints (10 closed loops), 8 sole probes, "
                                "dt 2 ms, cold-start PADMM to 1e-6 (cap 2000), PD + N(0,5 N m) torques",
                    "worlds": args.worlds, "rows_per_world_max": int(cold["rows"].max()),
-                   "warm_start": "cold (plain ADMM)"},
+                   "warm_start": "cold (plain ADMM)",
+                   "dispatch": "longest previous solve first" if args.schedule == "lpt" else "world index"},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VALU_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 5), "traffic": None,
-                     "kernel": "step_kernel<224,256>",
+                     "kernel": "step_kernel<224,512,2>",
                      "avg_launch_ms": round(float(cold["kernel_ms"].mean()), 4)},
         "solver": {"iters_mean": round(float(it.mean()), 1), "iters_p50": float(np.percentile(it, 50)),
                    "iters_p99": float(np.percentile(it, 99)), "converged_fraction": round(conv, 5),
@@ -215,7 +228,7 @@ def main():
     }
     if not args.no_previous:
         print("[bench] previous-step warm-start rollout", file=sys.stderr, flush=True)
-        prev = run_gpu(args.worlds, args.steps, args.warmup, kamx.WARM_PREVIOUS)
+        prev = run_gpu(args.worlds, args.steps, args.warmup, kamx.WARM_PREVIOUS, sched)
         pit = prev["iters"]
         result["warm_previous"] = {
             "value": round(args.worlds * args.steps / prev["wall_s"], 1),
@@ -223,6 +236,36 @@ def main():
             "iters_mean": round(float(pit.mean()), 1), "iters_p50": float(np.percentile(pit, 50)),
             "iters_p99": float(np.percentile(pit, 99)),
             "converged_fraction": round(float((prev["status"] == 0).mean()), 5)}
+    if not args.no_learned:
+        from paper_2603_16536_amd import learn
+        print(f"[bench] learned warm start: {args.train_steps}-step cold rollout for data (noise seed "
+              f"{TRAIN_SEED}), {args.epochs} epochs", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+
+        def factory():
+            sc = biped_workload(args.worlds)
+            m = kamx.Model(sc, params=dict(CFG2, seed=TRAIN_SEED), pd=PD, refs=np.zeros(sc.n_joints))
+            m.set_schedule(sched)
+            return m
+
+        net, info = learn.fit(factory, args.train_steps, epochs=args.epochs, batch=min(4096, args.worlds), lr=1e-3,
+                              seed=1004, log=lambda msg: print(f"[bench]   {msg}", file=sys.stderr, flush=True))
+        t_train = time.perf_counter() - t0
+        print("[bench] learned warm-start rollout", file=sys.stderr, flush=True)
+        lrn = run_gpu(args.worlds, args.steps, args.warmup, kamx.WARM_LEARNED, sched, net=net)
+        lit = lrn["iters"]
+        result["learned"] = {
+            "value": round(args.worlds * args.steps / lrn["wall_s"], 1),
+            "ms_per_step": round(1e3 * lrn["wall_s"] / args.steps, 4),
+            "speedup_vs_plain": round((args.worlds * args.steps / lrn["wall_s"]) / value, 4),
+            "iters_mean": round(float(lit.mean()), 1), "iters_p50": float(np.percentile(lit, 50)),
+            "iters_p99": float(np.percentile(lit, 99)),
+            "converged_fraction": round(float((lrn["status"] == 0).mean()), 5),
+            "network": "667 -> 256 -> 256 -> 224 (GELU), BF16 matrix-core kernels, FP32 accumulation",
+            "training": {"samples": info["samples"], "held_out": info["held_out"], "epochs": args.epochs,
+                         "final_train_loss": round(info["train_loss"][-1], 5), "val_loss": round(info["val_loss"], 5),
+                         "data_and_training_s": round(t_train, 2), "noise_seed": TRAIN_SEED}}
+        net.close()
     if args.calibrate_copy:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

@@ -53,6 +53,7 @@ extern "C" {
 #endif
 
 typedef struct kamx_model_s *kamx_model;
+typedef struct kamx_mlp_s *kamx_mlp;
 typedef struct ihipStream_t *kamx_stream; /* a hipStream_t; NULL = default stream */
 typedef int32_t kamx_status;
 
@@ -75,6 +76,10 @@ typedef int32_t kamx_status;
 #define KAMX_WARM_COLD 0     /* x = y = z = 0                            */
 #define KAMX_WARM_PREVIOUS 1 /* previous step's impulses, matched by slot */
 #define KAMX_WARM_EXTERNAL 2 /* impulses given by kamx_set_warmstart      */
+#define KAMX_WARM_LEARNED 3  /* prediction of the attached network         */
+
+#define KAMX_SCHED_INDEX 0 /* worlds of a size bucket dispatched in index order              */
+#define KAMX_SCHED_LPT 1   /* by decreasing iteration count of the previous step (default)    */
 
 /* Limits of one world (per-world problem sizes above these are rejected). */
 #define KAMX_MAX_BODIES_PER_WORLD 64
@@ -213,7 +218,23 @@ kamx_status kamx_set_external(kamx_model m, const float *joint_torque_dev, kamx_
  * kamx_model_info.  Copied at the call. */
 kamx_status kamx_set_warmstart(kamx_model m, const float *lambda_dev, kamx_stream stream);
 
-/* Advance every world by nsteps steps (asynchronous on stream). */
+/* Dispatch order of the worlds inside each size bucket (KAMX_SCHED_*).
+ * The order decides only which workgroup slot takes a world: results are
+ * bitwise identical under either mode.  The paper notes that uneven
+ * convergence and wave quantisation leave a tail (Sec. 6.2); ordering by the last
+ * iteration count puts them first.  Host-side, synchronous; EINVAL on an
+ * unknown mode. */
+kamx_status kamx_set_schedule(kamx_model m, int32_t mode);
+
+/* Advance every world by nsteps steps (asynchronous on stream).  nsteps = 1
+ * enqueues the step's kernels directly.  nsteps > 1 replays captured graphs
+ * of up to 32 steps (the loops that run each world to convergence stay
+ * inside the kernels, so the graph has fixed shape, Sec. 5.2); a graph is
+ * captured on first use of a step count and reused until a call that changes
+ * a kernel argument (kamx_set_params, kamx_set_external, kamx_contacts_upload
+ * with another array, kamx_set_schedule) drops it.  Results equal nsteps
+ * single steps bitwise.  Do not call with nsteps > 1 while the stream is
+ * itself being captured (use nsteps = 1 there). */
 kamx_status kamx_step(kamx_model m, int32_t nsteps, kamx_stream stream);
 
 /* Impulses of the last step (physical units, N s) into lambda_dev
@@ -253,6 +274,88 @@ kamx_status kamx_reset_count(kamx_model m, int64_t *count, kamx_stream stream);
  * when the environment variable KAMX_PHASE_CLOCK was set at model creation;
  * otherwise ESTATE. */
 kamx_status kamx_read_phase_clock(kamx_model m, uint64_t *clk_dev, kamx_stream stream);
+
+/* ---- learned warm start --------------------------------------------------
+ * Not in the paper, whose only warm start is the previous step's impulses
+ * (Sec. 4.1).  A network predicts a world's dual impulses for the coming
+ * step from its state features; the prediction only sets the starting point
+ * of Alg. 1 (the exit test on the residuals is unchanged), so a poor
+ * prediction costs iterations, never accuracy.
+ *
+ * Network: x^ = (x - mu_in) / sigma_in; z1 = W1 x^ + b1, h1 = gelu(z1);
+ * z2 = W2 h1 + b2, h2 = gelu(z2); y = mu_out + sigma_out (W3 h2 + b3), with
+ * gelu the erf form.  Every product runs on the matrix cores with BF16
+ * operands (round to nearest even) and FP32 accumulation; master weights,
+ * Adam moments and gradients are FP32.  Training minimises the mean squared
+ * error of the standardised outputs with bias-corrected Adam (beta1 0.9,
+ * beta2 0.999, eps 1e-8).
+ *
+ * Packed parameter order (FP32, row-major): W1 [n_hidden][n_in_pad],
+ * b1 [n_hidden], W2 [n_hidden][n_hidden], b2 [n_hidden],
+ * W3 [n_out_pad][n_hidden], b3 [n_out_pad]; n_in_pad and n_out_pad are
+ * n_in and n_out rounded up to multiples of 64 (padding entries stay zero
+ * under training).  Batches are padded to multiples of 64 inside. */
+
+/* Create a network with initial weights U(-1/sqrt(fan_in), 1/sqrt(fan_in))
+ * drawn from splitmix64(seed), identity normalisation, and workspace for
+ * batches up to max_batch.  n_hidden must be a multiple of 64 in [64, 4096].
+ * EINVAL on bad sizes, ENOMEM when device memory runs out. */
+kamx_status kamx_mlp_create(int32_t n_in, int32_t n_hidden, int32_t n_out, int32_t max_batch, uint64_t seed,
+                            kamx_mlp *out);
+kamx_status kamx_mlp_destroy(kamx_mlp net);
+
+/* Padded sizes and the number of packed FP32 parameters. */
+kamx_status kamx_mlp_info(kamx_mlp net, int32_t *n_in_pad, int32_t *n_out_pad, int64_t *n_params);
+
+/* Standardisation of inputs and outputs (device arrays mu_in, sigma_in
+ * [n_in], mu_out, sigma_out [n_out]).  An input with sigma <= 1e-12 is
+ * ignored (scale 0); an output with sigma <= 1e-12 uses sigma 1. */
+kamx_status kamx_mlp_set_normalization(kamx_mlp net, const float *mu_in, const float *sigma_in, const float *mu_out,
+                                       const float *sigma_out, kamx_stream stream);
+
+/* y_dev [batch][n_out] = network(x_dev [batch][n_in]); 1 <= batch <= max_batch. */
+kamx_status kamx_mlp_forward(kamx_mlp net, const float *x_dev, int32_t batch, float *y_dev, kamx_stream stream);
+
+/* One Adam step on the mean squared error of the standardised outputs
+ * against y_target_dev [batch][n_out] (physical units).  loss_dev (device,
+ * may be NULL) receives the loss before the update. */
+kamx_status kamx_mlp_train_step(kamx_mlp net, const float *x_dev, const float *y_target_dev, int32_t batch, float lr,
+                                float *loss_dev, kamx_stream stream);
+
+/* Packed FP32 parameters: set != 0 copies buf_dev in (and clears the Adam
+ * state), set == 0 copies them out. */
+kamx_status kamx_mlp_weights(kamx_mlp net, float *buf_dev, int32_t set, kamx_stream stream);
+
+/* Gradients of the last kamx_mlp_train_step (packed order) into buf_dev. */
+kamx_status kamx_mlp_gradients(kamx_mlp net, float *buf_dev, kamx_stream stream);
+
+/* Feature and slot sizes of a model whose worlds share one structure (same
+ * bodies, joints, limited joints and contact capacity; else EUNSUPPORTED).
+ * Slots: the 5 rows of every joint and the limit rows in row order, then
+ * three (n, t1, t2) per contact key 0 .. contact capacity - 1 (the probe
+ * index for probe contacts).  Features per world: for every body its
+ * position relative to the world's reset body (3), quaternion (4), linear
+ * and angular velocity (6); then the previous step's impulses by slot
+ * (zero after a reset); then the generalized joint forces of the coming
+ * step (actuation, noise and external). */
+kamx_status kamx_model_feature_dims(kamx_model m, int32_t *n_features, int32_t *n_slots);
+
+/* Features of the coming step into x_dev [n_worlds][n_features]. */
+kamx_status kamx_model_features(kamx_model m, float *x_dev, kamx_stream stream);
+
+/* Impulses of the last step by slot into y_dev [n_worlds][n_slots]
+ * (physical units; slots without a contact are zero): the training targets
+ * of the network. */
+kamx_status kamx_read_impulse_slots(kamx_model m, float *y_dev, kamx_stream stream);
+
+/* Network used by KAMX_WARM_LEARNED: n_in = n_features, n_out = n_slots,
+ * batch capacity >= n_worlds; NULL detaches.  The model keeps the pointer
+ * (the caller keeps the network alive while steps use it); its weights may
+ * change between steps.  With the network attached and warmstart LEARNED,
+ * every step runs the feature pass, the network, then the solve warm
+ * started from the prediction by slot (Alg. 1 step 2 with the previous-step
+ * cache replaced by the prediction). */
+kamx_status kamx_model_attach_mlp(kamx_model m, kamx_mlp net);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *kamx_last_error(void);

@@ -16,6 +16,15 @@ namespace kamx {
 hipError_t launch_step(const StepArgs &args, int mc, int n, hipStream_t stream);
 int bucket_capacity(int rows);
 size_t step_smem_bytes(int mc);
+hipError_t launch_lpt_order(const int32_t *worlds, int n, const int32_t *iters, int32_t *order, hipStream_t stream);
+hipError_t launch_advance_step(uint32_t *ctr, hipStream_t stream);
+hipError_t launch_impulse_slots(const WorldInfo *worlds, int n_worlds, int n_contact_slots, int n_slots,
+                                const float *lambda, const int32_t *keys, const int32_t *ncontacts, float *out,
+                                hipStream_t stream);
+kamx_status mlp_forward_internal(kamx_mlp n, const float *x, int batch, float *y, hipStream_t s);
+int mlp_n_in(kamx_mlp n);
+int mlp_n_out(kamx_mlp n);
+int mlp_capacity(kamx_mlp n);
 }  // namespace kamx
 
 using namespace kamx;
@@ -32,6 +41,18 @@ static kamx_status fail(kamx_status st, const char *fmt, ...) {
     return st;
 }
 
+namespace kamx {
+kamx_status mlp_fail(kamx_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return st;
+}
+}  // namespace kamx
+
 #define HIP_TRY(expr)                                                                          \
     do {                                                                                       \
         hipError_t e_ = (expr);                                                                \
@@ -41,7 +62,8 @@ static kamx_status fail(kamx_status st, const char *fmt, ...) {
 struct Bucket {
     int mc;
     int n;
-    int32_t *d_worlds;
+    int32_t *d_worlds;  // the bucket's worlds in index order
+    int32_t *d_order;   // dispatch order of the next step (a permutation of d_worlds)
 };
 
 struct kamx_model_s {
@@ -51,6 +73,7 @@ struct kamx_model_s {
     int max_contacts = 0;
     kamx_params params{};
     uint32_t step_index = 0;
+    int32_t schedule = KAMX_SCHED_LPT;
     std::vector<int32_t> row_offsets;
     std::vector<Bucket> buckets;
     std::vector<void *> allocations;
@@ -73,7 +96,24 @@ struct kamx_model_s {
     kamx_contact *d_contacts_out = nullptr;
     int32_t *d_ncontacts = nullptr, *d_reset_count = nullptr;
     uint64_t *d_phase_clk = nullptr;  // debug phase stamps (enabled by KAMX_PHASE_CLOCK)
+    uint32_t *d_step = nullptr;       // step counter read by the step kernels
+    // learned warm start (worlds of identical structure only)
+    bool uniform = false;
+    int n_feat = 0, n_slots = 0, n_contact_slots = 0;
+    kamx_mlp mlp = nullptr;
+    float *d_feat = nullptr, *d_ws = nullptr;
+    // captured multi-step rollouts: graph executables by step count; kernel
+    // arguments are baked in, so every setter that changes one clears them
+    std::vector<std::pair<int, hipGraphExec_t>> graphs;
+    hipStream_t capture_stream = nullptr;
 };
+
+static constexpr int kGraphSteps = 32;  // steps per captured graph
+
+static void drop_graphs(kamx_model m) {
+    for (auto &g : m->graphs) (void)hipGraphExecDestroy(g.second);
+    m->graphs.clear();
+}
 
 template <typename T>
 static kamx_status dalloc(kamx_model m, T **p, size_t count) {
@@ -108,7 +148,7 @@ static kamx_status validate_params(const kamx_params *p) {
     if (p->max_iters < 1 || p->max_iters > 1000000) return fail(KAMX_EINVAL, "max_iters out of range");
     if (p->fixed_iters < 0 || p->fixed_iters > 1000000) return fail(KAMX_EINVAL, "fixed_iters out of range");
     if (!(p->restart_factor > 0.f)) return fail(KAMX_EINVAL, "restart_factor must be positive");
-    if (p->warmstart < KAMX_WARM_COLD || p->warmstart > KAMX_WARM_EXTERNAL) return fail(KAMX_EINVAL, "bad warmstart");
+    if (p->warmstart < KAMX_WARM_COLD || p->warmstart > KAMX_WARM_LEARNED) return fail(KAMX_EINVAL, "bad warmstart");
     return KAMX_OK;
 }
 
@@ -168,6 +208,7 @@ const char *kamx_last_error(void) { return g_error.c_str(); }
 static kamx_status ensure_rlog(kamx_model m) {
     if (!m->params.log_restarts) return KAMX_OK;
     if (m->d_rlog && m->rlog_stride == m->params.max_iters) return KAMX_OK;
+    drop_graphs(m);
     if (m->d_rlog) {
         HIP_TRY(hipDeviceSynchronize());
         auto it = std::find(m->allocations.begin(), m->allocations.end(), (void *)m->d_rlog);
@@ -269,6 +310,14 @@ kamx_status kamx_model_create(const kamx_body_desc *bodies, int32_t nb, const ka
     m->max_contacts = max_contacts_per_world;
     m->params = *params;
     m->row_offsets = row_off;
+    m->uniform = true;
+    for (int w = 1; w < n_worlds; ++w)
+        if (wi[w].nb != wi[0].nb || wi[w].nj != wi[0].nj || wi[w].nlim != wi[0].nlim ||
+            wi[w].contact_cap != wi[0].contact_cap)
+            m->uniform = false;
+    m->n_contact_slots = wi[0].contact_cap;
+    m->n_slots = 5 * wi[0].nj + wi[0].nlim + 3 * wi[0].contact_cap;
+    m->n_feat = 13 * wi[0].nb + m->n_slots + wi[0].nj;
 
     auto cleanup_fail = [&](kamx_status st) {
         kamx_model_destroy(m);
@@ -330,6 +379,7 @@ kamx_status kamx_model_create(const kamx_body_desc *bodies, int32_t nb, const ka
     M_TRY(dalloc(m, &m->d_pbody, pbody.size()));
     M_TRY(dalloc(m, &m->d_pf, pf.size()));
     M_TRY(dalloc(m, &m->d_coff, n_worlds + 1));
+    M_TRY(dalloc(m, &m->d_step, 1));
     M_TRY(dalloc(m, &m->d_lambda, m->rows_cap));
     M_TRY(dalloc(m, &m->d_lambda_ext, m->rows_cap));
     M_TRY(dalloc(m, &m->d_keys, (size_t)n_worlds * kMaxContacts));
@@ -374,6 +424,9 @@ kamx_status kamx_model_create(const kamx_body_desc *bodies, int32_t nb, const ka
         b.d_worlds = nullptr;
         M_TRY(dalloc(m, &b.d_worlds, groups[s].size()));
         M_TRY(up(b.d_worlds, groups[s].data(), sizeof(int32_t) * groups[s].size()));
+        b.d_order = nullptr;
+        M_TRY(dalloc(m, &b.d_order, groups[s].size()));
+        M_TRY(up(b.d_order, groups[s].data(), sizeof(int32_t) * groups[s].size()));
         m->buckets.push_back(b);
     }
     *out = m;
@@ -383,8 +436,10 @@ kamx_status kamx_model_create(const kamx_body_desc *bodies, int32_t nb, const ka
 
 kamx_status kamx_model_destroy(kamx_model m) {
     if (!m) return KAMX_OK;
-    hipDeviceSynchronize();
-    for (void *p : m->allocations) hipFree(p);
+    (void)hipDeviceSynchronize();
+    drop_graphs(m);
+    if (m->capture_stream) (void)hipStreamDestroy(m->capture_stream);
+    for (void *p : m->allocations) (void)hipFree(p);
     delete m;
     return KAMX_OK;
 }
@@ -393,6 +448,7 @@ kamx_status kamx_set_params(kamx_model m, const kamx_params *params) {
     if (!m) return fail(KAMX_EINVAL, "model is NULL");
     K_TRY(validate_params(params));
     m->params = *params;
+    drop_graphs(m);
     K_TRY(ensure_rlog(m));
     return KAMX_OK;
 }
@@ -435,6 +491,7 @@ kamx_status kamx_contacts_upload(kamx_model m, const kamx_contact *contacts_dev,
                                  kamx_stream stream) {
     if (!m) return fail(KAMX_EINVAL, "model is NULL");
     if (!contacts_dev) {
+        if (m->d_contacts) drop_graphs(m);
         m->d_contacts = nullptr;
         return KAMX_OK;
     }
@@ -449,6 +506,7 @@ kamx_status kamx_contacts_upload(kamx_model m, const kamx_contact *contacts_dev,
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     HIP_TRY(hipMemcpyAsync(m->d_coff, world_offsets, sizeof(int32_t) * (m->n_worlds + 1), hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));  // world_offsets is a host array of the caller
+    if (m->d_contacts != contacts_dev) drop_graphs(m);
     m->d_contacts = contacts_dev;
     return KAMX_OK;
 }
@@ -456,6 +514,7 @@ kamx_status kamx_contacts_upload(kamx_model m, const kamx_contact *contacts_dev,
 kamx_status kamx_set_external(kamx_model m, const float *joint_torque_dev, kamx_stream stream) {
     (void)stream;
     if (!m) return fail(KAMX_EINVAL, "model is NULL");
+    if (m->d_ext != joint_torque_dev) drop_graphs(m);
     m->d_ext = joint_torque_dev;
     return KAMX_OK;
 }
@@ -468,12 +527,7 @@ kamx_status kamx_set_warmstart(kamx_model m, const float *lambda_dev, kamx_strea
     return KAMX_OK;
 }
 
-kamx_status kamx_step(kamx_model m, int32_t nsteps, kamx_stream stream) {
-    if (!m) return fail(KAMX_EINVAL, "model is NULL");
-    if (nsteps < 0) return fail(KAMX_EINVAL, "nsteps < 0");
-    K_TRY(check_device());
-    if (m->params.log_restarts) K_TRY(ensure_rlog(m));
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+static StepArgs step_args(kamx_model m) {
     StepArgs a;
     memset(&a, 0, sizeof a);
     a.worlds = m->d_worlds;
@@ -504,15 +558,161 @@ kamx_status kamx_step(kamx_model m, int32_t nsteps, kamx_stream stream) {
     a.reset_count = m->d_reset_count;
     a.phase_clk = m->d_phase_clk;
     a.p = to_solver(m->params);
+    a.step_ctr = m->d_step;
+    a.stage = 0;
+    a.n_feat = m->n_feat;
+    a.ws_slots = m->d_ws;
+    a.n_contact_slots = m->n_contact_slots;
+    return a;
+}
+
+// Feature pass of every bucket (the step kernels stopped after actuation).
+static kamx_status enqueue_features(kamx_model m, float *x, hipStream_t s) {
+    StepArgs a = step_args(m);
+    a.stage = 1;
+    a.features = x;
+    a.phase_clk = nullptr;
+    for (const Bucket &b : m->buckets) {
+        a.bucket_worlds = b.d_worlds;
+        a.n_bucket_worlds = b.n;
+        hipError_t e = launch_step(a, b.mc, b.n, s);
+        if (e != hipSuccess) return fail(KAMX_EDEVICE, "feature launch (bucket %d rows): %s", b.mc, hipGetErrorString(e));
+    }
+    return KAMX_OK;
+}
+
+// Enqueue nsteps steps: per step, every bucket's step kernel (largest
+// worlds first) and its dispatch order for the next step, then the counter.
+// With the learned warm start each step first runs the feature pass and the
+// network.
+static kamx_status enqueue_steps(kamx_model m, int nsteps, hipStream_t s) {
+    const StepArgs base = step_args(m);
+    const bool lpt = m->schedule == KAMX_SCHED_LPT;
+    const bool learned = m->params.warmstart == KAMX_WARM_LEARNED;
     for (int k = 0; k < nsteps; ++k) {
-        a.step_index = m->step_index++;
+        if (learned) {
+            K_TRY(enqueue_features(m, m->d_feat, s));
+            K_TRY(mlp_forward_internal(m->mlp, m->d_feat, m->n_worlds, m->d_ws, s));
+        }
         for (const Bucket &b : m->buckets) {
-            a.bucket_worlds = b.d_worlds;
+            StepArgs a = base;
+            a.bucket_worlds = lpt ? b.d_order : b.d_worlds;
             a.n_bucket_worlds = b.n;
             hipError_t e = launch_step(a, b.mc, b.n, s);
             if (e != hipSuccess) return fail(KAMX_EDEVICE, "step launch (bucket %d rows): %s", b.mc, hipGetErrorString(e));
+            if (lpt && b.n > 1) {
+                e = launch_lpt_order(b.d_worlds, b.n, m->d_iters, b.d_order, s);
+                if (e != hipSuccess) return fail(KAMX_EDEVICE, "schedule launch (bucket %d rows): %s", b.mc, hipGetErrorString(e));
+            }
+        }
+        hipError_t e = launch_advance_step(m->d_step, s);
+        if (e != hipSuccess) return fail(KAMX_EDEVICE, "counter launch: %s", hipGetErrorString(e));
+    }
+    return KAMX_OK;
+}
+
+// Graph executable of n steps (captured on the model's own stream on first
+// use; replayed on any stream).
+static kamx_status rollout_graph(kamx_model m, int n, hipGraphExec_t *out) {
+    for (auto &g : m->graphs)
+        if (g.first == n) {
+            *out = g.second;
+            return KAMX_OK;
+        }
+    if (!m->capture_stream) HIP_TRY(hipStreamCreateWithFlags(&m->capture_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(m->capture_stream, hipStreamCaptureModeRelaxed));
+    kamx_status st = enqueue_steps(m, n, m->capture_stream);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(m->capture_stream, &graph);
+    if (st != KAMX_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (e != hipSuccess) return fail(KAMX_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(KAMX_EDEVICE, "graph instantiate: %s", hipGetErrorString(e));
+    m->graphs.push_back({n, exec});
+    *out = exec;
+    return KAMX_OK;
+}
+
+kamx_status kamx_step(kamx_model m, int32_t nsteps, kamx_stream stream) {
+    if (!m) return fail(KAMX_EINVAL, "model is NULL");
+    if (nsteps < 0) return fail(KAMX_EINVAL, "nsteps < 0");
+    if (m->params.warmstart == KAMX_WARM_LEARNED && !m->mlp)
+        return fail(KAMX_ESTATE, "warm start LEARNED needs a network (kamx_model_attach_mlp)");
+    K_TRY(check_device());
+    if (m->params.log_restarts) K_TRY(ensure_rlog(m));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (nsteps == 1) {
+        K_TRY(enqueue_steps(m, 1, s));
+    } else if (nsteps > 1) {
+        const int chunk = std::min<int>(nsteps, kGraphSteps);
+        hipGraphExec_t g = nullptr;
+        K_TRY(rollout_graph(m, chunk, &g));
+        for (int k = 0; k < nsteps / chunk; ++k) HIP_TRY(hipGraphLaunch(g, s));
+        if (nsteps % chunk) {
+            K_TRY(rollout_graph(m, nsteps % chunk, &g));
+            HIP_TRY(hipGraphLaunch(g, s));
         }
     }
+    m->step_index += (uint32_t)nsteps;
+    return KAMX_OK;
+}
+
+kamx_status kamx_model_feature_dims(kamx_model m, int32_t *n_features, int32_t *n_slots) {
+    if (!m) return fail(KAMX_EINVAL, "model is NULL");
+    if (!m->uniform) return fail(KAMX_EUNSUPPORTED, "worlds differ in structure: no common feature layout");
+    if (n_features) *n_features = m->n_feat;
+    if (n_slots) *n_slots = m->n_slots;
+    return KAMX_OK;
+}
+
+kamx_status kamx_model_features(kamx_model m, float *x_dev, kamx_stream stream) {
+    if (!m || !x_dev) return fail(KAMX_EINVAL, "NULL argument");
+    if (!m->uniform) return fail(KAMX_EUNSUPPORTED, "worlds differ in structure: no common feature layout");
+    K_TRY(check_device());
+    return enqueue_features(m, x_dev, reinterpret_cast<hipStream_t>(stream));
+}
+
+kamx_status kamx_read_impulse_slots(kamx_model m, float *y_dev, kamx_stream stream) {
+    if (!m || !y_dev) return fail(KAMX_EINVAL, "NULL argument");
+    if (!m->uniform) return fail(KAMX_EUNSUPPORTED, "worlds differ in structure: no common slot layout");
+    K_TRY(check_device());
+    hipError_t e = launch_impulse_slots(m->d_worlds, m->n_worlds, m->n_contact_slots, m->n_slots, m->d_lambda,
+                                        m->d_keys, m->d_ncontacts, y_dev, reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail(KAMX_EDEVICE, "slot launch: %s", hipGetErrorString(e));
+    return KAMX_OK;
+}
+
+kamx_status kamx_model_attach_mlp(kamx_model m, kamx_mlp net) {
+    if (!m) return fail(KAMX_EINVAL, "model is NULL");
+    drop_graphs(m);
+    if (!net) {
+        m->mlp = nullptr;
+        return KAMX_OK;
+    }
+    if (!m->uniform) return fail(KAMX_EUNSUPPORTED, "worlds differ in structure: no common feature layout");
+    if (mlp_n_in(net) != m->n_feat || mlp_n_out(net) != m->n_slots)
+        return fail(KAMX_EINVAL, "network is %d -> %d, the model needs %d -> %d", mlp_n_in(net), mlp_n_out(net),
+                    m->n_feat, m->n_slots);
+    if (mlp_capacity(net) < m->n_worlds)
+        return fail(KAMX_EINVAL, "network batch capacity %d below %d worlds", mlp_capacity(net), m->n_worlds);
+    if (!m->d_feat) {
+        K_TRY(dalloc(m, &m->d_feat, (size_t)m->n_worlds * m->n_feat));
+        K_TRY(dalloc(m, &m->d_ws, (size_t)m->n_worlds * m->n_slots));
+    }
+    m->mlp = net;
+    return KAMX_OK;
+}
+
+kamx_status kamx_set_schedule(kamx_model m, int32_t mode) {
+    if (!m) return fail(KAMX_EINVAL, "model is NULL");
+    if (mode != KAMX_SCHED_INDEX && mode != KAMX_SCHED_LPT) return fail(KAMX_EINVAL, "unknown schedule mode %d", mode);
+    if (m->schedule != mode) drop_graphs(m);
+    m->schedule = mode;
     return KAMX_OK;
 }
 

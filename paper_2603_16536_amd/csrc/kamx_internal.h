@@ -86,9 +86,15 @@ struct StepArgs {
     kamx_contact *contacts_out;  // [n_worlds*kMaxContacts]
     int32_t *ncontacts_out;      // [n_worlds]
     int32_t *reset_count;        // [n_worlds]
-    uint64_t *phase_clk;         // [n_worlds*8] phase time stamps, or null
+    uint64_t *phase_clk;         // [n_worlds*16] phase time stamps, or null
     SolverParams p;
-    uint32_t step_index;
+    const uint32_t *step_ctr;    // device step counter (noise key), advanced after every step
+    // learned warm start
+    int32_t stage;               // 0: full step; 1: write the features of the coming step and stop
+    float *features;             // [n_worlds * n_feat] (stage 1)
+    int32_t n_feat;
+    const float *ws_slots;       // network output [n_worlds * slots] (warm start mode LEARNED)
+    int32_t n_contact_slots;     // contact keys with a slot (probes per world, else contact capacity)
 };
 
 // Packed lower-triangular storage with every row padded to a multiple of 4

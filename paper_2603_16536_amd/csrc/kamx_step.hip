@@ -545,7 +545,7 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
             rs = z < P.reset_height;
         }
         s_int[0] = rs;
-        if (rs) a.reset_count[w] += 1;
+        if (rs && a.stage == 0) a.reset_count[w] += 1;
     }
     __syncthreads();
     const int reset = s_int[0];
@@ -569,6 +569,7 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
 
     // ---- joints: coordinate, rate and actuation (generalized force along
     //      the coordinate: external + PD + noise)
+    const uint32_t step = *a.step_ctr;
     for (int j = tid; j < nj; j += NT) {
         int gj = W.j0 + j;
         int type = a.jint[4 * gj], la = a.jint[4 * gj + 1], lb = a.jint[4 * gj + 2], fl = a.jint[4 * gj + 3];
@@ -585,7 +586,7 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
         float kp = jf[16], kd = jf[17], ref = jf[18];
         if (kp != 0.f || kd != 0.f) tau += kp * (ref - c) - kd * rate;
         if ((fl & kJointActuated) && P.torque_sigma != 0.f)
-            tau += P.torque_sigma * noise_normal(P.seed_lo, P.seed_hi, (uint32_t)w, a.step_index, (uint32_t)j);
+            tau += P.torque_sigma * noise_normal(P.seed_lo, P.seed_hi, (uint32_t)w, step, (uint32_t)j);
         L.jfld(JTAU, j) = tau;
         for (int k = 0; k < 6; ++k) {
             L.jfld(JC + k, j) = Ja[k];
@@ -597,6 +598,43 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
         a.tau_out[gj] = tau;
     }
     __syncthreads();
+
+    // ---- feature pass of the learned warm start: the state the step starts
+    //      from (positions relative to the reset body), the previous step's
+    //      impulses by slot and the generalized forces of this step
+    if (a.stage == 1) {
+        float *f = a.features + (long)w * a.n_feat;
+        const int rb = W.reset_body;
+        for (int t = tid; t < 13 * nb; t += NT) {
+            const int b = t / 13, c = t - 13 * (t / 13);
+            float v;
+            if (c < 3) v = L.bf(BQ + c, b) - (rb >= 0 ? L.bf(BQ + c, rb) : 0.f);
+            else if (c < 7) v = L.bf(BQ + c, b);
+            else v = L.bf(BU + c - 7, b);
+            f[t] = v;
+        }
+        const int rc0 = 5 * nj + W.nlim;
+        const int S = rc0 + 3 * a.n_contact_slots;
+        for (int t = tid; t < S; t += NT) {
+            float v = 0.f;
+            if (!reset) {
+                if (t < rc0) {
+                    v = a.lambda[W.row_base + t];
+                } else {
+                    const int key = (t - rc0) / 3, e = (t - rc0) - 3 * ((t - rc0) / 3);
+                    const int nprev = a.ncontacts_out[w];
+                    for (int k = 0; k < nprev && k < kMaxContacts; ++k)
+                        if (a.keys[w * kMaxContacts + k] == key) {
+                            v = a.lambda[W.row_base + rc0 + 3 * k + e];
+                            break;
+                        }
+                }
+            }
+            f[13 * nb + t] = v;
+        }
+        for (int j = tid; j < nj; j += NT) f[13 * nb + S + j] = L.jfld(JTAU, j);
+        return;
+    }
 
     // ---- free velocity of every body: u_f = u + dt M^-1 h
     for (int b = tid; b < nb; b += NT) {
@@ -927,6 +965,17 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
             float lw = 0.f;
             if (wmode == KAMX_WARM_EXTERNAL) {
                 lw = a.lambda_ext[W.row_base + i];
+            } else if (wmode == KAMX_WARM_LEARNED) {
+                // network output by slot: joint and limit rows in order, then
+                // three slots per contact key
+                const float *ws = a.ws_slots + (long)w * (row_c0 + 3 * a.n_contact_slots);
+                if (i < row_c0) {
+                    lw = ws[i];
+                } else {
+                    int c = (i - row_c0) / 3, e = (i - row_c0) % 3;
+                    int key = cint[CKEY * kMaxContacts + c];
+                    lw = key >= 0 && key < a.n_contact_slots ? ws[row_c0 + 3 * key + e] : 0.f;
+                }
             } else if (i < row_c0) {
                 lw = a.lambda[W.row_base + i];
             } else {
@@ -1173,7 +1222,7 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
 #define KAMX_MARK(k)                                  \
     if (timing) {                                     \
         uint64_t now_ = wall_clock64();               \
-        if ((k) > 0) sub[(k) - 1] += now_ - tmark;    \
+        if ((k) > 0) sub[(k) > 0 ? (k) - 1 : 0] += now_ - tmark; \
         tmark = now_;                                 \
     }
         for (it = 1; it <= N; ++it) {
@@ -1483,6 +1532,43 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
     }
     __syncthreads();
     if (a.phase_clk && tid == 0) a.phase_clk[16 * w + 7] = wall_clock64();
+}
+
+// Impulses of the last step in slot layout (joint and limit rows, then three
+// slots per contact key; slots of absent contacts are zero), one thread per
+// world and slot.
+__global__ void impulse_slots_kernel(const WorldInfo *worlds, int n_worlds, int n_contact_slots, const float *lambda,
+                                     const int32_t *keys, const int32_t *ncontacts, float *out) {
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const WorldInfo W0 = worlds[0];
+    const int S = 5 * W0.nj + W0.nlim + 3 * n_contact_slots;
+    if (idx >= (long)n_worlds * S) return;
+    const int w = (int)(idx / S), t = (int)(idx - (long)w * S);
+    const WorldInfo W = worlds[w];
+    const int rc0 = 5 * W.nj + W.nlim;
+    float v = 0.f;
+    if (t < rc0) {
+        v = lambda[W.row_base + t];
+    } else {
+        const int key = (t - rc0) / 3, e = (t - rc0) % 3;
+        const int n = ncontacts[w];
+        for (int k = 0; k < n && k < kMaxContacts; ++k)
+            if (keys[w * kMaxContacts + k] == key) {
+                v = lambda[W.row_base + rc0 + 3 * k + e];
+                break;
+            }
+    }
+    out[idx] = v;
+}
+
+hipError_t launch_impulse_slots(const WorldInfo *worlds, int n_worlds, int n_contact_slots, int n_slots,
+                                const float *lambda, const int32_t *keys, const int32_t *ncontacts, float *out,
+                                hipStream_t stream) {
+    const long total = (long)n_worlds * n_slots;
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(impulse_slots_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, worlds,
+                       n_worlds, n_contact_slots, lambda, keys, ncontacts, out);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

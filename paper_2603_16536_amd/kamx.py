@@ -20,7 +20,8 @@ LIB_PATH = os.path.join(HERE, "libkamx.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 WORLD_OK, WORLD_MAXITER, WORLD_NONFINITE, WORLD_FACTOR_FAIL = 0, 1, 2, 4
-WARM_COLD, WARM_PREVIOUS, WARM_EXTERNAL = 0, 1, 2
+WARM_COLD, WARM_PREVIOUS, WARM_EXTERNAL, WARM_LEARNED = 0, 1, 2, 3
+SCHED_INDEX, SCHED_LPT = 0, 1
 MAX_CONTACTS_PER_WORLD = 64
 
 
@@ -87,6 +88,19 @@ def lib():
         L.kamx_set_external.argtypes = [vp, vp, vp]
         L.kamx_set_warmstart.argtypes = [vp, vp, vp]
         L.kamx_step.argtypes = [vp, i32, vp]
+        L.kamx_set_schedule.argtypes = [vp, i32]
+        L.kamx_mlp_create.argtypes = [i32, i32, i32, i32, C.c_uint64, C.POINTER(vp)]
+        L.kamx_mlp_destroy.argtypes = [vp]
+        L.kamx_mlp_info.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), i64p]
+        L.kamx_mlp_set_normalization.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.kamx_mlp_forward.argtypes = [vp, vp, i32, vp, vp]
+        L.kamx_mlp_train_step.argtypes = [vp, vp, vp, i32, C.c_float, vp, vp]
+        L.kamx_mlp_weights.argtypes = [vp, vp, i32, vp]
+        L.kamx_mlp_gradients.argtypes = [vp, vp, vp]
+        L.kamx_model_feature_dims.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.kamx_model_features.argtypes = [vp, vp, vp]
+        L.kamx_read_impulse_slots.argtypes = [vp, vp, vp]
+        L.kamx_model_attach_mlp.argtypes = [vp, vp]
         L.kamx_read_impulses.argtypes = [vp, vp, vp]
         L.kamx_read_stats.argtypes = [vp, vp, vp, vp, vp, vp]
         L.kamx_read_restart_log.argtypes = [vp, vp, vp]
@@ -98,7 +112,10 @@ def lib():
                      "kamx_state_upload", "kamx_state_download", "kamx_contacts_upload", "kamx_set_external",
                      "kamx_set_warmstart", "kamx_step", "kamx_read_impulses", "kamx_read_stats",
                      "kamx_read_restart_log", "kamx_read_torques", "kamx_read_contacts", "kamx_reset_count",
-                     "kamx_read_phase_clock"):
+                     "kamx_read_phase_clock", "kamx_set_schedule", "kamx_mlp_create", "kamx_mlp_destroy",
+                     "kamx_mlp_info", "kamx_mlp_set_normalization", "kamx_mlp_forward", "kamx_mlp_train_step",
+                     "kamx_mlp_weights", "kamx_mlp_gradients", "kamx_model_feature_dims", "kamx_model_features",
+                     "kamx_read_impulse_slots", "kamx_model_attach_mlp"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -296,6 +313,37 @@ class Model:
         torch.cuda.current_stream(self.device).synchronize()
 
     # -- stepping ------------------------------------------------------------
+    # -- learned warm start --------------------------------------------------
+    def feature_dims(self):
+        """(n_features, n_slots) of a model whose worlds share one structure."""
+        nf, ns = C.c_int32(), C.c_int32()
+        _check(lib().kamx_model_feature_dims(self.handle, C.byref(nf), C.byref(ns)))
+        return nf.value, ns.value
+
+    def features(self, out=None, stream=None):
+        """Features of the coming step, [n_worlds, n_features] (device)."""
+        nf, _ = self.feature_dims()
+        x = out if out is not None else torch.empty((self.n_worlds, nf), dtype=torch.float32, device=self.device)
+        _check(lib().kamx_model_features(self.handle, _ptr(x), _stream(stream)))
+        return x
+
+    def impulse_slots(self, out=None, stream=None):
+        """Impulses of the last step by slot, [n_worlds, n_slots] (device)."""
+        _, ns = self.feature_dims()
+        y = out if out is not None else torch.empty((self.n_worlds, ns), dtype=torch.float32, device=self.device)
+        _check(lib().kamx_read_impulse_slots(self.handle, _ptr(y), _stream(stream)))
+        return y
+
+    def attach_mlp(self, net):
+        """Network for the LEARNED warm start (None detaches); the model
+        keeps a reference so the network outlives its use."""
+        _check(lib().kamx_model_attach_mlp(self.handle, net.handle if net is not None else None))
+        self._mlp = net
+
+    def set_schedule(self, mode):
+        """Dispatch order inside size buckets: SCHED_LPT (default) or SCHED_INDEX."""
+        _check(lib().kamx_set_schedule(self.handle, int(mode)))
+
     def step(self, n=1, stream=None):
         _check(lib().kamx_step(self.handle, int(n), _stream(stream)))
 
@@ -375,3 +423,68 @@ def contacts_to_scene(scene, raw, counts):
         contact_world=np.array(cw, np.int32), contact_body=np.array(cb, np.int32).reshape(n, 2),
         contact_point=np.array(cp, np.float64).reshape(n, 3), contact_normal=np.array(cn, np.float64).reshape(n, 3),
         contact_gap=np.array(cg, np.float64), contact_mu=np.array(cm, np.float64), contact_key=np.array(ck, np.int32))
+
+
+class MLP:
+    """The learned warm-start network (device weights; every product on the
+    matrix cores in BF16 with FP32 accumulation)."""
+
+    def __init__(self, n_in, n_out, n_hidden=256, max_batch=4096, seed=0, device="cuda:0"):
+        self.device = torch.device(device)
+        self.n_in, self.n_out, self.n_hidden = int(n_in), int(n_out), int(n_hidden)
+        h = C.c_void_p()
+        _check(lib().kamx_mlp_create(self.n_in, self.n_hidden, self.n_out, int(max_batch), C.c_uint64(seed),
+                                     C.byref(h)))
+        self.handle = h
+        fp, op, n = C.c_int32(), C.c_int32(), C.c_int64()
+        _check(lib().kamx_mlp_info(h, C.byref(fp), C.byref(op), C.byref(n)))
+        self.n_in_pad, self.n_out_pad, self.n_params = fp.value, op.value, n.value
+        self.max_batch = int(max_batch)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().kamx_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _f32(self, a):
+        return torch.as_tensor(a, dtype=torch.float32, device=self.device).contiguous()
+
+    def set_normalization(self, mu_in, sigma_in, mu_out, sigma_out, stream=None):
+        t = [self._f32(a) for a in (mu_in, sigma_in, mu_out, sigma_out)]
+        _check(lib().kamx_mlp_set_normalization(self.handle, *[_ptr(x) for x in t], _stream(stream)))
+        torch.cuda.current_stream(self.device).synchronize()
+
+    def forward(self, x, out=None, stream=None):
+        x = self._f32(x)
+        b = x.shape[0]
+        y = out if out is not None else torch.empty((b, self.n_out), dtype=torch.float32, device=self.device)
+        _check(lib().kamx_mlp_forward(self.handle, _ptr(x), b, _ptr(y), _stream(stream)))
+        return y
+
+    def train_step(self, x, y, lr, loss=None, stream=None):
+        """One Adam step; ``loss`` (a one-element device tensor) receives the
+        loss before the update."""
+        x, y = self._f32(x), self._f32(y)
+        _check(lib().kamx_mlp_train_step(self.handle, _ptr(x), _ptr(y), x.shape[0], float(lr), _ptr(loss),
+                                         _stream(stream)))
+
+    def weights(self):
+        w = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
+        _check(lib().kamx_mlp_weights(self.handle, _ptr(w), 0, _stream(None)))
+        return w
+
+    def set_weights(self, w):
+        w = self._f32(w)
+        _check(lib().kamx_mlp_weights(self.handle, _ptr(w), 1, _stream(None)))
+        torch.cuda.current_stream(self.device).synchronize()
+
+    def gradients(self):
+        g = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
+        _check(lib().kamx_mlp_gradients(self.handle, _ptr(g), _stream(None)))
+        return g

@@ -47,10 +47,12 @@ def world_mass(scene):
     return np.bincount(scene.body_world, weights=scene.body_mass, minlength=scene.n_worlds)
 
 
-def compare_world(scene, params, g, w, replay=True, oracle_over=None):
+def compare_world(scene, params, g, w, replay=True, oracle_over=None, warm=None):
     """Replay world w in the oracle with the GPU's iteration count and
-    restart decisions; return the relative errors of u+, J^T lambda per body
-    and lambda, plus the oracle's FP64 NCP residual of the GPU impulses."""
+    restart decisions (and the same warm-start impulses ``warm``, the
+    world's rows in physical units, when given); return the relative errors
+    of u+, J^T lambda per body and lambda, plus the oracle's FP64 NCP
+    residual of the GPU impulses."""
     sub = g["used_scene"].subset([w])
     qw = None
     b0, b1 = scene.body_offsets()[w], scene.body_offsets()[w + 1]
@@ -61,7 +63,7 @@ def compare_world(scene, params, g, w, replay=True, oracle_over=None):
     P = oracle_params(params, **over)
     log = g["restart_log"][w:w + 1, :max(iters, 1)] if replay and "restart_log" in g else None
     tau = g["torques"][scene.joint_offsets()[w]:scene.joint_offsets()[w + 1]]
-    ref = oracle.step(sub, P, joint_torque=tau, replay_log=log)
+    ref = oracle.step(sub, P, joint_torque=tau, replay_log=log, lambda_ws=warm)
     S = oracle.world_system(sub, P, 0, joint_torque=tau)
     m = S["J"].shape[0]
     r0 = int(g["row_offsets"][w])

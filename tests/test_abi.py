@@ -53,3 +53,8 @@ def test_defaults_and_host_side_validation(libkamx):
     assert rc == kamx.EINVAL
     assert b"sizes" in kamx.lib().kamx_last_error()
     assert kamx.lib().kamx_step(None, 1, None) == kamx.EINVAL
+
+
+def test_schedule_mode_validation(libkamx):
+    from paper_2603_16536_amd import kamx
+    assert kamx.lib().kamx_set_schedule(None, kamx.SCHED_LPT) == kamx.EINVAL

@@ -1,0 +1,252 @@
+"""The warm-start network's matrix-core kernels (through the C ABI) against
+the FP64 reference with the same BF16 rounding points: forward outputs,
+loss, gradients and the Adam update.  The reference rounds the same
+operands to BF16 and accumulates in FP64, so the differences left are the
+FP32 accumulation order and rare one-unit BF16 rounding flips of hidden
+activations; the bar is 2e-3 of each tensor's largest magnitude (the BF16
+unit is 2^-8 = 3.9e-3; a wrong layout, transposed operand or dropped term
+gives errors of order one)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from oracle import mlp as M  # noqa: E402
+from paper_2603_16536_amd import kamx  # noqa: E402
+
+TOL = 2e-3
+
+
+def random_net(rng, n_in, n_hidden, n_out):
+    fp, op = M.pad64(n_in), M.pad64(n_out)
+    W1 = np.zeros((n_hidden, fp))
+    W1[:, :n_in] = rng.uniform(-1, 1, (n_hidden, n_in)) / np.sqrt(n_in)
+    W3 = np.zeros((op, n_hidden))
+    W3[:n_out] = rng.uniform(-1, 1, (n_out, n_hidden)) / np.sqrt(n_hidden)
+    b3 = np.zeros(op)
+    b3[:n_out] = rng.uniform(-0.1, 0.1, n_out)
+    net = M.MLP(n_in, n_hidden, n_out, W1, rng.uniform(-0.1, 0.1, n_hidden),
+                rng.uniform(-1, 1, (n_hidden, n_hidden)) / np.sqrt(n_hidden), rng.uniform(-0.1, 0.1, n_hidden),
+                W3, b3,
+                mu_in=np.r_[rng.normal(0, 1, n_in), np.zeros(fp - n_in)],
+                s_in=np.r_[1.0 / rng.uniform(0.5, 3, n_in), np.ones(fp - n_in)],
+                mu_out=np.r_[rng.normal(0, 1, n_out), np.zeros(op - n_out)],
+                sigma_out=np.r_[rng.uniform(0.5, 2, n_out), np.ones(op - n_out)])
+    # the device keeps FP32 parameters
+    for p in net.params():
+        p[...] = p.astype(np.float32)
+    net.mu_in[:] = net.mu_in.astype(np.float32)
+    net.mu_out[:] = net.mu_out.astype(np.float32)
+    net.sigma_out[:] = net.sigma_out.astype(np.float32)
+    return net
+
+
+def device_net(net, max_batch):
+    d = kamx.MLP(net.n_in, net.n_out, n_hidden=net.n_hidden, max_batch=max_batch, seed=1)
+    assert d.n_in_pad == net.n_in_pad and d.n_out_pad == net.n_out_pad
+    d.set_weights(net.packed().astype(np.float32))
+    sigma_in = (1.0 / net.s_in[:net.n_in]).astype(np.float32)
+    d.set_normalization(net.mu_in[:net.n_in], sigma_in, net.mu_out[:net.n_out], net.sigma_out[:net.n_out])
+    # the reference uses the FP32 scale the device derives from sigma
+    net.s_in[:net.n_in] = (1.0 / sigma_in.astype(np.float32)).astype(np.float32)
+    return d
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-30)
+
+
+@pytest.mark.parametrize("n_in,n_hidden,n_out,batch", [(100, 128, 50, 70), (667, 256, 224, 4096)])
+def test_forward_matches_reference(n_in, n_hidden, n_out, batch):
+    rng = np.random.default_rng(n_in)
+    net = random_net(rng, n_in, n_hidden, n_out)
+    d = device_net(net, batch)
+    x = rng.normal(0, 2, (batch, n_in)).astype(np.float32)
+    y = d.forward(x).cpu().numpy()
+    rows = np.arange(batch) if batch <= 128 else np.r_[0, 1, rng.choice(batch - 2, 62, replace=False) + 2, batch - 1]
+    ref, _ = M.forward(net, x[rows].astype(np.float64), bf16=True)
+    e = rel(y[rows], ref)
+    print(f"\nforward {n_in}-{n_hidden}-{n_hidden}-{n_out}, batch {batch}: max error / max |y| = {e:.2e}")
+    assert e < TOL
+    d.close()
+
+
+def test_gradients_loss_and_adam_match_reference():
+    rng = np.random.default_rng(7)
+    net = random_net(rng, 100, 128, 50)
+    batch = 70
+    d = device_net(net, 128)
+    x = rng.normal(0, 2, (batch, net.n_in)).astype(np.float32)
+    t = (net.mu_out[:50] + net.sigma_out[:50] * rng.normal(0, 1, (batch, 50))).astype(np.float32)
+    loss_dev = torch.zeros(1, dtype=torch.float32, device="cuda")
+    w0 = d.weights().cpu().numpy()
+    lr = 1e-3
+    d.train_step(x, t, lr, loss=loss_dev)
+    g = d.gradients().cpu().numpy()
+    w1 = d.weights().cpu().numpy()
+    loss, grads = M.loss_and_grads(net, x.astype(np.float64), t.astype(np.float64), bf16=True)
+    assert abs(loss_dev.item() - loss) <= 1e-4 * loss
+    k = 0
+    for name, gr in zip(["W1", "b1", "W2", "b2", "W3", "b3"], grads):
+        n = gr.size
+        e = rel(g[k:k + n].reshape(gr.shape), gr)
+        print(f"grad {name}: max error / max |g| = {e:.2e}")
+        assert e < TOL, name
+        k += n
+    # first Adam step: w1 = w0 - lr g / (|g| + eps) elementwise
+    gref = np.concatenate([gr.ravel() for gr in grads])
+    step = w0 - w1
+    big = np.abs(gref) > 0.05 * np.abs(gref).max()
+    expect = lr * gref / (np.abs(gref) + M.ADAM_EPS)
+    assert np.abs(step[big] - expect[big]).max() < 1e-2 * lr
+    assert np.abs(step).max() <= lr * 1.0001
+    d.close()
+
+
+def test_training_fits_a_smooth_map():
+    """Adam on the device drives the loss of a smooth synthetic map down by
+    more than 20x (learning check, not parity)."""
+    rng = np.random.default_rng(11)
+    n_in, n_out, batch = 48, 24, 512
+    A = rng.normal(0, 1, (n_out, n_in)) / np.sqrt(n_in)
+    x = rng.normal(0, 1, (batch, n_in)).astype(np.float32)
+    t = np.tanh(x @ A.T).astype(np.float32)
+    d = kamx.MLP(n_in, n_out, n_hidden=128, max_batch=batch, seed=3)
+    d.set_normalization(np.zeros(n_in), np.ones(n_in), np.zeros(n_out), t.std(axis=0) + 1e-3)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    xs, ts = torch.tensor(x, device="cuda"), torch.tensor(t, device="cuda")
+    d.train_step(xs, ts, 3e-3, loss=loss)
+    first = loss.item()
+    for _ in range(400):
+        d.train_step(xs, ts, 3e-3, loss=loss)
+    print(f"\nloss {first:.3e} -> {loss.item():.3e}")
+    assert loss.item() < first / 20
+    d.close()
+
+
+# ---- the network inside the step -------------------------------------------
+
+from paper_2603_16536_amd import scenes  # noqa: E402
+
+from parity_util import biped_refs, compare_world, gpu_step  # noqa: E402
+
+
+def biped_model(n, params, seed=1002):
+    scene = scenes.round_to_f32(scenes.biped_batch(n, seed=seed))
+    return scene, kamx.Model(scene, params=params, pd=(15.0, 0.6), refs=biped_refs(scene))
+
+
+BIPED = dict(dt=2e-3, eta=1e-4, rho_bilateral=1e-4, rho_contact=0.3, eps=1e-6, max_iters=2000, torque_sigma=5.0,
+             seed=77, contact_margin=0.02)
+
+
+def slots_to_rows(pred, model, scene):
+    """Host mapping of slot values to the rows of the contacts the step used."""
+    raw, cnt = model.contacts()
+    used = kamx.contacts_to_scene(scene, raw, cnt)
+    nj = scene.joint_offsets()
+    ro = model.row_offsets
+    lam = np.zeros(int(ro[-1]), np.float32)
+    co = used.contact_offsets()
+    for w in range(scene.n_worlds):
+        rc0 = 5 * (nj[w + 1] - nj[w])
+        lam[ro[w]:ro[w] + rc0] = pred[w, :rc0]
+        for c in range(co[w], co[w + 1]):
+            k = int(used.contact_key[c])
+            lam[ro[w] + rc0 + 3 * (c - co[w]):ro[w] + rc0 + 3 * (c - co[w]) + 3] = pred[w, rc0 + 3 * k:rc0 + 3 * k + 3]
+    return lam, used
+
+
+def test_features_and_slots_layout():
+    """Features of the coming step against the state, the previous impulses
+    by contact key and the torques the step then applies."""
+    scene, m = biped_model(8, BIPED)
+    nf, ns = m.feature_dims()
+    nb, nj = 31, 40
+    assert ns == 5 * nj + 3 * 8 and nf == 13 * nb + ns + nj
+    m.step(2)
+    x = m.features().cpu().numpy()
+    prev_slots = m.impulse_slots().cpu().numpy()
+    q, u = (t.cpu().numpy() for t in m.state())
+    lam = m.impulses().cpu().numpy()
+    raw, cnt = m.contacts()
+    used = kamx.contacts_to_scene(scene, raw, cnt)
+    m.step(1)
+    tau = m.torques().cpu().numpy()
+    co, ro = used.contact_offsets(), m.row_offsets
+    for w in range(8):
+        b = slice(31 * w, 31 * w + 31)
+        pel = q[31 * w + scene.reset_body[w] - scene.body_offsets()[w], :3] if scene.reset_body[w] >= 0 else 0
+        body = np.concatenate([q[b, :3] - pel, q[b, 3:], u[b]], axis=1).reshape(-1)
+        assert np.array_equal(x[w, :13 * nb], body.astype(np.float32))
+        expect = np.zeros(ns, np.float32)
+        expect[:200] = lam[ro[w]:ro[w] + 200]
+        for c in range(co[w], co[w + 1]):
+            k = int(used.contact_key[c])
+            expect[200 + 3 * k:203 + 3 * k] = lam[ro[w] + 200 + 3 * (c - co[w]):ro[w] + 203 + 3 * (c - co[w])]
+        assert np.array_equal(x[w, 13 * nb:13 * nb + ns], expect)
+        assert np.array_equal(prev_slots[w], expect)
+        assert np.array_equal(x[w, 13 * nb + ns:], tau[40 * w:40 * w + 40])
+    m.close()
+
+
+def test_learned_warm_start_equals_external_and_matches_oracle():
+    """Three models advanced by the same three cold steps (bitwise equal
+    states and step counters).  A steps warm started by the network; C steps
+    cold to reveal the contacts of that step (they depend on the state only);
+    B steps warm started externally with the prediction placed on C's
+    contact rows.  A equals B bitwise, and A's converged state matches the
+    oracle run from the same warm start with A's iteration count and
+    restart decisions."""
+    import torch
+    p = dict(BIPED, log_restarts=1)
+    n = 16
+    scene, A = biped_model(n, p)
+    _, B = biped_model(n, p)
+    _, Cm = biped_model(n, p)
+    for m in (A, B, Cm):
+        m.step(3)
+    nf, ns = A.feature_dims()
+    net = kamx.MLP(nf, ns, n_hidden=256, max_batch=n, seed=5)
+    ys = A.impulse_slots().cpu().numpy()
+    net.set_normalization(np.zeros(nf), np.ones(nf) * 10.0, ys.mean(axis=0), ys.std(axis=0) + 1e-4)
+    pred = net.forward(A.features()).cpu().numpy()
+    q_pre, u_pre = (t.cpu().numpy().astype(np.float64) for t in A.state())
+    A.attach_mlp(net)
+    A.set_params(**dict(p, warmstart=kamx.WARM_LEARNED))
+    A.step(1)
+    Cm.step(1)
+    lam_ws, _ = slots_to_rows(pred, Cm, scene)
+    B.set_params(**dict(p, warmstart=kamx.WARM_EXTERNAL))
+    B.set_warmstart(lam_ws)
+    B.step(1)
+    torch.cuda.synchronize()
+    qa, ua = (t.cpu().numpy() for t in A.state())
+    qb, ub = (t.cpu().numpy() for t in B.state())
+    sa = {k: v.cpu().numpy() for k, v in A.stats().items()}
+    sb = {k: v.cpu().numpy() for k, v in B.stats().items()}
+    assert np.array_equal(qa, qb) and np.array_equal(ua, ub) and np.array_equal(sa["iters"], sb["iters"])
+    # oracle replay of A from the pre-step state and the same warm start
+    raw, cnt = A.contacts()
+    g = dict(q=qa.astype(np.float64), u=ua.astype(np.float64), lam=A.impulses().cpu().numpy().astype(np.float64),
+             row_offsets=A.row_offsets, torques=A.torques().cpu().numpy().astype(np.float64),
+             restart_log=A.restart_log().cpu().numpy(), **sa)
+    pre = scene.replace(q=q_pre, u=u_pre)
+    g["used_scene"] = kamx.contacts_to_scene(pre, raw, cnt)
+    kp = kamx.make_params(**dict(p, warmstart=kamx.WARM_EXTERNAL))
+    errs = []
+    for w in range(n):
+        r0 = int(A.row_offsets[w])
+        errs.append(compare_world(pre, kp, g, w, warm=lam_ws[r0:r0 + int(sa["rows"][w])].astype(np.float64)))
+    e = np.array([[d["e_u"], d["e_imp"]] for d in errs])
+    print(f"\nlearned warm start: iters {sa['iters'].tolist()}; max rel err u+ {e[:, 0].max():.2e} "
+          f"J^T lambda {e[:, 1].max():.2e}")
+    assert e[:, 1].max() < 1e-4 and e[:, 0].max() < 5e-4
+    for m in (A, B, Cm):
+        m.close()
+    net.close()

@@ -188,3 +188,49 @@ def test_worlds_without_contacts_or_joints():
     errs = [compare_world(scene, kp, g, w) for w in range(2)]
     e = report("free box with contacts; limited chain without contacts", errs)
     assert e[:, 0].max() < TOL and e[:, 1].max() < TOL
+
+
+def test_dispatch_order_does_not_change_results():
+    """Three steps of 64 bipeds dispatched longest-first (reordered after
+    every step) and in index order: bitwise identical states and impulses."""
+    scene = scenes.round_to_f32(scenes.biped_batch(64, seed=1002))
+    out = []
+    for mode in (kamx.SCHED_LPT, kamx.SCHED_INDEX):
+        m = kamx.Model(scene, params=cfg2_params(torque_sigma=5.0, seed=99, max_iters=400, log_restarts=0),
+                       pd=(15.0, 0.6), refs=biped_refs(scene))
+        m.set_schedule(mode)
+        m.step(3)
+        q, u = m.state()
+        out.append((q.cpu().numpy(), u.cpu().numpy(), m.impulses().cpu().numpy(), m.stats()["iters"].cpu().numpy()))
+        m.close()
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
+
+
+def test_captured_rollout_equals_single_steps():
+    """kamx_step with nsteps > 1 replays captured graphs.  Three replays of a
+    5-step graph, with host reads and synchronization between them, and one
+    35-step call (a 32-step graph and a 3-step graph) against the same steps
+    enqueued one at a time: bitwise equal states, impulses and iteration
+    counts after every call (the noise key advances inside the graph)."""
+    scene = scenes.round_to_f32(scenes.biped_batch(8, seed=1002))
+    refs = biped_refs(scene)
+    p = cfg2_params(torque_sigma=5.0, seed=4321, max_iters=300, log_restarts=0)
+    graph = kamx.Model(scene, params=p, pd=(15.0, 0.6), refs=refs)
+    eager = kamx.Model(scene, params=p, pd=(15.0, 0.6), refs=refs)
+
+    def snap(m):
+        q, u = m.state()
+        return q.cpu().numpy(), u.cpu().numpy(), m.impulses().cpu().numpy(), m.stats()["iters"].cpu().numpy()
+
+    for n in (5, 5, 5, 35):
+        graph.step(n)
+        for _ in range(n):
+            eager.step(1)
+        a, b = snap(graph), snap(eager)
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y), n
+    torch.cuda.synchronize()
+    assert np.array_equal(graph.torques().cpu().numpy(), eager.torques().cpu().numpy())
+    graph.close()
+    eager.close()
