@@ -137,6 +137,13 @@ typedef struct {
     int32_t key;
 } kamx_contact;
 
+/* Box geometry for generated contacts: half extents along the body axes
+ * (all zero: the body is not a box) and friction coefficient. */
+typedef struct {
+    float half[3];
+    float mu;
+} kamx_box_desc;
+
 /* Solver and step parameters (Alg. 1, Sec. 4.1). */
 typedef struct {
     float dt;
@@ -208,6 +215,23 @@ kamx_status kamx_state_download(kamx_model m, float *q_dev, float *u_dev, kamx_s
  * are pending. */
 kamx_status kamx_contacts_upload(kamx_model m, const kamx_contact *contacts_dev, const int32_t *world_offsets,
                                  kamx_stream stream);
+
+/* Generate the contacts of every following step from box geometry
+ * (boxes [nb], host; copied): vertex-face tests of every box vertex against
+ * a bin made of the floor z = 0 and walls at x = +-half_x, y = +-half_y, and
+ * against the faces of every other box of the world (the vertex must lie
+ * over the face).  A contact (Sec. 3) has the vertex as its point, the face
+ * normal pointing from the face's body (b; -1 for the bin) to the vertex's
+ * body (a), the signed distance as gap, friction min(mu_a, mu_b) (the
+ * box's own mu against the bin) and key ((target * 64 + box) * 8 + vertex)
+ * with targets 0-4 the floor and walls -x, +x, -y, +y and 5 + k the k-th box
+ * of the world.  Candidates with gap below margin are kept, the deepest
+ * first (ties by key), up to max_contacts_per_world.  At most 20 boxes per
+ * world.  Replaces probe and uploaded contacts until kamx_contacts_upload is
+ * called; boxes = NULL turns generation off.  EINVAL on bad geometry or a
+ * model without contact capacity. */
+kamx_status kamx_contacts_box_bin(kamx_model m, const kamx_box_desc *boxes, float half_x, float half_y,
+                                  float margin);
 
 /* External generalized joint forces joint_torque_dev [nj] added to the
  * actuation of every following step; NULL clears them. */

@@ -18,6 +18,9 @@ int bucket_capacity(int rows);
 size_t step_smem_bytes(int mc);
 hipError_t launch_lpt_order(const int32_t *worlds, int n, const int32_t *iters, int32_t *order, hipStream_t stream);
 hipError_t launch_advance_step(uint32_t *ctr, hipStream_t stream);
+hipError_t launch_box_bin(const WorldInfo *worlds, int n_worlds, const float *q, const float *box_geom, float wx,
+                          float wy, float margin, kamx_contact *out, int32_t *count, hipStream_t stream);
+int box_bin_max_boxes();
 hipError_t launch_impulse_slots(const WorldInfo *worlds, int n_worlds, int n_contact_slots, int n_slots,
                                 const float *lambda, const int32_t *keys, const int32_t *ncontacts, float *out,
                                 hipStream_t stream);
@@ -102,10 +105,20 @@ struct kamx_model_s {
     int n_feat = 0, n_slots = 0, n_contact_slots = 0;
     kamx_mlp mlp = nullptr;
     float *d_feat = nullptr, *d_ws = nullptr;
+    // generated contacts (boxes in a bin)
+    bool box_bin = false;
+    float bin_wx = 0.f, bin_wy = 0.f, bin_margin = 0.f;
+    float *d_box_geom = nullptr;
+    kamx_contact *d_gen = nullptr;
+    int32_t *d_gen_count = nullptr;
     // captured multi-step rollouts: graph executables by step count; kernel
     // arguments are baked in, so every setter that changes one clears them
     std::vector<std::pair<int, hipGraphExec_t>> graphs;
     hipStream_t capture_stream = nullptr;
+    // concurrent size buckets: one stream per bucket (default priority)
+    std::vector<hipStream_t> bucket_streams;
+    hipEvent_t ev_fork = nullptr;
+    std::vector<hipEvent_t> ev_join;
 };
 
 static constexpr int kGraphSteps = 32;  // steps per captured graph
@@ -439,6 +452,9 @@ kamx_status kamx_model_destroy(kamx_model m) {
     (void)hipDeviceSynchronize();
     drop_graphs(m);
     if (m->capture_stream) (void)hipStreamDestroy(m->capture_stream);
+    for (hipStream_t st : m->bucket_streams) (void)hipStreamDestroy(st);
+    for (hipEvent_t ev : m->ev_join) (void)hipEventDestroy(ev);
+    if (m->ev_fork) (void)hipEventDestroy(m->ev_fork);
     for (void *p : m->allocations) (void)hipFree(p);
     delete m;
     return KAMX_OK;
@@ -506,8 +522,9 @@ kamx_status kamx_contacts_upload(kamx_model m, const kamx_contact *contacts_dev,
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     HIP_TRY(hipMemcpyAsync(m->d_coff, world_offsets, sizeof(int32_t) * (m->n_worlds + 1), hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));  // world_offsets is a host array of the caller
-    if (m->d_contacts != contacts_dev) drop_graphs(m);
+    if (m->d_contacts != contacts_dev || m->box_bin) drop_graphs(m);
     m->d_contacts = contacts_dev;
+    m->box_bin = false;
     return KAMX_OK;
 }
 
@@ -542,8 +559,9 @@ static StepArgs step_args(kamx_model m) {
     a.ext_tau = m->d_ext;
     a.pbody = m->d_pbody;
     a.pf = m->d_pf;
-    a.contacts = m->d_contacts;
+    a.contacts = m->box_bin ? m->d_gen : m->d_contacts;
     a.coff = m->d_coff;
+    a.ccount = m->box_bin ? m->d_gen_count : nullptr;
     a.lambda = m->d_lambda;
     a.lambda_ext = m->d_lambda_ext;
     a.keys = m->d_keys;
@@ -564,6 +582,20 @@ static StepArgs step_args(kamx_model m) {
     a.ws_slots = m->d_ws;
     a.n_contact_slots = m->n_contact_slots;
     return a;
+}
+
+static kamx_status ensure_bucket_streams(kamx_model m) {
+    if (!m->bucket_streams.empty()) return KAMX_OK;
+    HIP_TRY(hipEventCreateWithFlags(&m->ev_fork, hipEventDisableTiming));
+    for (size_t i = 0; i < m->buckets.size(); ++i) {
+        hipStream_t st = nullptr;
+        HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        m->bucket_streams.push_back(st);
+        hipEvent_t ev = nullptr;
+        HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        m->ev_join.push_back(ev);
+    }
+    return KAMX_OK;
 }
 
 // Feature pass of every bucket (the step kernels stopped after actuation).
@@ -590,19 +622,40 @@ static kamx_status enqueue_steps(kamx_model m, int nsteps, hipStream_t s) {
     const bool lpt = m->schedule == KAMX_SCHED_LPT;
     const bool learned = m->params.warmstart == KAMX_WARM_LEARNED;
     for (int k = 0; k < nsteps; ++k) {
+        if (m->box_bin) {
+            hipError_t e = launch_box_bin(m->d_worlds, m->n_worlds, m->d_q, m->d_box_geom, m->bin_wx, m->bin_wy,
+                                          m->bin_margin, m->d_gen, m->d_gen_count, s);
+            if (e != hipSuccess) return fail(KAMX_EDEVICE, "contact generation launch: %s", hipGetErrorString(e));
+        }
         if (learned) {
             K_TRY(enqueue_features(m, m->d_feat, s));
             K_TRY(mlp_forward_internal(m->mlp, m->d_feat, m->n_worlds, m->d_ws, s));
         }
-        for (const Bucket &b : m->buckets) {
+        // several buckets run concurrently on the model's bucket streams
+        // (fork from s, join back), so the tail of one bucket overlaps the
+        // others; a single bucket runs on s itself
+        const int nbk = (int)m->buckets.size();
+        const bool fork = nbk > 1;
+        if (fork) {
+            K_TRY(ensure_bucket_streams(m));
+            HIP_TRY(hipEventRecord(m->ev_fork, s));
+        }
+        for (int bi = 0; bi < nbk; ++bi) {
+            const Bucket &b = m->buckets[bi];
+            hipStream_t bs = fork ? m->bucket_streams[bi] : s;
+            if (fork) HIP_TRY(hipStreamWaitEvent(bs, m->ev_fork, 0));
             StepArgs a = base;
             a.bucket_worlds = lpt ? b.d_order : b.d_worlds;
             a.n_bucket_worlds = b.n;
-            hipError_t e = launch_step(a, b.mc, b.n, s);
+            hipError_t e = launch_step(a, b.mc, b.n, bs);
             if (e != hipSuccess) return fail(KAMX_EDEVICE, "step launch (bucket %d rows): %s", b.mc, hipGetErrorString(e));
             if (lpt && b.n > 1) {
-                e = launch_lpt_order(b.d_worlds, b.n, m->d_iters, b.d_order, s);
+                e = launch_lpt_order(b.d_worlds, b.n, m->d_iters, b.d_order, bs);
                 if (e != hipSuccess) return fail(KAMX_EDEVICE, "schedule launch (bucket %d rows): %s", b.mc, hipGetErrorString(e));
+            }
+            if (fork) {
+                HIP_TRY(hipEventRecord(m->ev_join[bi], bs));
+                HIP_TRY(hipStreamWaitEvent(s, m->ev_join[bi], 0));
             }
         }
         hipError_t e = launch_advance_step(m->d_step, s);
@@ -705,6 +758,47 @@ kamx_status kamx_model_attach_mlp(kamx_model m, kamx_mlp net) {
         K_TRY(dalloc(m, &m->d_ws, (size_t)m->n_worlds * m->n_slots));
     }
     m->mlp = net;
+    return KAMX_OK;
+}
+
+kamx_status kamx_contacts_box_bin(kamx_model m, const kamx_box_desc *boxes, float half_x, float half_y,
+                                  float margin) {
+    if (!m) return fail(KAMX_EINVAL, "model is NULL");
+    drop_graphs(m);
+    if (!boxes) {
+        m->box_bin = false;
+        return KAMX_OK;
+    }
+    if (!(half_x > 0.f) || !(half_y > 0.f) || !(margin >= 0.f))
+        return fail(KAMX_EINVAL, "bin half widths must be positive and margin >= 0");
+    if (m->max_contacts < 1) return fail(KAMX_EINVAL, "the model has no contact capacity (max_contacts_per_world)");
+    std::vector<float> geom(4 * (size_t)m->nb);
+    std::vector<int> per_world(m->n_worlds, 0);
+    std::vector<WorldInfo> wi(m->n_worlds);
+    HIP_TRY(hipMemcpy(wi.data(), m->d_worlds, sizeof(WorldInfo) * m->n_worlds, hipMemcpyDeviceToHost));
+    for (int w = 0; w < m->n_worlds; ++w)
+        for (int b = wi[w].b0; b < wi[w].b0 + wi[w].nb; ++b) {
+            const kamx_box_desc &d = boxes[b];
+            bool is_box = d.half[0] > 0.f || d.half[1] > 0.f || d.half[2] > 0.f;
+            if (is_box && !(d.half[0] > 0.f && d.half[1] > 0.f && d.half[2] > 0.f && d.mu >= 0.f))
+                return fail(KAMX_EINVAL, "body %d: box half extents must all be positive and mu >= 0", b);
+            for (int e = 0; e < 3; ++e) geom[4 * b + e] = is_box ? d.half[e] : 0.f;
+            geom[4 * b + 3] = is_box ? d.mu : 0.f;
+            per_world[w] += is_box;
+        }
+    const int cap = box_bin_max_boxes();
+    for (int w = 0; w < m->n_worlds; ++w)
+        if (per_world[w] > cap) return fail(KAMX_EINVAL, "world %d: %d boxes (at most %d)", w, per_world[w], cap);
+    if (!m->d_box_geom) {
+        K_TRY(dalloc(m, &m->d_box_geom, 4 * (size_t)m->nb));
+        K_TRY(dalloc(m, &m->d_gen, (size_t)m->n_worlds * kMaxContacts));
+        K_TRY(dalloc(m, &m->d_gen_count, (size_t)m->n_worlds));
+    }
+    HIP_TRY(hipMemcpy(m->d_box_geom, geom.data(), sizeof(float) * geom.size(), hipMemcpyHostToDevice));
+    m->bin_wx = half_x;
+    m->bin_wy = half_y;
+    m->bin_margin = margin;
+    m->box_bin = true;
     return KAMX_OK;
 }
 

@@ -73,6 +73,7 @@ struct StepArgs {
     // explicit contacts
     const kamx_contact *contacts;  // null: use probes
     const int32_t *coff;           // [n_worlds+1]
+    const int32_t *ccount;         // non-null: contacts of world w at w * kMaxContacts, ccount[w] of them
     // outputs and caches
     float *lambda;          // [rows] impulses of the last step (physical)
     const float *lambda_ext;  // [rows] external warm start

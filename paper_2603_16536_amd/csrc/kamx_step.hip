@@ -673,8 +673,8 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
     //      probe order by a wave ballot)
     int *cint = reinterpret_cast<int *>(L.c);
     if (a.contacts) {
-        int c0 = a.coff[w];
-        int n = a.coff[w + 1] - c0;
+        int c0 = a.ccount ? w * kMaxContacts : a.coff[w];
+        int n = a.ccount ? a.ccount[w] : a.coff[w + 1] - c0;
         if (n > W.contact_cap) n = W.contact_cap;
         if (n < 0) n = 0;
         if (tid == 0) s_int[1] = n;

@@ -101,6 +101,7 @@ def lib():
         L.kamx_model_features.argtypes = [vp, vp, vp]
         L.kamx_read_impulse_slots.argtypes = [vp, vp, vp]
         L.kamx_model_attach_mlp.argtypes = [vp, vp]
+        L.kamx_contacts_box_bin.argtypes = [vp, vp, C.c_float, C.c_float, C.c_float]
         L.kamx_read_impulses.argtypes = [vp, vp, vp]
         L.kamx_read_stats.argtypes = [vp, vp, vp, vp, vp, vp]
         L.kamx_read_restart_log.argtypes = [vp, vp, vp]
@@ -115,7 +116,7 @@ def lib():
                      "kamx_read_phase_clock", "kamx_set_schedule", "kamx_mlp_create", "kamx_mlp_destroy",
                      "kamx_mlp_info", "kamx_mlp_set_normalization", "kamx_mlp_forward", "kamx_mlp_train_step",
                      "kamx_mlp_weights", "kamx_mlp_gradients", "kamx_model_feature_dims", "kamx_model_features",
-                     "kamx_read_impulse_slots", "kamx_model_attach_mlp"):
+                     "kamx_read_impulse_slots", "kamx_model_attach_mlp", "kamx_contacts_box_bin"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -189,9 +190,10 @@ class Model:
 
     ``scene``: a scenes.Scene; ``params``: keyword overrides of the library
     defaults; ``max_contacts``: capacity for explicit contacts per world
-    (0 = probe contacts only); ``pd``: optional (kp, kd) for the actuated
-    joints, driven toward their coordinate in the initial pose
-    (``refs`` gives those coordinates; without it ref = 0)."""
+    (0 = probe contacts only); ``pd``: optional (kp, kd) for every actuated
+    joint (without it the scene's per-joint gains apply), driving the joint
+    coordinate toward ``refs`` (default 0, the assembled pose of joints
+    whose frames coincide at assembly)."""
 
     def __init__(self, scene, params=None, max_contacts=0, pd=None, refs=None, device="cuda:0"):
         self.device = torch.device(device)
@@ -214,12 +216,15 @@ class Model:
             joints["limit_hi"][:nj] = scene.joint_limit[:, 1]
             act = scene.joint_actuated.astype(np.int32)
             joints["actuated"][:nj] = act
+            on = act != 0
             if pd is not None:
-                on = act != 0
                 joints["kp"][:nj][on] = float(pd[0])
                 joints["kd"][:nj][on] = float(pd[1])
-                if refs is not None:
-                    joints["ref"][:nj][on] = np.asarray(refs, np.float32)[on]
+            elif scene.joint_pd.shape[0] == nj:
+                joints["kp"][:nj][on] = scene.joint_pd[on, 0]
+                joints["kd"][:nj][on] = scene.joint_pd[on, 1]
+            if refs is not None:
+                joints["ref"][:nj][on] = np.asarray(refs, np.float32)[on]
         probes = np.zeros(max(np_, 1), PROBE_DTYPE)
         if np_:
             probes["world"][:np_] = scene.probe_world
@@ -313,6 +318,19 @@ class Model:
         torch.cuda.current_stream(self.device).synchronize()
 
     # -- stepping ------------------------------------------------------------
+    def contacts_box_bin(self, half=(0.15, 0.15), margin=0.01, boxes=None):
+        """Generate contacts every step from the scene's box geometry
+        (``scene.body_box``: half extents and mu per body) against a bin of
+        the given half widths; ``boxes=False`` turns generation off."""
+        if boxes is False:
+            _check(lib().kamx_contacts_box_bin(self.handle, None, 0.0, 0.0, 0.0))
+            return
+        bx = np.asarray(self.scene.body_box if boxes is None else boxes, np.float32).reshape(-1, 4)
+        assert bx.shape[0] == self.scene.n_bodies
+        arr = np.ascontiguousarray(bx)
+        _check(lib().kamx_contacts_box_bin(self.handle, C.c_void_p(arr.ctypes.data), float(half[0]), float(half[1]),
+                                           float(margin)))
+
     # -- learned warm start --------------------------------------------------
     def feature_dims(self):
         """(n_features, n_slots) of a model whose worlds share one structure."""

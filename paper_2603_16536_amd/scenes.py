@@ -138,6 +138,8 @@ class Scene:
     body_inertia: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))
     q: np.ndarray = field(default_factory=lambda: np.zeros((0, 7)))
     u: np.ndarray = field(default_factory=lambda: np.zeros((0, 6)))
+    # box geometry per body (half extents, friction); zero rows: not a box
+    body_box: np.ndarray = field(default_factory=lambda: np.zeros((0, 4)))
 
     joint_type: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))
     joint_world: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))
@@ -145,6 +147,9 @@ class Scene:
     joint_frame: np.ndarray = field(default_factory=lambda: np.zeros((0, 14)))
     joint_limit: np.ndarray = field(default_factory=lambda: np.zeros((0, 2)))
     joint_actuated: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))
+    # per-joint PD gains (kp, kd) toward the assembled coordinate; used when
+    # the caller gives no global gains
+    joint_pd: np.ndarray = field(default_factory=lambda: np.zeros((0, 2)))
 
     # contact probe points: body-frame points tested against the plane z = 0
     probe_world: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))
@@ -213,6 +218,7 @@ class Scene:
         s.body_inertia = self.body_inertia[b0:b1].copy()
         s.q = self.q[b0:b1].copy()
         s.u = self.u[b0:b1].copy()
+        s.body_box = _box_of(self)[b0:b1].copy()
         j0, j1 = jo[w], jo[w + 1]
         s.joint_type = self.joint_type[j0:j1].copy()
         s.joint_world = np.zeros(j1 - j0, np.int32)
@@ -221,6 +227,7 @@ class Scene:
         s.joint_frame = self.joint_frame[j0:j1].copy()
         s.joint_limit = self.joint_limit[j0:j1].copy()
         s.joint_actuated = self.joint_actuated[j0:j1].copy()
+        s.joint_pd = _pd_of(self)[j0:j1].copy()
         p0, p1 = po[w], po[w + 1]
         s.probe_world = np.zeros(p1 - p0, np.int32)
         s.probe_body = (self.probe_body[p0:p1] - b0).astype(np.int32)
@@ -248,11 +255,19 @@ class Scene:
         return dataclasses.replace(self, **kw)
 
 
+def _box_of(s):
+    return s.body_box if s.body_box.shape[0] == s.n_bodies else np.zeros((s.n_bodies, 4))
+
+
+def _pd_of(s):
+    return s.joint_pd if s.joint_pd.shape[0] == s.n_joints else np.zeros((s.n_joints, 2))
+
+
 def concat(scenes, gravity=None, dt=None, reset_height=None):
     """Stack single- or multi-world scenes into one batch."""
     out = Scene(n_worlds=0)
-    bw, bm, bi, q, u = [], [], [], [], []
-    jt, jw, jb, jf, jl, ja = [], [], [], [], [], []
+    bw, bm, bi, q, u, bx = [], [], [], [], [], []
+    jt, jw, jb, jf, jl, ja, jp = [], [], [], [], [], [], []
     pw, pb, pp, pm = [], [], [], []
     cw, cb, cp, cn, cg, cm, ck = [], [], [], [], [], [], []
     rb = []
@@ -264,12 +279,14 @@ def concat(scenes, gravity=None, dt=None, reset_height=None):
         bi.append(s.body_inertia)
         q.append(s.q)
         u.append(s.u)
+        bx.append(_box_of(s))
         jt.append(s.joint_type)
         jw.append(s.joint_world + nw)
         jb.append(np.where(s.joint_body >= 0, s.joint_body + nb, -1))
         jf.append(s.joint_frame)
         jl.append(s.joint_limit)
         ja.append(s.joint_actuated)
+        jp.append(_pd_of(s))
         pw.append(s.probe_world + nw)
         pb.append(s.probe_body + nb)
         pp.append(s.probe_point)
@@ -293,12 +310,14 @@ def concat(scenes, gravity=None, dt=None, reset_height=None):
     out.body_inertia = np.concatenate(bi).reshape(-1, 3)
     out.q = np.concatenate(q).reshape(-1, 7)
     out.u = np.concatenate(u).reshape(-1, 6)
+    out.body_box = np.concatenate(bx).reshape(-1, 4)
     out.joint_type = np.concatenate(jt).astype(np.int32)
     out.joint_world = np.concatenate(jw).astype(np.int32)
     out.joint_body = np.concatenate(jb).reshape(-1, 2).astype(np.int32)
     out.joint_frame = np.concatenate(jf).reshape(-1, 14)
     out.joint_limit = np.concatenate(jl).reshape(-1, 2)
     out.joint_actuated = np.concatenate(ja).astype(np.int32)
+    out.joint_pd = np.concatenate(jp).reshape(-1, 2)
     out.probe_world = np.concatenate(pw).astype(np.int32)
     out.probe_body = np.concatenate(pb).astype(np.int32)
     out.probe_point = np.concatenate(pp).reshape(-1, 3)
@@ -322,7 +341,7 @@ class _Builder:
 
     def __init__(self):
         self.mass, self.inertia, self.q, self.u = [], [], [], []
-        self.jt, self.jb, self.jf, self.jl, self.ja = [], [], [], [], []
+        self.jt, self.jb, self.jf, self.jl, self.ja, self.jp = [], [], [], [], [], []
         self.pb, self.pp, self.pm = [], [], []
         self.cb, self.cp, self.cn, self.cg, self.cm, self.ck = [], [], [], [], [], []
 
@@ -344,7 +363,7 @@ class _Builder:
         return np.concatenate([p_local, q_local])
 
     def joint(self, jtype, a, b, point_w, axis_w, limit=(np.nan, np.nan), actuated=0,
-              point_b_w=None):
+              point_b_w=None, pd=(0.0, 0.0)):
         """Joint whose frames coincide in the current (assembled) pose: both
         frames sit at ``point_w`` (``point_b_w`` for side b if given) with x
         along ``axis_w``."""
@@ -356,6 +375,7 @@ class _Builder:
         self.jf.append(np.concatenate([fa, fb]))
         self.jl.append(np.asarray(limit, np.float64))
         self.ja.append(int(actuated))
+        self.jp.append(np.asarray(pd, np.float64))
         return len(self.jt) - 1
 
     def probe(self, b, point_local, mu):
@@ -387,6 +407,7 @@ class _Builder:
         s.joint_frame = np.array(self.jf).reshape(-1, 14)
         s.joint_limit = np.array(self.jl).reshape(-1, 2)
         s.joint_actuated = np.array(self.ja, np.int32)
+        s.joint_pd = np.array(self.jp).reshape(-1, 2)
         npb = len(self.pb)
         s.probe_world = np.zeros(npb, np.int32)
         s.probe_body = np.array(self.pb, np.int32)
@@ -541,6 +562,9 @@ def fourbar_batch(n_worlds, seed=1001, with_box=True, dt=1e-3):
 BIPED_FOOT = (0.20, 0.10, 0.04)
 
 
+BIPED_PD = (15.0, 0.6)  # N m / rad, N m s / rad: the DR Legs gains of the paper's RL setup (Sec. 6.3)
+
+
 def biped_world(rng, dt=2e-3, mu=None, link_masses=None):
     """A 31-body biped: pelvis + 2 legs x (hip-yaw, hip-roll, thigh, shin,
     foot) + 2 legs x 5 crank-rod parallelogram transmissions (2 bodies and 3
@@ -566,19 +590,19 @@ def biped_world(rng, dt=2e-3, mu=None, link_masses=None):
     for side in (1.0, -1.0):
         yl = 0.09 * side
         hy = B.body(0.5, box_inertia(0.5, 0.06, 0.06, 0.04), (0.0, yl, H - 0.05), ident)
-        B.joint(REVOLUTE, hy, pelvis, (0.0, yl, H - 0.03), za, actuated=1)
+        B.joint(REVOLUTE, hy, pelvis, (0.0, yl, H - 0.03), za, actuated=1, pd=BIPED_PD)
         hr = B.body(0.5, box_inertia(0.5, 0.06, 0.06, 0.04), (0.0, yl, H - 0.10), ident)
-        B.joint(REVOLUTE, hr, hy, (0.0, yl, H - 0.08), xa, actuated=1)
+        B.joint(REVOLUTE, hr, hy, (0.0, yl, H - 0.08), xa, actuated=1, pd=BIPED_PD)
         Hp = np.array([0.0, yl, hip_z])
         Kn = np.array([0.0, yl, knee_z])
         An = np.array([0.0, yl, ankle_z])
         thigh = _rod_body(B, Hp, Kn, 1.2, width=0.06)
-        B.joint(REVOLUTE, thigh, hr, Hp, ya, actuated=1)
+        B.joint(REVOLUTE, thigh, hr, Hp, ya, actuated=1, pd=BIPED_PD)
         shin = _rod_body(B, Kn, An, 0.8, width=0.05)
-        B.joint(REVOLUTE, shin, thigh, Kn, ya, actuated=1)
+        B.joint(REVOLUTE, shin, thigh, Kn, ya, actuated=1, pd=BIPED_PD)
         fc = np.array([0.02, yl, 0.5 * fz])  # sole on z = 0
         foot = B.body(0.6, box_inertia(0.6, fx, fy, fz), fc, ident)
-        B.joint(REVOLUTE, foot, shin, An, ya, actuated=1)
+        B.joint(REVOLUTE, foot, shin, An, ya, actuated=1, pd=BIPED_PD)
         for ix in (-1, 1):
             for iy in (-1, 1):
                 B.probe(foot, (0.5 * fx * ix, 0.5 * fy * iy, -0.5 * fz), mu)
@@ -616,6 +640,149 @@ def biped_batch(n_worlds, seed=1002, dt=2e-3):
     s.probe_mu = np.repeat(mus, 8)
     s.contact_mu = np.repeat(mus, 8)
     return s
+
+
+def _circle_intersection(c0, r0, c1, r1, side):
+    """A point at distance r0 from c0 and r1 from c1 in the x-z plane
+    (y of c0), on the side of the c0->c1 line given by the sign of side."""
+    c0 = np.asarray(c0, np.float64)
+    c1 = np.asarray(c1, np.float64)
+    d = c1 - c0
+    L = float(np.hypot(d[0], d[2]))
+    if not (abs(r0 - r1) < L < r0 + r1):
+        raise ValueError("circles do not intersect")
+    a = (r0 * r0 - r1 * r1 + L * L) / (2 * L)
+    h = np.sqrt(r0 * r0 - a * a)
+    ex = d / L
+    ez = np.array([-ex[2], 0.0, ex[0]])  # in-plane normal
+    return c0 + a * ex + np.sign(side) * h * ez
+
+
+def excavator_world(rng, dt=2e-3):
+    """A 12-body hydraulic excavator: cab on a swing revolute to the world;
+    boom, stick and bucket on revolute pins; three hydraulic cylinders
+    (barrel and rod on revolute pins, joined by a prismatic joint with a
+    stroke limit); a bucket linkage of two links closing a four-bar with the
+    stick and bucket, the bucket cylinder's rod pinned at the links' common
+    pin.  16 joints (13 revolute, 3 prismatic), 4 kinematic loops, 80
+    bilateral rows + 3 stroke-limit rows.  Masses from 5000 kg (cab) down to
+    0.5 kg (linkage links): mass ratio 1e4.  Geometry jittered by a few per
+    cent per world, assembled exactly (circle intersection for the bucket
+    four-bar).  The swing and the three cylinders hold their assembled
+    coordinates with PD gains."""
+    j = lambda: 1.0 + rng.uniform(-0.04, 0.04)
+    ident = np.array([0.0, 0.0, 0.0, 1.0])
+    ya, za = (0.0, 1.0, 0.0), (0.0, 0.0, 1.0)
+    B = _Builder()
+    cab = B.body(5000.0, box_inertia(5000.0, 3.0, 2.5, 1.5), (0.0, 0.0, 1.55), ident)
+    B.joint(REVOLUTE, cab, -1, (0.0, 0.0, 0.8), za, actuated=1, pd=(2.0e5, 2.0e4))
+    P0 = np.array([0.8 * j(), 0.0, 2.0])           # boom foot pin (on the cab)
+    P1 = P0 + np.array([3.2 * j(), 0.0, 1.6 * j()])  # boom tip / stick pin
+    P2 = P1 + np.array([1.4 * j(), 0.0, -2.4 * j()])  # stick tip / bucket pin
+    P3 = P2 + np.array([0.35, 0.0, -0.65 * j()])      # bucket teeth
+    boom = _rod_body(B, P0, P1, 800.0, width=0.5)
+    stick = _rod_body(B, P1, P2, 400.0, width=0.35)
+    bucket = _rod_body(B, P2, P3, 300.0, width=0.8)
+    B.joint(REVOLUTE, boom, cab, P0, ya)
+    B.joint(REVOLUTE, stick, boom, P1, ya)
+    B.joint(REVOLUTE, bucket, stick, P2, ya)
+    cyls = []
+
+    def cylinder(body0, a, body1, b, m_barrel, m_rod, stroke=0.35):
+        a = np.asarray(a, np.float64)
+        b = np.asarray(b, np.float64)
+        mid = 0.5 * (a + b)
+        barrel = _rod_body(B, a, mid + 0.1 * (b - a), m_barrel, width=0.18)
+        rod = _rod_body(B, mid - 0.1 * (b - a), b, m_rod, width=0.10)
+        B.joint(REVOLUTE, barrel, body0, a, ya)
+        B.joint(REVOLUTE, rod, body1, b, ya)
+        # slide coordinate measured from the assembled stroke
+        cyls.append(B.joint(PRISMATIC, rod, barrel, mid, b - a, limit=(-stroke, stroke), actuated=1,
+                            pd=(4.0e6, 2.0e5)))
+        return barrel, rod
+
+    # boom cylinder: cab -> boom; stick cylinder: boom -> stick
+    cylinder(cab, (1.3 * j(), 0.0, 1.2), boom, P0 + 0.45 * (P1 - P0) + np.array([0.0, 0.0, -0.25]), 60.0, 30.0)
+    cylinder(boom, P0 + 0.7 * (P1 - P0) + np.array([0.0, 0.0, 0.45]), stick,
+             P1 + np.array([-0.35, 0.0, 0.45]), 40.0, 20.0)
+    # bucket linkage: link1 pinned to the stick, link2 pinned to the bucket,
+    # joined at J; the bucket cylinder pushes on J
+    L1 = P2 + 0.22 * (P1 - P2) + np.array([0.12, 0.0, 0.0])
+    K = P2 + np.array([0.28, 0.0, -0.08])
+    Jp = _circle_intersection(L1, 0.45 * j(), K, 0.42 * j(), side=1.0)
+    link1 = _rod_body(B, L1, Jp, 0.5, width=0.06)
+    link2 = _rod_body(B, Jp, K, 0.5, width=0.06)
+    cylinder(stick, P1 + 0.3 * (P2 - P1) + np.array([0.25, 0.0, 0.1]), link1, Jp, 20.0, 10.0)
+    B.joint(REVOLUTE, link1, stick, L1, ya)
+    B.joint(REVOLUTE, link2, link1, Jp, ya)
+    B.joint(REVOLUTE, link2, bucket, K, ya)
+    return B.scene(dt, reset_body=-1)
+
+
+def excavator_batch(n_worlds, seed=1003, dt=2e-3):
+    rng = np.random.default_rng(seed)
+    return concat([excavator_world(rng, dt) for _ in range(n_worlds)])
+
+
+def heterogeneous_batch(n_worlds, seed=1003, dt=2e-3):
+    """An equal mix of four-bars (with the sliding box), bipeds and
+    excavators, interleaved world by world (four-bar, biped, excavator, ...)."""
+    rng = np.random.default_rng(seed)
+    n_f = (n_worlds + 2) // 3
+    n_b = (n_worlds + 1) // 3
+    n_e = n_worlds // 3
+    fb = fourbar_batch(n_f, seed=int(rng.integers(1 << 30)), dt=dt)
+    bp = biped_batch(n_b, seed=int(rng.integers(1 << 30)), dt=dt)
+    ex = excavator_batch(n_e, seed=int(rng.integers(1 << 30)), dt=dt)
+    parts = []
+    for k in range(n_f):
+        parts.append(fb._one(k))
+        if k < n_b:
+            parts.append(bp._one(k))
+        if k < n_e:
+            parts.append(ex._one(k))
+    return concat(parts, dt=dt, reset_height=0.2)
+
+
+BIN_HALF = (0.15, 0.15)  # 0.3 m x 0.3 m bin (walls 0.3 m high)
+
+
+def box_bin_world(rng, n_boxes=20, dt=2e-3, half=BIN_HALF):
+    """``n_boxes`` free boxes above a bin: sides U[0.02, 0.1] m, density
+    U[100, 5000] kg/m^3 (mass ratio up to ~6e3), friction U[0.3, 1.0], random
+    orientation, at rest.  Boxes are dropped one by one at a random (x, y)
+    that keeps their axis-aligned bounds inside the walls, just above every
+    earlier box whose bounds overlap in x-y (so nothing starts in contact).
+    No joints; contacts come from box-in-bin generation each step."""
+    B = _Builder()
+    placed = []  # (lo, hi) bounds
+    box = []
+    for _ in range(n_boxes):
+        side = rng.uniform(0.02, 0.1, 3)
+        h = 0.5 * side
+        rho = rng.uniform(100.0, 5000.0)
+        m = rho * side.prod()
+        q = random_quat(rng)
+        R = quat_to_mat(q)
+        ext = np.abs(R) @ h
+        x = rng.uniform(-half[0] + ext[0] + 1e-3, half[0] - ext[0] - 1e-3)
+        y = rng.uniform(-half[1] + ext[1] + 1e-3, half[1] - ext[1] - 1e-3)
+        z = ext[2] + 0.005
+        for lo, hi in placed:
+            if lo[0] < x + ext[0] and x - ext[0] < hi[0] and lo[1] < y + ext[1] and y - ext[1] < hi[1]:
+                z = max(z, hi[2] + ext[2] + 0.005)
+        c = np.array([x, y, z])
+        placed.append((c - ext, c + ext))
+        B.body(m, box_inertia(m, *side), c, q)
+        box.append(np.r_[h, rng.uniform(0.3, 1.0)])
+    s = B.scene(dt)
+    s.body_box = np.array(box)
+    return s
+
+
+def box_bin_batch(n_worlds, seed=1005, n_boxes=20, dt=2e-3):
+    rng = np.random.default_rng(seed)
+    return concat([box_bin_world(rng, n_boxes, dt) for _ in range(n_worlds)])
 
 
 def perturb_state(scene, rng, v_scale=0.2, w_scale=0.5):

@@ -16,8 +16,9 @@ def oracle_params(p: "kamx.kamx_params", **over):
 
 
 def gpu_step(scene, params, explicit_contacts=True, ext=None, max_contacts=None, warm=None):
-    """One step of every world on the GPU.  Returns numpy outputs and the
-    scene with the contacts the library actually used."""
+    """One step of every world on the GPU.  Returns numpy outputs, the
+    contacts the library used (for checking its own contact generation) and
+    the inputs the oracle needs to rebuild the step on its side."""
     import torch
 
     mc = max_contacts if max_contacts is not None else (
@@ -39,22 +40,69 @@ def gpu_step(scene, params, explicit_contacts=True, ext=None, max_contacts=None,
         out["restart_log"] = model.restart_log().cpu().numpy()
     raw, cnt = model.contacts()
     out["used_scene"] = kamx.contacts_to_scene(scene, raw, cnt)
+    out["inputs"] = dict(ext=None if ext is None else np.asarray(ext, np.float64), explicit=explicit_contacts,
+                         step=0, pd=None, refs=None)
     model.close()
     return out
+
+
+def oracle_torques(scene, params, w, ext=None, step=0, pd=None, refs=None):
+    """Generalized joint forces of world w computed on the oracle side: the
+    external forces, PD toward refs (per-joint gains of the scene unless pd
+    is given) on the actuated joints, and sigma N(0, 1) noise from the
+    Philox4x32-10 / Box-Muller definition keyed by (seed; world, step, joint
+    slot)."""
+    jo = scene.joint_offsets()
+    j0, j1 = jo[w], jo[w + 1]
+    tau = np.zeros(j1 - j0)
+    if ext is not None:
+        tau += np.asarray(ext, np.float64)[j0:j1]
+    gains = scene.joint_pd if scene.joint_pd.shape[0] == scene.n_joints else np.zeros((scene.n_joints, 2))
+    sigma = float(params.torque_sigma)
+    for j in range(j0, j1):
+        if not scene.joint_actuated[j]:
+            continue
+        kp, kd = (float(pd[0]), float(pd[1])) if pd is not None else (gains[j, 0], gains[j, 1])
+        if kp != 0.0 or kd != 0.0:
+            c, Ja, Jb = oracle.joint_coordinate(scene, scene.q, j)
+            a, b = scene.joint_body[j]
+            rate = Ja @ scene.u[a] + (Jb @ scene.u[b] if b >= 0 else 0.0)
+            ref = 0.0 if refs is None else float(np.float32(refs[j]))
+            tau[j - j0] += kp * (ref - c) - kd * rate
+        if sigma != 0.0:
+            u1, u2 = scenes.philox_normal_pair(int(params.seed), np.array([w]), step, np.array([j - j0]))
+            tau[j - j0] += sigma * np.sqrt(-2.0 * np.log(float(u1[0]))) * np.cos(2 * np.pi * float(u2[0]))
+    return tau
 
 
 def world_mass(scene):
     return np.bincount(scene.body_world, weights=scene.body_mass, minlength=scene.n_worlds)
 
 
-def compare_world(scene, params, g, w, replay=True, oracle_over=None, warm=None):
+def compare_world(scene, params, g, w, replay=True, oracle_over=None, warm=None, inputs=None):
     """Replay world w in the oracle with the GPU's iteration count and
     restart decisions (and the same warm-start impulses ``warm``, the
     world's rows in physical units, when given); return the relative errors
     of u+, J^T lambda per body and lambda, plus the oracle's FP64 NCP
-    residual of the GPU impulses."""
-    sub = g["used_scene"].subset([w])
-    qw = None
+    residual of the GPU impulses.  The oracle builds its own contacts and
+    joint forces from the pre-step state in ``scene`` (``inputs`` describes
+    what the GPU was given); the contacts the GPU generated must match
+    them key for key."""
+    import oracle.contacts as OC
+    inp = dict(g.get("inputs") or {})
+    inp.update(inputs or {})
+    if inp.get("explicit", True):
+        csc = scene
+    else:
+        csc = OC.probe_contacts(scene, scene.q, float(params.contact_margin))
+    sub = csc.subset([w])
+    gsub = g["used_scene"].subset([w])
+    assert np.array_equal(np.sort(gsub.contact_key), np.sort(sub.contact_key)), "contact sets differ"
+    # the GPU's contact order (by key) mapped onto the oracle's
+    g_of_key = {int(k): i for i, k in enumerate(gsub.contact_key)}
+    cperm = [g_of_key[int(k)] for k in sub.contact_key]
+    tau = oracle_torques(scene, params, w, ext=inp.get("ext"), step=inp.get("step", 0), pd=inp.get("pd"),
+                         refs=inp.get("refs"))
     b0, b1 = scene.body_offsets()[w], scene.body_offsets()[w + 1]
     iters = int(g["iters"][w])
     over = dict(oracle_over or {})
@@ -62,13 +110,16 @@ def compare_world(scene, params, g, w, replay=True, oracle_over=None, warm=None)
         over["fixed_iters"] = max(iters, 1)
     P = oracle_params(params, **over)
     log = g["restart_log"][w:w + 1, :max(iters, 1)] if replay and "restart_log" in g else None
-    tau = g["torques"][scene.joint_offsets()[w]:scene.joint_offsets()[w + 1]]
     ref = oracle.step(sub, P, joint_torque=tau, replay_log=log, lambda_ws=warm)
     S = oracle.world_system(sub, P, 0, joint_torque=tau)
     m = S["J"].shape[0]
     r0 = int(g["row_offsets"][w])
-    lam_g = g["lam"][r0:r0 + m]
+    lam_raw = g["lam"][r0:r0 + m]
     assert np.all(g["lam"][r0 + m:int(g["row_offsets"][w + 1])] == 0.0)
+    rc0 = m - 3 * len(cperm)
+    lam_g = lam_raw.copy()
+    for i, gi in enumerate(cperm):
+        lam_g[rc0 + 3 * i:rc0 + 3 * i + 3] = lam_raw[rc0 + 3 * gi:rc0 + 3 * gi + 3]
     floor_imp = 1e-6 * world_mass(scene)[w] * 9.81 * params.dt
     floor_vel = 1e-6 * 9.81 * params.dt
     u_g = g["u"][b0:b1].reshape(-1)

@@ -195,58 +195,98 @@ def test_features_and_slots_layout():
     m.close()
 
 
+def oracle_features(scene, params, w, refs):
+    """Features of world w at the scene's state before its first step, on
+    the oracle side: body state relative to the reset body, zero previous
+    impulses, the step's joint forces."""
+    from parity_util import oracle_torques
+    bo = scene.body_offsets()
+    b0, b1 = bo[w], bo[w + 1]
+    root = scene.q[scene.reset_body[w], :3]
+    body = np.concatenate([scene.q[b0:b1, :3] - root, scene.q[b0:b1, 3:], scene.u[b0:b1]], axis=1).reshape(-1)
+    tau = oracle_torques(scene, params, w, step=0, pd=(15.0, 0.6), refs=refs)
+    nj = len(tau)
+    n_slots = 5 * nj + 3 * 8
+    return np.concatenate([body, np.zeros(n_slots), tau])
+
+
 def test_learned_warm_start_equals_external_and_matches_oracle():
-    """Three models advanced by the same three cold steps (bitwise equal
-    states and step counters).  A steps warm started by the network; C steps
-    cold to reveal the contacts of that step (they depend on the state only);
-    B steps warm started externally with the prediction placed on C's
-    contact rows.  A equals B bitwise, and A's converged state matches the
-    oracle run from the same warm start with A's iteration count and
-    restart decisions."""
+    """Four fresh models of the same batch.  A steps warm started by its
+    network; B externally with the network's device prediction placed on the
+    rows (C, a cold step, reveals the contact order): A equals B bitwise.
+    The oracle computes the features and the prediction itself (FP64 with
+    the same BF16 rounding points, same weights); D steps externally warm
+    started from that prediction and matches the oracle run from it (same
+    iteration count and restart decisions).  The device prediction agrees
+    with the oracle's within the network bar."""
     import torch
+    import oracle.contacts as OC
     p = dict(BIPED, log_restarts=1)
     n = 16
     scene, A = biped_model(n, p)
     _, B = biped_model(n, p)
     _, Cm = biped_model(n, p)
-    for m in (A, B, Cm):
-        m.step(3)
+    _, D = biped_model(n, p)
+    refs = biped_refs(scene)
     nf, ns = A.feature_dims()
-    net = kamx.MLP(nf, ns, n_hidden=256, max_batch=n, seed=5)
-    ys = A.impulse_slots().cpu().numpy()
-    net.set_normalization(np.zeros(nf), np.ones(nf) * 10.0, ys.mean(axis=0), ys.std(axis=0) + 1e-4)
-    pred = net.forward(A.features()).cpu().numpy()
-    q_pre, u_pre = (t.cpu().numpy().astype(np.float64) for t in A.state())
+    rng = np.random.default_rng(31)
+    ref_net = random_net(rng, nf, 256, ns)
+    ref_net.mu_in[:] = 0.0
+    ref_net.s_in[:] = 1.0
+    ref_net.mu_out[:] = 0.0
+    ref_net.sigma_out[:] = 0.02
+    net = device_net(ref_net, n)
+    # device prediction and the learned step
+    pred_dev = net.forward(A.features()).cpu().numpy()
     A.attach_mlp(net)
     A.set_params(**dict(p, warmstart=kamx.WARM_LEARNED))
     A.step(1)
     Cm.step(1)
-    lam_ws, _ = slots_to_rows(pred, Cm, scene)
+    lam_dev, _ = slots_to_rows(pred_dev, Cm, scene)
     B.set_params(**dict(p, warmstart=kamx.WARM_EXTERNAL))
-    B.set_warmstart(lam_ws)
+    B.set_warmstart(lam_dev)
     B.step(1)
     torch.cuda.synchronize()
     qa, ua = (t.cpu().numpy() for t in A.state())
     qb, ub = (t.cpu().numpy() for t in B.state())
-    sa = {k: v.cpu().numpy() for k, v in A.stats().items()}
-    sb = {k: v.cpu().numpy() for k, v in B.stats().items()}
-    assert np.array_equal(qa, qb) and np.array_equal(ua, ub) and np.array_equal(sa["iters"], sb["iters"])
-    # oracle replay of A from the pre-step state and the same warm start
-    raw, cnt = A.contacts()
-    g = dict(q=qa.astype(np.float64), u=ua.astype(np.float64), lam=A.impulses().cpu().numpy().astype(np.float64),
-             row_offsets=A.row_offsets, torques=A.torques().cpu().numpy().astype(np.float64),
-             restart_log=A.restart_log().cpu().numpy(), **sa)
-    pre = scene.replace(q=q_pre, u=u_pre)
-    g["used_scene"] = kamx.contacts_to_scene(pre, raw, cnt)
+    assert np.array_equal(qa, qb) and np.array_equal(ua, ub)
+    assert np.array_equal(A.stats()["iters"].cpu().numpy(), B.stats()["iters"].cpu().numpy())
+    # oracle-side features, prediction and warm start
     kp = kamx.make_params(**dict(p, warmstart=kamx.WARM_EXTERNAL))
+    X = np.stack([oracle_features(scene, kp, w, refs) for w in range(n)])
+    pred_orc, _ = M.forward(ref_net, X, bf16=True)
+    e_pred = rel(pred_dev, pred_orc)
+    print(f"\ndevice vs oracle prediction: {e_pred:.2e}")
+    assert e_pred < TOL
+    csc = OC.probe_contacts(scene, scene.q, float(kp.contact_margin))
+    co = csc.contact_offsets()
+    ro = A.row_offsets
+    lam_orc = np.zeros(int(ro[-1]))
+    for w in range(n):
+        lam_orc[ro[w]:ro[w] + 200] = pred_orc[w, :200]
+        for c in range(co[w], co[w + 1]):
+            k = int(csc.contact_key[c])
+            r = ro[w] + 200 + 3 * (c - co[w])
+            lam_orc[r:r + 3] = pred_orc[w, 200 + 3 * k:203 + 3 * k]
+    D.set_params(**dict(p, warmstart=kamx.WARM_EXTERNAL))
+    D.set_warmstart(lam_orc.astype(np.float32))
+    D.step(1)
+    torch.cuda.synchronize()
+    raw, cnt = D.contacts()
+    sd = {k: v.cpu().numpy() for k, v in D.stats().items()}
+    g = dict(u=D.state()[1].cpu().numpy().astype(np.float64), lam=D.impulses().cpu().numpy().astype(np.float64),
+             row_offsets=ro, restart_log=D.restart_log().cpu().numpy(),
+             used_scene=kamx.contacts_to_scene(scene, raw, cnt),
+             inputs=dict(explicit=False, step=0, ext=None, pd=(15.0, 0.6), refs=refs), **sd)
     errs = []
     for w in range(n):
-        r0 = int(A.row_offsets[w])
-        errs.append(compare_world(pre, kp, g, w, warm=lam_ws[r0:r0 + int(sa["rows"][w])].astype(np.float64)))
+        r0 = int(ro[w])
+        warm = lam_orc[r0:r0 + int(sd["rows"][w])].astype(np.float32).astype(np.float64)
+        errs.append(compare_world(scene, kp, g, w, warm=warm))
     e = np.array([[d["e_u"], d["e_imp"]] for d in errs])
-    print(f"\nlearned warm start: iters {sa['iters'].tolist()}; max rel err u+ {e[:, 0].max():.2e} "
+    print(f"learned-style warm start: iters {sd['iters'].tolist()}; max rel err u+ {e[:, 0].max():.2e} "
           f"J^T lambda {e[:, 1].max():.2e}")
     assert e[:, 1].max() < 1e-4 and e[:, 0].max() < 5e-4
-    for m in (A, B, Cm):
+    for m in (A, B, Cm, D):
         m.close()
     net.close()

@@ -234,3 +234,46 @@ def test_captured_rollout_equals_single_steps():
     assert np.array_equal(graph.torques().cpu().numpy(), eager.torques().cpu().numpy())
     graph.close()
     eager.close()
+
+
+def test_excavator_hydraulic_linkage_replayed():
+    """The 12-body excavator (4 loops, 3 prismatic cylinders with stroke
+    limits, mass ratio 1e4) with random twists and cylinder forces: u+ and
+    J^T lambda per body within 1e-4 of the oracle replay."""
+    rng = np.random.default_rng(21)
+    scene = scenes.round_to_f32(scenes.excavator_batch(8, seed=1003))
+    scene = scenes.perturb_state(scene, rng, 0.05, 0.05)
+    scene.u = scene.u.astype(np.float32).astype(np.float64)
+    tau = np.zeros(scene.n_joints)
+    act = scene.joint_actuated.astype(bool)
+    tau[act] = rng.normal(0.0, 2000.0, act.sum())
+    g = gpu_step(scene, cfg2_params(), ext=tau.astype(np.float32))
+    params = kamx.make_params(**cfg2_params())
+    assert np.all(g["rows"] == 83)
+    errs = [compare_world(scene, params, g, w) for w in range(8)]
+    e = report(f"excavator 8 worlds, iters {g['iters'].tolist()}", errs)
+    assert e[:, 0].max() < TOL and e[:, 1].max() < TOL
+
+
+def test_three_structures_in_one_call_equal_separate_calls():
+    """Four-bars, bipeds and excavators interleaved in one model (three size
+    buckets running concurrently) step bitwise like three separate models."""
+    mixed = scenes.round_to_f32(scenes.heterogeneous_batch(9, seed=5))
+    kinds = ["f", "b", "e"] * 3
+    parts = {k: [w for w in range(9) if kinds[w] == k] for k in "fbe"}
+    p = cfg2_params(max_iters=300, torque_sigma=3.0, seed=8)
+    gm = gpu_step(mixed, p, explicit_contacts=False)
+    bo = mixed.body_offsets()
+    for k, ws in parts.items():
+        sub = mixed.subset(ws)
+        # noise is keyed by the world index: the separate model gets the
+        # mixed model's applied joint forces (PD + noise) as external forces,
+        # with its own PD and noise off
+        sub = sub.replace(joint_pd=np.zeros_like(sub.joint_pd))
+        gs = gpu_step(sub, dict(p, torque_sigma=0.0), explicit_contacts=False,
+                      ext=gm["torques"][np.concatenate([np.arange(mixed.joint_offsets()[w],
+                                                                  mixed.joint_offsets()[w + 1]) for w in ws])].astype(np.float32))
+        so = sub.body_offsets()
+        for i, w in enumerate(ws):
+            assert np.array_equal(gm["u"][bo[w]:bo[w + 1]], gs["u"][so[i]:so[i + 1]]), (k, w)
+            assert gm["iters"][w] == gs["iters"][i]

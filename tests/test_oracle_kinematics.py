@@ -181,3 +181,31 @@ def test_fourbar_geometry_satisfies_freudenstein():
         lhs = (d / a) * math.cos(th4) - (d / c) * math.cos(th2) + (a * a - b * b + c * c + d * d) / (2 * a * c)
         assert abs(lhs - math.cos(th2 - th4)) < 1e-12
         assert abs(th2 - g["th2"]) < 1e-12
+
+
+def test_excavator_assembly_and_mobility(orc):
+    """The hydraulic excavator is assembled on the manifold; its four planar
+    loops leave 80 - 12 = 68 independent bilateral rows, i.e. four degrees
+    of freedom (swing and the three cylinder strokes, Gruebler count
+    72 - 68); the three stroke-limit rows sit at the nearer bound, 0.35 m
+    away, and with them the mechanism keeps only the swing."""
+    ex = scenes.excavator_batch(4, seed=9)
+    assert ex.n_bodies == 48 and ex.n_joints == 64
+    for w in range(4):
+        S = orc.world_system(ex, orc.Params(dt=2e-3), w)
+        bil = S["kind"] == orc.ROW_BILATERAL
+        assert S["J"].shape == (83, 72) and bil.sum() == 80
+        assert np.abs(S["f"][bil]).max() < 1e-12
+        assert np.linalg.matrix_rank(S["J"][bil], tol=1e-9) == 68
+        assert np.allclose(S["f"][S["kind"] == orc.ROW_LIMIT], 0.35, atol=1e-12)
+        assert np.linalg.matrix_rank(S["J"], tol=1e-9) == 71
+    m = ex.body_mass[:12]
+    assert m.max() / m.min() == pytest.approx(1e4)
+
+
+def test_heterogeneous_batch_interleaves_three_structures():
+    h = scenes.heterogeneous_batch(7, seed=3)
+    nb = np.diff(h.body_offsets())
+    assert nb.tolist() == [4, 31, 12, 4, 31, 12, 4]
+    nj = np.diff(h.joint_offsets())
+    assert nj.tolist() == [4, 40, 16, 4, 40, 16, 4]
