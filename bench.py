@@ -31,6 +31,14 @@ def biped_workload(n_worlds, seed=1002):
 CFG2 = dict(dt=2e-3, eta=1e-4, rho_bilateral=1e-4, rho_contact=0.3, eps=1e-6, max_iters=2000,
             baumgarte=0.2, contact_margin=0.02, torque_sigma=5.0, seed=1002, reset_height=0.2)
 PD = (15.0, 0.6)   # the paper's DR Legs gains (N m / rad, N m s / rad)
+WORKLOADS = {
+    "biped": "biped-{n}: 31 bodies, 40 revolute joints (10 closed loops), 8 sole probes, dt 2 ms, cold-start "
+             "PADMM to 1e-6 (cap 2000), PD + N(0,5 N m) torques",
+    "hetero": "heterogeneous-{n}: four-bar (32 rows), biped (224 rows) and excavator (83 rows) interleaved, three "
+              "concurrent size buckets, dt 2 ms, PADMM to 1e-6 (cap 200)",
+    "boxbin": "box-bin-{n}: 20 boxes per world falling into a 0.3 m bin, vertex-face contacts generated every "
+              "step (at most 64, 192 rows), dt 2 ms, PADMM to 1e-6 (cap 200)",
+}
 TRAIN_SEED = 2002  # noise seed of the rollout that feeds training (the timed rollouts use CFG2's)
 
 
@@ -60,16 +68,53 @@ def algorithmic_flops(rows, iters, sum_kb2):
     return m ** 3 / 3.0 + k * (2 * m * m + 30 * m) + 12.0 * sum_kb2 + 2 * m * m
 
 
-def run_gpu(n_worlds, steps, warmup, warmstart, schedule, net=None, seed=None):
-    import torch
-    from paper_2603_16536_amd import kamx
+def measured_traffic():
+    """HBM bytes per step-kernel launch from the committed rocprofv3 FETCH_SIZE
+    and WRITE_SIZE runs (scaled by a plain copy of known size), or None when
+    the kernel source has changed since they were taken."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    rec = os.path.join(here, "profiles", "step_kernel_biped4096_traffic.txt")
+    src = os.path.join(here, "paper_2603_16536_amd", "csrc", "kamx_step.hip")
+    if not (os.path.exists(rec) and os.path.exists(src)):
+        return None
+    kv = dict(line.split(": ", 1) for line in open(rec).read().splitlines() if ": " in line)
+    if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != kv.get("kernel_sha256_prefix"):
+        return None
+    return int(kv["fetch_bytes_per_launch"]) + int(kv["write_bytes_per_launch"])
 
-    scene = biped_workload(n_worlds)
+
+def make_model(workload, n_worlds, warmstart, schedule, seed=None):
+    """The benchmark model of a workload: the biped batch (headline), the
+    heterogeneous mix of four-bars, bipeds and excavators, or boxes in a bin
+    with contacts generated every step."""
+    from paper_2603_16536_amd import kamx, scenes
+
     params = dict(CFG2, warmstart=warmstart)
     if seed is not None:
         params["seed"] = seed
-    model = kamx.Model(scene, params=params, pd=PD, refs=np.zeros(scene.n_joints))
+    if workload == "biped":
+        scene = biped_workload(n_worlds)
+        model = kamx.Model(scene, params=params, pd=PD, refs=np.zeros(scene.n_joints))
+    elif workload == "hetero":
+        scene = scenes.round_to_f32(scenes.heterogeneous_batch(n_worlds, seed=1003))
+        # per-joint gains of each structure; a 200-iteration budget (the
+        # excavator's rounded loops keep a residual floor above 1e-6)
+        model = kamx.Model(scene, params=dict(params, max_iters=200))
+    elif workload == "boxbin":
+        scene = scenes.round_to_f32(scenes.box_bin_batch(n_worlds, seed=1005))
+        model = kamx.Model(scene, params=dict(params, torque_sigma=0.0, max_iters=200), max_contacts=64)
+        model.contacts_box_bin(scenes.BIN_HALF, 0.01)
+    else:
+        raise ValueError(workload)
     model.set_schedule(schedule)
+    return scene, model
+
+
+def run_gpu(n_worlds, steps, warmup, warmstart, schedule, net=None, seed=None, workload="biped"):
+    import torch
+
+    scene, model = make_model(workload, n_worlds, warmstart, schedule, seed)
     if net is not None:
         model.attach_mlp(net)
     stream = torch.cuda.current_stream()
@@ -95,7 +140,7 @@ def run_gpu(n_worlds, steps, warmup, warmstart, schedule, net=None, seed=None):
     out = dict(
         wall_s=t1 - t0, kernel_ms=kernel_ms, iters=iters.cpu().numpy(), rows=rows.cpu().numpy(),
         status=status.cpu().numpy(), resets=model.reset_count() - resets0, buckets=model.n_buckets,
-        sum_kb2=incidence_sq(scene),
+        sum_kb2=incidence_sq(scene) if workload == "biped" else 0.0,
     )
     model.close()
     return out
@@ -171,6 +216,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-previous", action="store_true", help="skip the previous-step warm-start run")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start run")
+    ap.add_argument("--workload", choices=tuple(WORKLOADS), default="biped",
+                    help="biped (headline), hetero (four-bar/biped/excavator mix) or boxbin")
     ap.add_argument("--train-steps", type=int, default=250, help="steps of the cold rollout that feeds training")
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--schedule", choices=("lpt", "index"), default="lpt",
@@ -193,7 +240,10 @@ def main():
     print(f"[bench] cold-start rollout: {args.worlds} worlds, warmup {args.warmup}, steps {args.steps}",
           file=sys.stderr, flush=True)
     sched = kamx.SCHED_LPT if args.schedule == "lpt" else kamx.SCHED_INDEX
-    cold = run_gpu(args.worlds, args.steps, args.warmup, kamx.WARM_COLD, sched)
+    if args.workload != "biped":
+        args.no_learned = True
+        args.no_cpu = True
+    cold = run_gpu(args.worlds, args.steps, args.warmup, kamx.WARM_COLD, sched, workload=args.workload)
     value = args.worlds * args.steps / cold["wall_s"]
     it = cold["iters"]
     conv = float((cold["status"] == 0).mean())
@@ -213,14 +263,14 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "biped-4096: 31 bodies, 40 revolute joints (10 closed loops), 8 sole probes, "
-                               "dt 2 ms, cold-start PADMM to 1e-6 (cap 2000), PD + N(0,5 N m) torques",
+        "config": {"workload": WORKLOADS[args.workload].format(n=args.worlds),
                    "worlds": args.worlds, "rows_per_world_max": int(cold["rows"].max()),
                    "warm_start": "cold (plain ADMM)",
                    "dispatch": "longest previous solve first" if args.schedule == "lpt" else "world index"},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VALU_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 5), "traffic": None,
-                     "kernel": "step_kernel<224,512,2>",
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 5),
+                     "traffic": measured_traffic() if args.workload == "biped" and args.worlds == 4096 else None,
+                     "kernel": "step_kernel<224,512,2>" if args.workload == "biped" else "all step kernels",
                      "avg_launch_ms": round(float(cold["kernel_ms"].mean()), 4)},
         "solver": {"iters_mean": round(float(it.mean()), 1), "iters_p50": float(np.percentile(it, 50)),
                    "iters_p99": float(np.percentile(it, 99)), "converged_fraction": round(conv, 5),
@@ -228,7 +278,7 @@ def main():
     }
     if not args.no_previous:
         print("[bench] previous-step warm-start rollout", file=sys.stderr, flush=True)
-        prev = run_gpu(args.worlds, args.steps, args.warmup, kamx.WARM_PREVIOUS, sched)
+        prev = run_gpu(args.worlds, args.steps, args.warmup, kamx.WARM_PREVIOUS, sched, workload=args.workload)
         pit = prev["iters"]
         result["warm_previous"] = {
             "value": round(args.worlds * args.steps / prev["wall_s"], 1),

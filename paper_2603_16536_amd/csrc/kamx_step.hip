@@ -437,6 +437,17 @@ __device__ inline float dot4(const float *a, const float *b) {
     return x.x * y.x + x.y * y.y + x.z * y.z + x.w * y.w;
 }
 
+// ---- 16x16 tiles of the packed lower triangle on the matrix cores
+// v_mfma_f32_16x16x4f32: lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16] of a 16x4 by 4x16 product and holds rows
+// 4 (l / 16) + c, column l % 16 of the 16x16 accumulator.
+typedef float mfx4 __attribute__((ext_vector_type(4)));
+
+__device__ inline mfx4 mfma4(float a, float b, mfx4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+
+// element (r, c) of the packed lower triangle; 0 above the diagonal
+__device__ inline float tri_at(const float *A, int r, int c) { return c <= r ? A[tri_row_offset(r) + c] : 0.f; }
+
 // Body gather of the matrix-free product: g_b = sum over the rows incident
 // to body b of J_{r,b}^T p_r x_r, one thread per (body, component), FP64,
 // rows in increasing order.  Ends with a barrier.
@@ -536,7 +547,11 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
 
     const int nb = W.nb, nj = W.nj;
 
-    if (a.phase_clk && tid == 0) a.phase_clk[16 * w + 0] = wall_clock64();
+    if (a.phase_clk && tid == 0) {
+        a.phase_clk[16 * w + 0] = wall_clock64();
+        a.phase_clk[16 * w + 14] = __smid();  // compute unit that runs this world
+        a.phase_clk[16 * w + 15] = __builtin_amdgcn_s_getreg(GETREG_IMMED(31, 0, HW_ID));  // raw hardware id
+    }
     // ---- reset: a world whose reset body fell below the threshold restarts
     if (tid == 0) {
         int rs = 0;
@@ -1083,74 +1098,44 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
             }
             __syncthreads();
             if (s_int[2]) break;
-            // panel: L_IK = A_IK Xkk^T for the tiles I below the diagonal
+            // panel: L_IK = A_IK Xkk^T for the tiles I below the diagonal, one
+            // wave per tile on the matrix cores (each wave reads its tile
+            // completely before overwriting it)
             const int nI = T - K - 1;
-            constexpr int PR = ((MC / 16 - 1) * 256 + NT - 1) / NT;
-            float pres[PR];
-            int pe[PR];
+            {
+                const int lane = tid & 63, wv = tid >> 6, fr = lane & 15, fk = lane >> 4;
+                for (int Ii = wv; Ii < nI; Ii += NT / 64) {
+                    const int I = K + 1 + Ii;
+                    mfx4 acc = {0.f, 0.f, 0.f, 0.f};
+                    const float *Ar = A + tri_row_offset(16 * I + fr) + k0;
 #pragma unroll
-            for (int rd = 0; rd < PR; ++rd) {
-                int e = tid + rd * NT;
-                pe[rd] = e;
-                pres[rd] = 0.f;
-                if (e < nI * 256) {
-                    int I = K + 1 + (e >> 8), rr = (e >> 4) & 15, cc = e & 15;
-                    const float *Ar = A + tri_row_offset(16 * I + rr) + k0;
-                    const float *Xr = Xs + 16 * cc;
-                    float acc = 0.f;
+                    for (int ch = 0; ch < 4; ++ch) acc = mfma4(Ar[4 * ch + fk], Xs[16 * fr + 4 * ch + fk], acc);
 #pragma unroll
-                    for (int ch = 0; ch < 4; ++ch) acc += dot4(Ar + 4 * ch, Xr + 4 * ch);
-                    pres[rd] = acc;
+                    for (int c = 0; c < 4; ++c) A[tri_row_offset(16 * I + 4 * fk + c) + k0 + fr] = acc[c];
                 }
             }
             __syncthreads();
+            // trailing update A_IJ -= L_IK L_JK^T, K < J <= I: one wave per
+            // tile pair on the matrix cores
+            {
+                const int npair = nI * (nI + 1) / 2;
+                const int lane = tid & 63, wv = tid >> 6, fr = lane & 15, fk = lane >> 4;
+                for (int p = wv; p < npair; p += NT / 64) {
+                    int Ii = (int)((sqrtf(8.f * (float)p + 1.f) - 1.f) * 0.5f);
+                    while ((Ii + 1) * (Ii + 2) / 2 <= p) ++Ii;
+                    while (Ii * (Ii + 1) / 2 > p) --Ii;
+                    const int Jj = p - Ii * (Ii + 1) / 2;
+                    const int I = K + 1 + Ii, J = K + 1 + Jj;
+                    const float *Ri = A + tri_row_offset(16 * I + fr) + k0;
+                    const float *Rj = A + tri_row_offset(16 * J + fr) + k0;
+                    mfx4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int rd = 0; rd < PR; ++rd) {
-                int e = pe[rd];
-                if (e < nI * 256) {
-                    int I = K + 1 + (e >> 8), rr = (e >> 4) & 15, cc = e & 15;
-                    A[tri_row_offset(16 * I + rr) + k0 + cc] = pres[rd];
-                }
-            }
-            __syncthreads();
-            // trailing update A_IJ -= L_IK L_JK^T, K < J <= I
-            const int npair = nI * (nI + 1) / 2;
-            for (int t = tid; t < 16 * npair; t += NT) {
-                int p = t >> 4, mt = t & 15, mr = mt >> 2, mc = mt & 3;
-                int Ii = (int)((sqrtf(8.f * (float)p + 1.f) - 1.f) * 0.5f);
-                while ((Ii + 1) * (Ii + 2) / 2 <= p) ++Ii;
-                while (Ii * (Ii + 1) / 2 > p) --Ii;
-                int Jj = p - Ii * (Ii + 1) / 2;
-                int I = K + 1 + Ii, J = K + 1 + Jj;
-                if (I == J && mc > mr) continue;
-                const int r0 = 16 * I + 4 * mr, c0 = 16 * J + 4 * mc;
-                float acc[4][4];
+                    for (int ch = 0; ch < 4; ++ch) acc = mfma4(Ri[4 * ch + fk], Rj[4 * ch + fk], acc);
 #pragma unroll
-                for (int x = 0; x < 4; ++x)
-#pragma unroll
-                    for (int y = 0; y < 4; ++y) acc[x][y] = 0.f;
-#pragma unroll
-                for (int ch = 0; ch < 4; ++ch) {
-                    float4 lr[4], lc[4];
-#pragma unroll
-                    for (int x = 0; x < 4; ++x)
-                        lr[x] = *reinterpret_cast<const float4 *>(A + tri_row_offset(r0 + x) + k0 + 4 * ch);
-#pragma unroll
-                    for (int y = 0; y < 4; ++y)
-                        lc[y] = *reinterpret_cast<const float4 *>(A + tri_row_offset(c0 + y) + k0 + 4 * ch);
-#pragma unroll
-                    for (int x = 0; x < 4; ++x)
-#pragma unroll
-                        for (int y = 0; y < 4; ++y)
-                            acc[x][y] += lr[x].x * lc[y].x + lr[x].y * lc[y].y + lr[x].z * lc[y].z + lr[x].w * lc[y].w;
-                }
-                const bool diag = (I == J) && (mc == mr);
-#pragma unroll
-                for (int x = 0; x < 4; ++x) {
-                    float *dst = A + tri_row_offset(r0 + x) + c0;
-#pragma unroll
-                    for (int y = 0; y < 4; ++y)
-                        if (!diag || y <= x) dst[y] -= acc[x][y];
+                    for (int c = 0; c < 4; ++c) {
+                        const int rr = 4 * fk + c;
+                        if (I != J || fr <= rr) A[tri_row_offset(16 * I + rr) + 16 * J + fr] -= acc[c];
+                    }
                 }
             }
             __syncthreads();
@@ -1160,37 +1145,79 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
     const int factor_fail = s_int[2];
 
     if (a.phase_clk && tid == 0) a.phase_clk[16 * w + 4] = wall_clock64();
-    // ---- explicit inverse of the factor, in place: X = L^-1 (columns from
-    //      the last one; four threads per row split each dot product)
+    // ---- explicit inverse of the factor, in place: X = L^-1 over 16x16
+    //      tiles.  Diagonal tiles are inverted in registers (one wave per
+    //      tile); then tile row by tile row, M_ik = X_ii L_ik (k < i) and
+    //      X_ij = -sum_{k=j}^{i-1} M_ik X_kj, one wave per tile on the
+    //      matrix cores, results held in registers until every wave has read
+    //      the row.
     if (!factor_fail) {
-        for (int j = m - 1; j >= 0; --j) {
-            float ljj = A[tri_row_offset(j) + j];
-            if (tid < MC) vcol[tid] = (tid > j && tid < m) ? A[tri_row_offset(tid) + j] : 0.f;
-            __syncthreads();
-            float inv = 1.f / ljj;
-            float acc = 0.f;
-            const bool act = si > j && si < m;
-            if (act) {
-                const float *Ri = A + tri_row_offset(si);
-                const int c0 = (j + 1) >> 2, c1 = (si + 4) >> 2;
-                float a1 = 0.f, a2 = 0.f, a3 = 0.f;
-                int c = c0 + sq;
-                for (; c + 3 * TPR < c1; c += 4 * TPR) {
-                    acc += dot4(Ri + 4 * c, vcol + 4 * c);
-                    a1 += dot4(Ri + 4 * (c + TPR), vcol + 4 * (c + TPR));
-                    a2 += dot4(Ri + 4 * (c + 2 * TPR), vcol + 4 * (c + 2 * TPR));
-                    a3 += dot4(Ri + 4 * (c + 3 * TPR), vcol + 4 * (c + 3 * TPR));
-                }
-                for (; c < c1; c += TPR) acc += dot4(Ri + 4 * c, vcol + 4 * c);
-                acc = (acc + a1) + (a2 + a3);
+        const int T = (m + 15) >> 4;
+        const int lane = tid & 63, wv = tid >> 6, fr = lane & 15, fk = lane >> 4;
+        constexpr int NW = NT / 64;
+        static_assert(2 * NW >= MC / 16 - 1, "two off-diagonal tiles per wave must cover a tile row");
+        for (int Ti = wv; Ti < T; Ti += NW) {
+            const int k0 = 16 * Ti, r = lane;
+            float a[16];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) a[c] = (r < 16 && c <= r) ? A[tri_row_offset(k0 + (r & 15)) + k0 + c] : 0.f;
+            float xc[16];
+#pragma unroll
+            for (int rr = 0; rr < 16; ++rr) {
+                float acc = (r == rr) ? 1.f : 0.f;
+#pragma unroll
+                for (int kk = 0; kk < rr; ++kk) acc -= rdlane(a[kk], rr) * xc[kk];
+                xc[rr] = acc / rdlane(a[rr], rr);
             }
-            acc = group_sum<TPR>(acc);
-            if (sq == 0) {
-                if (act) A[tri_row_offset(si) + j] = -acc * inv;
-                else if (si == j) A[tri_row_offset(si) + j] = inv;
+            if (r < 16) {
+#pragma unroll
+                for (int rr = 0; rr < 16; ++rr)
+                    if (rr >= r) A[tri_row_offset(k0 + rr) + k0 + r] = xc[rr];
             }
-            __syncthreads();
         }
+        __syncthreads();
+        for (int Ti = 1; Ti < T; ++Ti) {
+            const int i0 = 16 * Ti;
+            // M_ik = X_ii L_ik in place
+            for (int Tk = wv; Tk < Ti; Tk += NW) {
+                mfx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int ch = 0; ch < 4; ++ch)
+                    acc = mfma4(tri_at(A, i0 + fr, i0 + 4 * ch + fk),
+                                A[tri_row_offset(i0 + 4 * ch + fk) + 16 * Tk + fr], acc);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) A[tri_row_offset(i0 + 4 * fk + c) + 16 * Tk + fr] = acc[c];
+            }
+            __syncthreads();
+            // X_ij = -sum_k M_ik X_kj (two tiles per wave at most: 14 tile rows, 8 waves)
+            mfx4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int Tj = wv + q * NW;
+                if (Tj >= Ti) continue;
+                mfx4 acc = {0.f, 0.f, 0.f, 0.f};
+                for (int Tk = Tj; Tk < Ti; ++Tk) {
+                    const float *Mr = A + tri_row_offset(i0 + fr) + 16 * Tk;
+#pragma unroll
+                    for (int ch = 0; ch < 4; ++ch) {
+                        const int kr = 16 * Tk + 4 * ch + fk, jc = 16 * Tj + fr;
+                        acc = mfma4(Mr[4 * ch + fk], tri_at(A, kr, jc), acc);
+                    }
+                }
+                if (q == 0) acc0 = acc;
+                else acc1 = acc;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int Tj = wv + q * NW;
+                if (Tj >= Ti) continue;
+                const mfx4 acc = q == 0 ? acc0 : acc1;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) A[tri_row_offset(i0 + 4 * fk + c) + 16 * Tj + fr] = -acc[c];
+            }
+        }
+        __syncthreads();
     }
 
     if (a.phase_clk && tid == 0) a.phase_clk[16 * w + 5] = wall_clock64();

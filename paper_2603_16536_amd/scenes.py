@@ -785,6 +785,48 @@ def box_bin_batch(n_worlds, seed=1005, n_boxes=20, dt=2e-3):
     return concat([box_bin_world(rng, n_boxes, dt) for _ in range(n_worlds)])
 
 
+def box_bin_resting_world(rng, dt=2e-3, half=BIN_HALF):
+    """Twelve boxes already in contact, for single-step tests: six on the
+    floor in a 3 x 2 grid (two of them against the -x and +x walls, unrotated),
+    each carrying a smaller box of the same yaw on its top face.  Every
+    contact penetrates by a draw from U[0, 2 mm]; vertex-face decisions stay
+    at least 4 mm from their thresholds; 56 contacts in all."""
+    B = _Builder()
+    box = []
+    cells = [(-0.1, -0.06), (0.0, -0.06), (0.1, -0.06), (-0.1, 0.06), (0.0, 0.06), (0.1, 0.06)]
+    for i, (cx, cy) in enumerate(cells):
+        side = rng.uniform(0.04, 0.06, 3)
+        h = 0.5 * side
+        wall = i in (0, 2)
+        yaw = 0.0 if wall else rng.uniform(0, 2 * np.pi)
+        q = quat_axis_angle((0.0, 0.0, 1.0), yaw)
+        d = rng.uniform(0.0, 0.002)
+        if wall:
+            sgn = -1.0 if i == 0 else 1.0
+            cx = sgn * (half[0] - h[0] + rng.uniform(0.0, 0.002))
+        c = np.array([cx, cy, h[2] - d])
+        rho = rng.uniform(100.0, 5000.0)
+        m = rho * side.prod()
+        lo = B.body(m, box_inertia(m, *side), c, q)
+        box.append(np.r_[h, rng.uniform(0.3, 1.0)])
+        # the smaller box on top, same yaw, footprint 5-10 mm inside each side
+        hu = np.r_[h[:2] - rng.uniform(0.005, 0.01, 2), rng.uniform(0.01, 0.03)]
+        du = rng.uniform(0.0, 0.002)
+        cu = np.array([c[0], c[1], c[2] + h[2] + hu[2] - du])
+        mu_ = rng.uniform(100.0, 5000.0) * 8 * hu.prod()
+        B.body(mu_, box_inertia(mu_, *(2 * hu)), cu, q)
+        box.append(np.r_[hu, rng.uniform(0.3, 1.0)])
+        _ = lo
+    s = B.scene(dt)
+    s.body_box = np.array(box)
+    return s
+
+
+def box_bin_resting_batch(n_worlds, seed=1005, dt=2e-3):
+    rng = np.random.default_rng(seed)
+    return concat([box_bin_resting_world(rng, dt) for _ in range(n_worlds)])
+
+
 def perturb_state(scene, rng, v_scale=0.2, w_scale=0.5):
     """Random twists (not constraint-consistent) for single-step problems."""
     s = scene.replace(u=scene.u.copy())

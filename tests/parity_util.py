@@ -91,7 +91,10 @@ def compare_world(scene, params, g, w, replay=True, oracle_over=None, warm=None,
     import oracle.contacts as OC
     inp = dict(g.get("inputs") or {})
     inp.update(inputs or {})
-    if inp.get("explicit", True):
+    if inp.get("box_bin") is not None:
+        wx, wy, margin, cap = inp["box_bin"]
+        csc = OC.box_bin_contacts(scene, scene.q, wx, wy, margin, cap)
+    elif inp.get("explicit", True):
         csc = scene
     else:
         csc = OC.probe_contacts(scene, scene.q, float(params.contact_margin))
@@ -127,6 +130,18 @@ def compare_world(scene, params, g, w, replay=True, oracle_over=None, warm=None,
     imp_g = S["J"].T @ lam_g
     imp_o = S["J"].T @ ref["lam"]
     e_u = np.abs(u_g - u_o).max() / max(np.abs(u_o).max(), floor_vel)
+    # momentum-weighted velocity error: M (u_g - u_o) per body (mass for the
+    # linear part, world inertia for the angular part) against the largest
+    # net impulse; an impulse error within the bar moves a body of mass m by
+    # at most that error / m, so this is the u+ check that stays meaningful
+    # when light and heavy bodies share a world
+    du = (g["u"][b0:b1] - ref["u"]).reshape(-1, 6)
+    mom = np.zeros_like(du)
+    for k, b in enumerate(range(b0, b1)):
+        R = scenes.quat_to_mat(scene.q[b, 3:])
+        mom[k, :3] = scene.body_mass[b] * du[k, :3]
+        mom[k, 3:] = R @ (scene.body_inertia[b] * (R.T @ du[k, 3:]))
+    e_mom = np.abs(mom).max() / max(np.abs(imp_o).max(), floor_imp)
     e_imp = np.abs(imp_g - imp_o).max() / max(np.abs(imp_o).max(), floor_imp)
     e_lam = np.abs(lam_g - ref["lam"]).max() / max(np.abs(ref["lam"]).max(), floor_imp)
     # FP64 natural-map residual of the GPU impulses (preconditioned units)
@@ -140,7 +155,7 @@ def compare_world(scene, params, g, w, replay=True, oracle_over=None, warm=None,
     lt = lam_g / p
     v = p * (D @ lam_g + vf)
     r_ncp = ncp_natural_residual(lt, v, kind, mu)
-    return dict(e_u=e_u, e_imp=e_imp, e_lam=e_lam, r_ncp=r_ncp, ref=ref, m=m, iters=iters)
+    return dict(e_u=e_u, e_mom=e_mom, e_imp=e_imp, e_lam=e_lam, r_ncp=r_ncp, ref=ref, m=m, iters=iters)
 
 
 def ncp_natural_residual(lt, v, kind, mu):

@@ -1,0 +1,91 @@
+"""Box-in-bin contact generation on the device against the oracle's
+generator on the same FP32 state (keys exactly; points, normals and gaps to
+FP32 rounding), the step built on those contacts against the oracle replay,
+and a falling-box rollout that stays in the bin."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import oracle.contacts as OC  # noqa: E402
+from paper_2603_16536_amd import kamx, scenes  # noqa: E402
+
+from parity_util import compare_world  # noqa: E402
+
+MARGIN = 0.004
+HALF = scenes.BIN_HALF
+PARAMS = dict(dt=2e-3, eta=1e-4, rho_bilateral=1e-4, rho_contact=0.3, eps=1e-6, max_iters=2000, log_restarts=1)
+
+
+def run_one_step(scene, params=PARAMS):
+    m = kamx.Model(scene, params=params, max_contacts=64)
+    m.contacts_box_bin(HALF, MARGIN)
+    m.step(1)
+    torch.cuda.synchronize()
+    raw, cnt = m.contacts()
+    st = {k: v.cpu().numpy() for k, v in m.stats().items()}
+    g = dict(u=m.state()[1].cpu().numpy().astype(np.float64), lam=m.impulses().cpu().numpy().astype(np.float64),
+             row_offsets=m.row_offsets, restart_log=m.restart_log().cpu().numpy(),
+             used_scene=kamx.contacts_to_scene(scene, raw, cnt),
+             inputs=dict(box_bin=(HALF[0], HALF[1], MARGIN, 64), ext=None, step=0), **st)
+    m.close()
+    return g
+
+
+def test_box_bin_contacts_match_oracle_generator():
+    scene = scenes.round_to_f32(scenes.box_bin_resting_batch(16, seed=1005))
+    g = run_one_step(scene)
+    dev = g["used_scene"]
+    ref = OC.box_bin_contacts(scene, scene.q, HALF[0], HALF[1], MARGIN, 64)
+    dco, rco = dev.contact_offsets(), ref.contact_offsets()
+    for w in range(16):
+        dk = dev.contact_key[dco[w]:dco[w + 1]]
+        rk = ref.contact_key[rco[w]:rco[w + 1]]
+        assert np.array_equal(np.sort(dk), np.sort(rk)), w
+        di = {int(k): i for i, k in enumerate(dk)}
+        for j, k in enumerate(rk):
+            a, b = dco[w] + di[int(k)], rco[w] + j
+            assert np.array_equal(dev.contact_body[a], ref.contact_body[b])
+            assert np.abs(dev.contact_point[a] - ref.contact_point[b]).max() < 1e-6
+            assert np.abs(dev.contact_normal[a] - ref.contact_normal[b]).max() < 1e-6
+            assert abs(dev.contact_gap[a] - ref.contact_gap[b]) < 1e-6
+            assert dev.contact_mu[a] == np.float32(ref.contact_mu[b])
+        # the device lists the deepest first
+        gd = dev.contact_gap[dco[w]:dco[w + 1]]
+        assert np.all(np.diff(gd) >= 0)
+
+
+def test_box_bin_step_matches_oracle_replay():
+    scene = scenes.round_to_f32(scenes.box_bin_resting_batch(8, seed=7))
+    g = run_one_step(scene)
+    kp = kamx.make_params(**PARAMS)
+    errs = [compare_world(scene, kp, g, w) for w in range(8)]
+    e = np.array([[d["e_u"], d["e_imp"], d["r_ncp"]] for d in errs])
+    print(f"\nbox bin, 8 worlds, iters {g['iters'].tolist()}: max rel err u+ {e[:, 0].max():.2e} "
+          f"J^T lambda {e[:, 1].max():.2e}, FP64 r_ncp {e[:, 2].max():.2e}")
+    assert e[:, 0].max() < 1e-4 and e[:, 1].max() < 1e-4
+
+
+def test_falling_boxes_settle_inside_the_bin():
+    scene = scenes.round_to_f32(scenes.box_bin_batch(32, seed=1005))
+    m = kamx.Model(scene, params=dict(PARAMS, log_restarts=0), max_contacts=64)
+    m.contacts_box_bin(HALF, 0.01)
+    m.step(300)
+    torch.cuda.synchronize()
+    q, u = (t.cpu().numpy() for t in m.state())
+    st = {k: v.cpu().numpy() for k, v in m.stats().items()}
+    raw, cnt = m.contacts()
+    m.close()
+    assert np.all(np.isfinite(q)) and np.all(np.isfinite(u))
+    ext = np.abs(np.stack([scenes.quat_to_mat(x) for x in q[:, 3:].astype(np.float64)])) @ scene.body_box[:, :3, None]
+    ext = ext[..., 0]
+    assert np.all(np.abs(q[:, 0]) < HALF[0] + 0.01) and np.all(np.abs(q[:, 1]) < HALF[1] + 0.01)
+    assert np.all(q[:, 2] - ext[:, 2] > -0.01)
+    print(f"\nafter 300 steps: contacts per world {cnt.cpu().numpy().mean():.1f}, iters mean "
+          f"{st['iters'].mean():.0f}, converged {np.mean(st['status'] == 0):.2f}")
+    assert cnt.cpu().numpy().min() >= 4

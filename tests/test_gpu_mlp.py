@@ -220,7 +220,9 @@ def test_learned_warm_start_equals_external_and_matches_oracle():
     iteration count and restart decisions).  The device prediction agrees
     with the oracle's within the network bar."""
     import torch
+    import oracle
     import oracle.contacts as OC
+    from parity_util import oracle_params, oracle_torques
     p = dict(BIPED, log_restarts=1)
     n = 16
     scene, A = biped_model(n, p)
@@ -233,8 +235,24 @@ def test_learned_warm_start_equals_external_and_matches_oracle():
     ref_net = random_net(rng, nf, 256, ns)
     ref_net.mu_in[:] = 0.0
     ref_net.s_in[:] = 1.0
-    ref_net.mu_out[:] = 0.0
-    ref_net.sigma_out[:] = 0.02
+    # output scale of a trained network: centred on the oracle's converged
+    # impulses of these worlds (by slot), spread a few per cent of their
+    # spread across worlds
+    kp0 = kamx.make_params(**p)
+    csc0 = OC.probe_contacts(scene, scene.q, float(kp0.contact_margin))
+    T0 = np.concatenate([oracle_torques(scene, kp0, w, pd=(15.0, 0.6), refs=refs) for w in range(n)])
+    P0 = oracle_params(kp0, eps=1e-10, max_iters=20000)
+    ref0 = oracle.step(csc0, P0, joint_torque=T0)
+    slots = np.zeros((n, ns))
+    co0 = csc0.contact_offsets()
+    for w in range(n):
+        r0 = int(ref0["row_offset"][w])
+        slots[w, :200] = ref0["lam"][r0:r0 + 200]
+        for c in range(co0[w], co0[w + 1]):
+            k = int(csc0.contact_key[c])
+            slots[w, 200 + 3 * k:203 + 3 * k] = ref0["lam"][r0 + 200 + 3 * (c - co0[w]):r0 + 203 + 3 * (c - co0[w])]
+    ref_net.mu_out[:ns] = slots.mean(axis=0).astype(np.float32)
+    ref_net.sigma_out[:ns] = (0.05 * slots.std(axis=0) + 1e-5).astype(np.float32)
     net = device_net(ref_net, n)
     # device prediction and the learned step
     pred_dev = net.forward(A.features()).cpu().numpy()
@@ -253,6 +271,7 @@ def test_learned_warm_start_equals_external_and_matches_oracle():
     assert np.array_equal(A.stats()["iters"].cpu().numpy(), B.stats()["iters"].cpu().numpy())
     # oracle-side features, prediction and warm start
     kp = kamx.make_params(**dict(p, warmstart=kamx.WARM_EXTERNAL))
+    kpd = kamx.make_params(**dict(p, warmstart=kamx.WARM_EXTERNAL, fixed_iters=600, max_iters=600))
     X = np.stack([oracle_features(scene, kp, w, refs) for w in range(n)])
     pred_orc, _ = M.forward(ref_net, X, bf16=True)
     e_pred = rel(pred_dev, pred_orc)
@@ -268,7 +287,11 @@ def test_learned_warm_start_equals_external_and_matches_oracle():
             k = int(csc.contact_key[c])
             r = ro[w] + 200 + 3 * (c - co[w])
             lam_orc[r:r + 3] = pred_orc[w, 200 + 3 * k:203 + 3 * k]
-    D.set_params(**dict(p, warmstart=kamx.WARM_EXTERNAL))
+    # D runs 600 iterations, well past convergence from any of these warm
+    # starts, so the comparison holds every body (light links included) to
+    # the converged answer rather than to an eps-sized band around it
+    pd_ = dict(p, warmstart=kamx.WARM_EXTERNAL, fixed_iters=600, max_iters=600)
+    D.set_params(**pd_)
     D.set_warmstart(lam_orc.astype(np.float32))
     D.step(1)
     torch.cuda.synchronize()
@@ -282,11 +305,11 @@ def test_learned_warm_start_equals_external_and_matches_oracle():
     for w in range(n):
         r0 = int(ro[w])
         warm = lam_orc[r0:r0 + int(sd["rows"][w])].astype(np.float32).astype(np.float64)
-        errs.append(compare_world(scene, kp, g, w, warm=warm))
+        errs.append(compare_world(scene, kpd, g, w, warm=warm))
     e = np.array([[d["e_u"], d["e_imp"]] for d in errs])
     print(f"learned-style warm start: iters {sd['iters'].tolist()}; max rel err u+ {e[:, 0].max():.2e} "
           f"J^T lambda {e[:, 1].max():.2e}")
-    assert e[:, 1].max() < 1e-4 and e[:, 0].max() < 5e-4
+    assert e[:, 1].max() < 1e-4 and e[:, 0].max() < 1e-4
     for m in (A, B, Cm, D):
         m.close()
     net.close()

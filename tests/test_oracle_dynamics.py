@@ -358,3 +358,19 @@ def test_status_flags(orc):
     ref = orc.step(s, P)
     nb0 = 31
     assert np.array_equal(out["u"][:nb0], ref["u"][:nb0])
+
+
+def test_redundant_loops_with_rounded_frames_have_a_dual_residual_floor(orc):
+    """Reading of the paper's redundant loops: the excavator assembled in
+    FP64 converges to 1e-6 within a few tens of iterations; the same
+    excavator with every input rounded to FP32 cannot close its four planar
+    loops exactly, and Baumgarte feedback on the redundant rows leaves the
+    dual residual a floor above 1e-6, so the cap is reached; without the
+    feedback the rounded system converges again."""
+    ex = scenes.excavator_batch(2, seed=1003)
+    P = orc.Params(dt=2e-3, eta=1e-4, rho_bil=1e-4, rho_c=0.3, eps=1e-6, max_iters=2000, baumgarte=0.2)
+    assert np.all(orc.step(ex, P)["iters"] < 100)
+    r = orc.step(scenes.round_to_f32(ex), P)
+    assert np.all(r["iters"] == 2000) and np.all(r["resid"][:, 1] > 1e-6)
+    assert np.all(r["resid"][:, 0] < 1e-6)
+    assert np.all(orc.step(scenes.round_to_f32(ex), P.replace(baumgarte=0.0))["iters"] < 100)
