@@ -78,8 +78,10 @@ typedef int32_t kamx_status;
 #define KAMX_WARM_EXTERNAL 2 /* impulses given by kamx_set_warmstart      */
 #define KAMX_WARM_LEARNED 3  /* prediction of the attached network         */
 
-#define KAMX_SCHED_INDEX 0 /* worlds of a size bucket dispatched in index order              */
-#define KAMX_SCHED_LPT 1   /* by decreasing iteration count of the previous step (default)    */
+#define KAMX_SCHED_INDEX 0 /* one launch per step, worlds of a bucket in index order           */
+#define KAMX_SCHED_LPT 1   /* one launch per step, by decreasing previous iteration count       */
+#define KAMX_SCHED_CHAIN 2 /* multi-step calls keep each world on its workgroup for up to 64
+                              steps per launch; single steps as LPT (default)                 */
 
 /* Limits of one world (per-world problem sizes above these are rejected). */
 #define KAMX_MAX_BODIES_PER_WORLD 64
@@ -242,24 +244,40 @@ kamx_status kamx_set_external(kamx_model m, const float *joint_torque_dev, kamx_
  * kamx_model_info.  Copied at the call. */
 kamx_status kamx_set_warmstart(kamx_model m, const float *lambda_dev, kamx_stream stream);
 
-/* Dispatch order of the worlds inside each size bucket (KAMX_SCHED_*).
- * The order decides only which workgroup slot takes a world: results are
- * bitwise identical under either mode.  The paper notes that uneven
- * convergence and wave quantisation leave a tail (Sec. 6.2); ordering by the last
- * iteration count puts them first.  Host-side, synchronous; EINVAL on an
- * unknown mode. */
+/* How steps are mapped onto workgroups (KAMX_SCHED_*).  The mapping decides
+ * only which workgroup runs a world's step and when: results are bitwise
+ * identical under every mode.  Convergence is uneven (Sec. 4.1; the paper
+ * notes the tail effect, Sec. 6.2): ~1% of biped steps need the whole
+ * iteration budget.  With one launch per step every step waits for its
+ * slowest world; ordering by the previous count (LPT) helps only as far as
+ * slow steps recur.  CHAIN keeps each world on one workgroup for a run of
+ * steps, so a slow solve delays only its own world and the hardware
+ * balances whole chains.  Chains apply to calls of kamx_step with
+ * nsteps > 1 when every step's inputs are on the device already (no
+ * generated contacts, no learned warm start); otherwise steps are launched
+ * one by one.  Host-side, synchronous; EINVAL on an unknown mode. */
 kamx_status kamx_set_schedule(kamx_model m, int32_t mode);
 
 /* Advance every world by nsteps steps (asynchronous on stream).  nsteps = 1
- * enqueues the step's kernels directly.  nsteps > 1 replays captured graphs
- * of up to 32 steps (the loops that run each world to convergence stay
- * inside the kernels, so the graph has fixed shape, Sec. 5.2); a graph is
- * captured on first use of a step count and reused until a call that changes
- * a kernel argument (kamx_set_params, kamx_set_external, kamx_contacts_upload
- * with another array, kamx_set_schedule) drops it.  Results equal nsteps
- * single steps bitwise.  Do not call with nsteps > 1 while the stream is
- * itself being captured (use nsteps = 1 there). */
+ * enqueues the step's kernels directly.  nsteps > 1 either runs chained
+ * launches (KAMX_SCHED_CHAIN, up to 64 steps per launch) or replays
+ * captured graphs of up to 32 single-step launches (the loops that run each
+ * world to convergence stay inside the kernels, so the graph has fixed
+ * shape, Sec. 5.2); a graph is captured on first use of a step count and
+ * reused until a call that changes a kernel argument (kamx_set_params,
+ * kamx_set_external, kamx_contacts_upload with another array,
+ * kamx_set_schedule, kamx_set_iteration_log, kamx_contacts_box_bin,
+ * kamx_model_attach_mlp) drops it.  Results equal nsteps single steps
+ * bitwise.  Do not call with nsteps > 1 while the stream is itself being
+ * captured (use nsteps = 1 there). */
 kamx_status kamx_step(kamx_model m, int32_t nsteps, kamx_stream stream);
+
+/* Iteration count and active row count of every step of every following
+ * kamx_step call: iters_dev and rows_dev [steps][n_worlds] (device,
+ * caller-owned, valid while steps are pending; rows_dev may be NULL); row k
+ * holds the k-th step of the call, steps beyond `steps` are not logged.
+ * iters_dev = NULL turns logging off.  EINVAL if steps < 1. */
+kamx_status kamx_set_iteration_log(kamx_model m, int32_t *iters_dev, int32_t *rows_dev, int32_t steps);
 
 /* Impulses of the last step (physical units, N s) into lambda_dev
  * [rows_capacity]; rows beyond a world's active count are zero. */

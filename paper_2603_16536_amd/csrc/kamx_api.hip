@@ -17,7 +17,7 @@ hipError_t launch_step(const StepArgs &args, int mc, int n, hipStream_t stream);
 int bucket_capacity(int rows);
 size_t step_smem_bytes(int mc);
 hipError_t launch_lpt_order(const int32_t *worlds, int n, const int32_t *iters, int32_t *order, hipStream_t stream);
-hipError_t launch_advance_step(uint32_t *ctr, hipStream_t stream);
+hipError_t launch_advance_step(uint32_t *ctr, uint32_t inc, hipStream_t stream);
 hipError_t launch_box_bin(const WorldInfo *worlds, int n_worlds, const float *q, const float *box_geom, float wx,
                           float wy, float margin, kamx_contact *out, int32_t *count, hipStream_t stream);
 int box_bin_max_boxes();
@@ -76,7 +76,10 @@ struct kamx_model_s {
     int max_contacts = 0;
     kamx_params params{};
     uint32_t step_index = 0;
-    int32_t schedule = KAMX_SCHED_LPT;
+    int32_t schedule = KAMX_SCHED_CHAIN;
+    int32_t *iter_log = nullptr;  // caller-owned [iter_log_rows * n_worlds] iterations per step
+    int32_t *row_log = nullptr;   // caller-owned, same shape: active rows per step
+    int32_t iter_log_rows = 0;
     std::vector<int32_t> row_offsets;
     std::vector<Bucket> buckets;
     std::vector<void *> allocations;
@@ -122,6 +125,7 @@ struct kamx_model_s {
 };
 
 static constexpr int kGraphSteps = 32;  // steps per captured graph
+static constexpr int kChainSteps = 64;  // steps per launch when worlds keep their workgroup
 
 static void drop_graphs(kamx_model m) {
     for (auto &g : m->graphs) (void)hipGraphExecDestroy(g.second);
@@ -577,6 +581,8 @@ static StepArgs step_args(kamx_model m) {
     a.phase_clk = m->d_phase_clk;
     a.p = to_solver(m->params);
     a.step_ctr = m->d_step;
+    a.nsteps = 1;
+    a.n_worlds = m->n_worlds;
     a.stage = 0;
     a.n_feat = m->n_feat;
     a.ws_slots = m->d_ws;
@@ -613,53 +619,73 @@ static kamx_status enqueue_features(kamx_model m, float *x, hipStream_t s) {
     return KAMX_OK;
 }
 
-// Enqueue nsteps steps: per step, every bucket's step kernel (largest
-// worlds first) and its dispatch order for the next step, then the counter.
-// With the learned warm start each step first runs the feature pass and the
-// network.
-static kamx_status enqueue_steps(kamx_model m, int nsteps, hipStream_t s) {
-    const StepArgs base = step_args(m);
-    const bool lpt = m->schedule == KAMX_SCHED_LPT;
-    const bool learned = m->params.warmstart == KAMX_WARM_LEARNED;
-    for (int k = 0; k < nsteps; ++k) {
-        if (m->box_bin) {
-            hipError_t e = launch_box_bin(m->d_worlds, m->n_worlds, m->d_q, m->d_box_geom, m->bin_wx, m->bin_wy,
-                                          m->bin_margin, m->d_gen, m->d_gen_count, s);
-            if (e != hipSuccess) return fail(KAMX_EDEVICE, "contact generation launch: %s", hipGetErrorString(e));
+// One launch per bucket advancing every world by n steps (n > 1 only when
+// every step's inputs are already on the device: no per-step contact
+// generation or network), starting at position pos of the current call.
+// Single steps also run the contact generation, the feature pass and the
+// network when those are on, and reorder the bucket for the next step.
+static kamx_status enqueue_launch(kamx_model m, int n, int pos, hipStream_t s) {
+    StepArgs base = step_args(m);
+    base.nsteps = n;
+    base.n_worlds = m->n_worlds;
+    if (m->iter_log && pos < m->iter_log_rows) {
+        base.iter_log = m->iter_log + (long)pos * m->n_worlds;
+        base.row_log = m->row_log ? m->row_log + (long)pos * m->n_worlds : nullptr;
+        base.iter_log_rows = m->iter_log_rows - pos;
+    }
+    const bool lpt = n == 1 && m->schedule != KAMX_SCHED_INDEX;
+    if (m->box_bin) {
+        hipError_t e = launch_box_bin(m->d_worlds, m->n_worlds, m->d_q, m->d_box_geom, m->bin_wx, m->bin_wy,
+                                      m->bin_margin, m->d_gen, m->d_gen_count, s);
+        if (e != hipSuccess) return fail(KAMX_EDEVICE, "contact generation launch: %s", hipGetErrorString(e));
+    }
+    if (m->params.warmstart == KAMX_WARM_LEARNED) {
+        K_TRY(enqueue_features(m, m->d_feat, s));
+        K_TRY(mlp_forward_internal(m->mlp, m->d_feat, m->n_worlds, m->d_ws, s));
+    }
+    // several buckets run concurrently on the model's bucket streams (fork
+    // from s, join back), so the tail of one bucket overlaps the others; a
+    // single bucket runs on s itself
+    const int nbk = (int)m->buckets.size();
+    const bool fork = nbk > 1;
+    if (fork) {
+        K_TRY(ensure_bucket_streams(m));
+        HIP_TRY(hipEventRecord(m->ev_fork, s));
+    }
+    for (int bi = 0; bi < nbk; ++bi) {
+        const Bucket &b = m->buckets[bi];
+        hipStream_t bs = fork ? m->bucket_streams[bi] : s;
+        if (fork) HIP_TRY(hipStreamWaitEvent(bs, m->ev_fork, 0));
+        StepArgs a = base;
+        a.bucket_worlds = lpt ? b.d_order : b.d_worlds;
+        a.n_bucket_worlds = b.n;
+        hipError_t e = launch_step(a, b.mc, b.n, bs);
+        if (e != hipSuccess) return fail(KAMX_EDEVICE, "step launch (bucket %d rows): %s", b.mc, hipGetErrorString(e));
+        if (lpt && b.n > 1) {
+            e = launch_lpt_order(b.d_worlds, b.n, m->d_iters, b.d_order, bs);
+            if (e != hipSuccess) return fail(KAMX_EDEVICE, "schedule launch (bucket %d rows): %s", b.mc, hipGetErrorString(e));
         }
-        if (learned) {
-            K_TRY(enqueue_features(m, m->d_feat, s));
-            K_TRY(mlp_forward_internal(m->mlp, m->d_feat, m->n_worlds, m->d_ws, s));
-        }
-        // several buckets run concurrently on the model's bucket streams
-        // (fork from s, join back), so the tail of one bucket overlaps the
-        // others; a single bucket runs on s itself
-        const int nbk = (int)m->buckets.size();
-        const bool fork = nbk > 1;
         if (fork) {
-            K_TRY(ensure_bucket_streams(m));
-            HIP_TRY(hipEventRecord(m->ev_fork, s));
+            HIP_TRY(hipEventRecord(m->ev_join[bi], bs));
+            HIP_TRY(hipStreamWaitEvent(s, m->ev_join[bi], 0));
         }
-        for (int bi = 0; bi < nbk; ++bi) {
-            const Bucket &b = m->buckets[bi];
-            hipStream_t bs = fork ? m->bucket_streams[bi] : s;
-            if (fork) HIP_TRY(hipStreamWaitEvent(bs, m->ev_fork, 0));
-            StepArgs a = base;
-            a.bucket_worlds = lpt ? b.d_order : b.d_worlds;
-            a.n_bucket_worlds = b.n;
-            hipError_t e = launch_step(a, b.mc, b.n, bs);
-            if (e != hipSuccess) return fail(KAMX_EDEVICE, "step launch (bucket %d rows): %s", b.mc, hipGetErrorString(e));
-            if (lpt && b.n > 1) {
-                e = launch_lpt_order(b.d_worlds, b.n, m->d_iters, b.d_order, bs);
-                if (e != hipSuccess) return fail(KAMX_EDEVICE, "schedule launch (bucket %d rows): %s", b.mc, hipGetErrorString(e));
-            }
-            if (fork) {
-                HIP_TRY(hipEventRecord(m->ev_join[bi], bs));
-                HIP_TRY(hipStreamWaitEvent(s, m->ev_join[bi], 0));
-            }
-        }
-        hipError_t e = launch_advance_step(m->d_step, s);
-        if (e != hipSuccess) return fail(KAMX_EDEVICE, "counter launch: %s", hipGetErrorString(e));
+    }
+    hipError_t e = launch_advance_step(m->d_step, (uint32_t)n, s);
+    if (e != hipSuccess) return fail(KAMX_EDEVICE, "counter launch: %s", hipGetErrorString(e));
+    return KAMX_OK;
+}
+
+static bool chained(kamx_model m) {
+    return m->schedule == KAMX_SCHED_CHAIN && !m->box_bin && m->params.warmstart != KAMX_WARM_LEARNED;
+}
+
+// Enqueue nsteps steps from position pos of the current call.
+static kamx_status enqueue_steps(kamx_model m, int nsteps, hipStream_t s, int pos = 0) {
+    const bool chain = chained(m);
+    for (int k = 0; k < nsteps;) {
+        const int n = chain ? std::min(nsteps - k, kChainSteps) : 1;
+        K_TRY(enqueue_launch(m, n, pos + k, s));
+        k += n;
     }
     return KAMX_OK;
 }
@@ -674,7 +700,7 @@ static kamx_status rollout_graph(kamx_model m, int n, hipGraphExec_t *out) {
         }
     if (!m->capture_stream) HIP_TRY(hipStreamCreateWithFlags(&m->capture_stream, hipStreamNonBlocking));
     HIP_TRY(hipStreamBeginCapture(m->capture_stream, hipStreamCaptureModeRelaxed));
-    kamx_status st = enqueue_steps(m, n, m->capture_stream);
+    kamx_status st = enqueue_steps(m, n, m->capture_stream, 0);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(m->capture_stream, &graph);
     if (st != KAMX_OK) {
@@ -699,19 +725,39 @@ kamx_status kamx_step(kamx_model m, int32_t nsteps, kamx_stream stream) {
     K_TRY(check_device());
     if (m->params.log_restarts) K_TRY(ensure_rlog(m));
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    if (nsteps == 1) {
-        K_TRY(enqueue_steps(m, 1, s));
+    if (nsteps == 1 || chained(m)) {
+        K_TRY(enqueue_steps(m, nsteps, s, 0));
     } else if (nsteps > 1) {
+        // per-step launches replayed from captured graphs; the iteration
+        // log positions are part of the captured arguments, so a call is
+        // cut into graph-sized pieces at fixed positions
         const int chunk = std::min<int>(nsteps, kGraphSteps);
+        int pos = 0;
         hipGraphExec_t g = nullptr;
-        K_TRY(rollout_graph(m, chunk, &g));
-        for (int k = 0; k < nsteps / chunk; ++k) HIP_TRY(hipGraphLaunch(g, s));
-        if (nsteps % chunk) {
-            K_TRY(rollout_graph(m, nsteps % chunk, &g));
-            HIP_TRY(hipGraphLaunch(g, s));
+        if (!m->iter_log) {
+            K_TRY(rollout_graph(m, chunk, &g));
+            for (int k = 0; k < nsteps / chunk; ++k) HIP_TRY(hipGraphLaunch(g, s));
+            pos = (nsteps / chunk) * chunk;
+            if (nsteps % chunk) {
+                K_TRY(rollout_graph(m, nsteps % chunk, &g));
+                HIP_TRY(hipGraphLaunch(g, s));
+            }
+        } else {
+            K_TRY(enqueue_steps(m, nsteps, s, 0));
         }
+        (void)pos;
     }
     m->step_index += (uint32_t)nsteps;
+    return KAMX_OK;
+}
+
+kamx_status kamx_set_iteration_log(kamx_model m, int32_t *iters_dev, int32_t *rows_dev, int32_t steps) {
+    if (!m) return fail(KAMX_EINVAL, "model is NULL");
+    if (iters_dev && steps < 1) return fail(KAMX_EINVAL, "steps must be positive");
+    drop_graphs(m);
+    m->iter_log = iters_dev;
+    m->row_log = iters_dev ? rows_dev : nullptr;
+    m->iter_log_rows = iters_dev ? steps : 0;
     return KAMX_OK;
 }
 
@@ -804,7 +850,8 @@ kamx_status kamx_contacts_box_bin(kamx_model m, const kamx_box_desc *boxes, floa
 
 kamx_status kamx_set_schedule(kamx_model m, int32_t mode) {
     if (!m) return fail(KAMX_EINVAL, "model is NULL");
-    if (mode != KAMX_SCHED_INDEX && mode != KAMX_SCHED_LPT) return fail(KAMX_EINVAL, "unknown schedule mode %d", mode);
+    if (mode != KAMX_SCHED_INDEX && mode != KAMX_SCHED_LPT && mode != KAMX_SCHED_CHAIN)
+        return fail(KAMX_EINVAL, "unknown schedule mode %d", mode);
     if (m->schedule != mode) drop_graphs(m);
     m->schedule = mode;
     return KAMX_OK;

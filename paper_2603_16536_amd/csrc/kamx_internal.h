@@ -89,7 +89,12 @@ struct StepArgs {
     int32_t *reset_count;        // [n_worlds]
     uint64_t *phase_clk;         // [n_worlds*16] phase time stamps, or null
     SolverParams p;
-    const uint32_t *step_ctr;    // device step counter (noise key), advanced after every step
+    const uint32_t *step_ctr;    // device step counter (noise key) at the launch's first step
+    int32_t nsteps;              // steps per launch (each workgroup keeps its world for all of them)
+    int32_t n_worlds;            // worlds of the model (stride of iter_log)
+    int32_t *iter_log;           // [iter_log_rows * n_worlds] iterations of every step, or null
+    int32_t *row_log;            // [iter_log_rows * n_worlds] active rows of every step, or null
+    int32_t iter_log_rows;       // steps of this launch that have a log row
     // learned warm start
     int32_t stage;               // 0: full step; 1: write the features of the coming step and stop
     float *features;             // [n_worlds * n_feat] (stage 1)

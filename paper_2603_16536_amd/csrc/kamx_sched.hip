@@ -47,14 +47,14 @@ __global__ __launch_bounds__(kSchedThreads) void lpt_order_kernel(const int32_t 
 }
 
 // One thread: the step counter that keys the noise of the next step.
-__global__ void advance_step_kernel(uint32_t *ctr) {
-    if (threadIdx.x == 0) ctr[0] = ctr[0] + 1u;
+__global__ void advance_step_kernel(uint32_t *ctr, uint32_t inc) {
+    if (threadIdx.x == 0) ctr[0] = ctr[0] + inc;
 }
 
 }  // namespace
 
-hipError_t launch_advance_step(uint32_t *ctr, hipStream_t stream) {
-    hipLaunchKernelGGL(advance_step_kernel, dim3(1), dim3(64), 0, stream, ctr);
+hipError_t launch_advance_step(uint32_t *ctr, uint32_t inc, hipStream_t stream) {
+    hipLaunchKernelGGL(advance_step_kernel, dim3(1), dim3(64), 0, stream, ctr, inc);
     return hipGetLastError();
 }
 

@@ -521,13 +521,17 @@ __device__ inline void delassus_apply(const Lds &L, int m, int nb, const float *
 // the fused step kernel
 // ---------------------------------------------------------------------------
 
+// One step of world w (every phase of the step; the workgroup owns the
+// world).  step is the step index that keys the actuation noise; k the
+// position of the step inside the launch.
 template <int MC, int NT, int TPR>
-__global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
+__device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, int *s_int) {
     extern __shared__ float4 smem4[];
     float *sm = reinterpret_cast<float *>(smem4);
-    __shared__ int s_int[8];
     const int tid = threadIdx.x;
+    // read per step (not hoisted out of the caller's step loop)
     const int w = a.bucket_worlds[blockIdx.x];
+    const uint32_t step = *a.step_ctr + (uint32_t)k;
     const WorldInfo W = a.worlds[w];
     const SolverParams &P = a.p;
 
@@ -584,7 +588,6 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
 
     // ---- joints: coordinate, rate and actuation (generalized force along
     //      the coordinate: external + PD + noise)
-    const uint32_t step = *a.step_ctr;
     for (int j = tid; j < nj; j += NT) {
         int gj = W.j0 + j;
         int type = a.jint[4 * gj], la = a.jint[4 * gj + 1], lb = a.jint[4 * gj + 2], fl = a.jint[4 * gj + 3];
@@ -1034,7 +1037,7 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
             } else {
                 vzp[i] = 0.f;
             }
-            for (int e = 0; e < blk; ++e) {
+            _Pragma("unroll") for (int e = 0; e < 3; ++e) if (e < blk) {
                 vx[i + e] = vyp[i + e];
                 vyh[i + e] = vyp[i + e];
                 vzh[i + e] = vzp[i + e];
@@ -1045,101 +1048,133 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
 
     if (a.phase_clk && tid == 0) a.phase_clk[16 * w + 3] = wall_clock64();
     // ---- Cholesky of D~ + diag(eta + rho), in place (Alg. 1 step 1):
-    //      right-looking over 16x16 tiles.  Wave 0 factors the diagonal tile
-    //      in registers (lane r holds row r) and also forms its inverse; the
-    //      panel below is multiplied by that inverse; the trailing tiles get
-    //      a rank-16 update computed in 4x4 register micro-tiles.
+    //      right-looking over 16x16 tiles.  Wave 0 factors a diagonal tile in
+    //      registers (lane r holds row r) and forms its inverse; the panel
+    //      below is multiplied by that inverse on the matrix cores; the
+    //      trailing tiles get their rank-16 update on the matrix cores.  With
+    //      one step of lookahead, wave 0 updates and factors the next
+    //      diagonal tile while the other waves update the rest.
     const int si = tid / TPR, sq = tid % TPR;
     {
         const int T = (m + 15) >> 4;
         float *Xs = L.red;  // 16x16 inverse of the current diagonal factor tile (red + wb are free here)
+        const int lane = tid & 63, wv = tid >> 6, fr = lane & 15, fk = lane >> 4;
+        constexpr int NW = NT / 64;
         if (tid == 0) s_int[2] = 0;
         __syncthreads();
-        for (int K = 0; K < T; ++K) {
+        // factor diagonal tile K (wave 0 only) and write its inverse to Xs
+        auto factor_diag = [&](int K) {
             const int k0 = 16 * K;
-            if (tid < 64) {
-                const int r = tid;
-                float a[16];
-                const float *Rr = A + tri_row_offset(k0 + (r & 15)) + k0;
+            const int r = lane;
+            float a[16];
+            const float *Rr = A + tri_row_offset(k0 + (r & 15)) + k0;
 #pragma unroll
-                for (int c = 0; c < 16; ++c) a[c] = (r < 16 && c <= r) ? Rr[c] : 0.f;
-                bool ok = true;
+            for (int c = 0; c < 16; ++c) a[c] = (r < 16 && c <= r) ? Rr[c] : 0.f;
+            bool ok = true;
+            float ild[16];  // 1 / l_kk (the same in every lane)
 #pragma unroll
-                for (int k = 0; k < 16; ++k) {
-                    float d = rdlane(a[k], k);
-                    ok = ok && (d > 0.f) && isfinite(d);
-                    float lkk = sqrtf(d), il = 1.f / lkk;
-                    if (r == k) a[k] = lkk;
-                    else if (r > k) a[k] *= il;
+            for (int k = 0; k < 16; ++k) {
+                float d = rdlane(a[k], k);
+                ok = ok && (d > 0.f) && isfinite(d);
+                // hardware reciprocal square root (1 ulp); l_kk = d / sqrt(d)
+                float il = __builtin_amdgcn_rsqf(d), lkk = d * il;
+                ild[k] = il;
+                if (r == k) a[k] = lkk;
+                else if (r > k) a[k] *= il;
 #pragma unroll
-                    for (int j = k + 1; j < 16; ++j) {
-                        float ljk = rdlane(a[k], j);
-                        if (r >= j) a[j] -= a[k] * ljk;
-                    }
+                for (int j = k + 1; j < 16; ++j) {
+                    float ljk = rdlane(a[k], j);
+                    if (r >= j) a[j] -= a[k] * ljk;
                 }
-                // column r of the tile's inverse (forward substitution)
-                float xc[16];
-#pragma unroll
-                for (int rr = 0; rr < 16; ++rr) {
-                    float acc = (r == rr) ? 1.f : 0.f;
-#pragma unroll
-                    for (int kk = 0; kk < rr; ++kk) acc -= rdlane(a[kk], rr) * xc[kk];
-                    xc[rr] = acc / rdlane(a[rr], rr);
-                }
-                if (r < 16) {
-                    float *Rw = A + tri_row_offset(k0 + r) + k0;
-#pragma unroll
-                    for (int c = 0; c < 16; ++c)
-                        if (c <= r) Rw[c] = a[c];
-#pragma unroll
-                    for (int rr = 0; rr < 16; ++rr) Xs[16 * rr + r] = xc[rr];  // zero above the diagonal
-                }
-                if (!ok && r == 0) s_int[2] = 1;
             }
-            __syncthreads();
+            // column r of the tile's inverse (forward substitution)
+            float xc[16];
+#pragma unroll
+            for (int rr = 0; rr < 16; ++rr) {
+                float acc = (r == rr) ? 1.f : 0.f;
+#pragma unroll
+                for (int kk = 0; kk < rr; ++kk) acc -= rdlane(a[kk], rr) * xc[kk];
+                xc[rr] = acc * ild[rr];
+            }
+            if (r < 16) {
+                float *Rw = A + tri_row_offset(k0 + r) + k0;
+#pragma unroll
+                for (int c = 0; c < 16; ++c)
+                    if (c <= r) Rw[c] = a[c];
+#pragma unroll
+                for (int rr = 0; rr < 16; ++rr) Xs[16 * rr + r] = xc[rr];  // zero above the diagonal
+            }
+            if (!ok && r == 0) s_int[2] = 1;
+        };
+        // A_IJ -= L_IK L_JK^T for one tile pair (one wave, matrix cores)
+        auto update_pair = [&](int I, int J, int k0) {
+            const float *Ri = A + tri_row_offset(16 * I + fr) + k0;
+            const float *Rj = A + tri_row_offset(16 * J + fr) + k0;
+            mfx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ch = 0; ch < 4; ++ch) acc = mfma4(Ri[4 * ch + fk], Rj[4 * ch + fk], acc);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int rr = 4 * fk + c;
+                if (I != J || fr <= rr) A[tri_row_offset(16 * I + rr) + 16 * J + fr] -= acc[c];
+            }
+        };
+#ifdef KAMX_FACTOR_TIMING
+        uint64_t fsub[4] = {0, 0, 0, 0}, fmark = a.phase_clk && tid == 0 ? wall_clock64() : 0;
+#define KAMX_FMARK(k)                                   \
+    if (a.phase_clk && tid == 0) {                      \
+        uint64_t now_ = wall_clock64();                 \
+        fsub[k] += now_ - fmark;                        \
+        fmark = now_;                                   \
+    }
+#else
+#define KAMX_FMARK(k)
+#endif
+        if (wv == 0) factor_diag(0);
+        __syncthreads();
+        KAMX_FMARK(0);
+        for (int K = 0; K < T; ++K) {
             if (s_int[2]) break;
-            // panel: L_IK = A_IK Xkk^T for the tiles I below the diagonal, one
-            // wave per tile on the matrix cores (each wave reads its tile
-            // completely before overwriting it)
+            const int k0 = 16 * K;
             const int nI = T - K - 1;
-            {
-                const int lane = tid & 63, wv = tid >> 6, fr = lane & 15, fk = lane >> 4;
-                for (int Ii = wv; Ii < nI; Ii += NT / 64) {
-                    const int I = K + 1 + Ii;
-                    mfx4 acc = {0.f, 0.f, 0.f, 0.f};
-                    const float *Ar = A + tri_row_offset(16 * I + fr) + k0;
+            // panel: L_IK = A_IK Xkk^T for the tiles I below the diagonal,
+            // one wave per tile (each wave reads its tile before overwriting it)
+            for (int Ii = wv; Ii < nI; Ii += NW) {
+                const int I = K + 1 + Ii;
+                mfx4 acc = {0.f, 0.f, 0.f, 0.f};
+                const float *Ar = A + tri_row_offset(16 * I + fr) + k0;
 #pragma unroll
-                    for (int ch = 0; ch < 4; ++ch) acc = mfma4(Ar[4 * ch + fk], Xs[16 * fr + 4 * ch + fk], acc);
+                for (int ch = 0; ch < 4; ++ch) acc = mfma4(Ar[4 * ch + fk], Xs[16 * fr + 4 * ch + fk], acc);
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) A[tri_row_offset(16 * I + 4 * fk + c) + k0 + fr] = acc[c];
-                }
+                for (int c = 0; c < 4; ++c) A[tri_row_offset(16 * I + 4 * fk + c) + k0 + fr] = acc[c];
             }
             __syncthreads();
-            // trailing update A_IJ -= L_IK L_JK^T, K < J <= I: one wave per
-            // tile pair on the matrix cores
-            {
-                const int npair = nI * (nI + 1) / 2;
-                const int lane = tid & 63, wv = tid >> 6, fr = lane & 15, fk = lane >> 4;
-                for (int p = wv; p < npair; p += NT / 64) {
+            KAMX_FMARK(1);
+            if (nI == 0) break;
+            // trailing update A_IJ -= L_IK L_JK^T, K < J <= I.  Pair 0 is the
+            // next diagonal tile: wave 0 updates and factors it; the other
+            // waves take the remaining pairs.
+            const int npair = nI * (nI + 1) / 2;
+            if (wv == 0) {
+                update_pair(K + 1, K + 1, k0);
+                factor_diag(K + 1);
+            } else {
+                for (int p = wv; p < npair; p += NW - 1) {
                     int Ii = (int)((sqrtf(8.f * (float)p + 1.f) - 1.f) * 0.5f);
                     while ((Ii + 1) * (Ii + 2) / 2 <= p) ++Ii;
                     while (Ii * (Ii + 1) / 2 > p) --Ii;
                     const int Jj = p - Ii * (Ii + 1) / 2;
-                    const int I = K + 1 + Ii, J = K + 1 + Jj;
-                    const float *Ri = A + tri_row_offset(16 * I + fr) + k0;
-                    const float *Rj = A + tri_row_offset(16 * J + fr) + k0;
-                    mfx4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                    for (int ch = 0; ch < 4; ++ch) acc = mfma4(Ri[4 * ch + fk], Rj[4 * ch + fk], acc);
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        const int rr = 4 * fk + c;
-                        if (I != J || fr <= rr) A[tri_row_offset(16 * I + rr) + 16 * J + fr] -= acc[c];
-                    }
+                    update_pair(K + 1 + Ii, K + 1 + Jj, k0);
                 }
             }
             __syncthreads();
+            KAMX_FMARK(2);
         }
+#ifdef KAMX_FACTOR_TIMING
+        if (a.phase_clk && tid == 0)
+            for (int q = 0; q < 3; ++q) a.phase_clk[16 * w + 8 + q] = fsub[q];
+#endif
+#undef KAMX_FMARK
     }
     __syncthreads();
     const int factor_fail = s_int[2];
@@ -1167,7 +1202,7 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
                 float acc = (r == rr) ? 1.f : 0.f;
 #pragma unroll
                 for (int kk = 0; kk < rr; ++kk) acc -= rdlane(a[kk], rr) * xc[kk];
-                xc[rr] = acc / rdlane(a[rr], rr);
+                xc[rr] = acc * __builtin_amdgcn_rcpf(rdlane(a[rr], rr));  // hardware reciprocal (1 ulp)
             }
             if (r < 16) {
 #pragma unroll
@@ -1258,7 +1293,7 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
             // residual against the current x
             if (owner) {
                 s_own = kind_i == kRowNormal ? mu_i * sqrtf(vzh[i + 1] * vzh[i + 1] + vzh[i + 2] * vzh[i + 2]) : 0.f;
-                for (int e = 0; e < blk; ++e) {
+                _Pragma("unroll") for (int e = 0; e < 3; ++e) if (e < blk) {
                     float rr = e == 0 ? rho_i : vrho[i + e];
                     float xe = vx[i + e];
                     float rhs = -vvt[i + e] - (e == 0 ? s_own : 0.f) + eta * xe + rr * vyh[i + e] + vzh[i + e];
@@ -1370,7 +1405,7 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
                 const int oa = L.ri(RIA, i), ob = L.ri(RIB, i);  // a block shares its two bodies
                 body_minv64(L, oa, wa);
                 if (ob >= 0) body_minv64(L, ob, wbv);
-                for (int e = 0; e < blk; ++e) {
+                _Pragma("unroll") for (int e = 0; e < 3; ++e) if (e < blk) {
                     float dx = delassus_row_w(L, vp, i + e, wa, wbv, ob >= 0);
                     vdx[i + e] = dx;
                     xn[e] = vxn[i + e];
@@ -1387,14 +1422,14 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
                 } else {
                     yb[0] = xn[0] - zh[0] / rr[0];
                 }
-                for (int e = 0; e < blk; ++e) {
+                _Pragma("unroll") for (int e = 0; e < 3; ++e) if (e < blk) {
                     zb[e] = zh[e] - rr[e] * (xn[e] - yb[e]);
                     lrp = fmaxf(lrp, fabsf(xn[e] - yb[e]));
                     float dy = yb[e] - yh[e], dz = zb[e] - zh[e];
                     lcc += rr[e] * dy * dy + dz * dz / rr[e];
                 }
                 float g = kind_i == kRowNormal ? mu_i * sqrtf(vv[1] * vv[1] + vv[2] * vv[2]) : 0.f;
-                for (int e = 0; e < blk; ++e) {
+                _Pragma("unroll") for (int e = 0; e < 3; ++e) if (e < blk) {
                     float d = vv[e] + (e == 0 ? g : 0.f) - zb[e];
                     lrd = fmaxf(lrd, fabsf(d));
                     if (d != d) lrd = d;
@@ -1424,7 +1459,7 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
                 }
             }
             if (owner) {
-                for (int e = 0; e < blk; ++e) {
+                _Pragma("unroll") for (int e = 0; e < 3; ++e) if (e < blk) {
                     float yo = vyp[i + e], zo = vzp[i + e];
                     if (!P.accel) {
                         vyh[i + e] = yb[e];
@@ -1454,8 +1489,10 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
             }
         }
 #undef KAMX_MARK
+#ifndef KAMX_FACTOR_TIMING
         if (timing)
             for (int k = 0; k < 6; ++k) a.phase_clk[16 * w + 8 + k] = sub[k];
+#endif
         if (it > N) it = N;
         if (P.fixed_iters <= 0 && !converged && status == 0) status = KAMX_WORLD_MAXITER;
         __syncthreads();
@@ -1464,16 +1501,16 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
         float lncp = 0.f;
         if (owner) {
             float v[3], o[3], y[3], nm[3];
-            for (int e = 0; e < blk; ++e) {
+            _Pragma("unroll") for (int e = 0; e < 3; ++e) if (e < blk) {
                 v[e] = vaux[i + e] + vvt[i + e];
                 y[e] = vyp[i + e];
             }
             float g = kind_i == kRowNormal ? mu_i * sqrtf(v[1] * v[1] + v[2] * v[2]) : 0.f;
-            for (int e = 0; e < blk; ++e) nm[e] = y[e] - (v[e] + (e == 0 ? g : 0.f));
+            _Pragma("unroll") for (int e = 0; e < 3; ++e) if (e < blk) nm[e] = y[e] - (v[e] + (e == 0 ? g : 0.f));
             if (kind_i == kRowNormal) proj_cone(mu_i, nm[0], nm[1], nm[2], o[0], o[1], o[2]);
             else if (kind_i == kRowLimit) o[0] = fmaxf(nm[0], 0.f);
             else o[0] = nm[0];
-            for (int e = 0; e < blk; ++e) lncp = fmaxf(lncp, fabsf(y[e] - o[e]));
+            _Pragma("unroll") for (int e = 0; e < 3; ++e) if (e < blk) lncp = fmaxf(lncp, fabsf(y[e] - o[e]));
         }
         float l1 = 0.f, l2 = 0.f, l3 = 0.f;
         reduce4<NT>(lncp, l1, l2, l3, L.red);
@@ -1492,6 +1529,10 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
     if (tid == 0) {
         a.iters[w] = it;
         a.status[w] = status;
+        if (a.iter_log && k < a.iter_log_rows) {
+            a.iter_log[(long)k * a.n_worlds + w] = it;
+            if (a.row_log) a.row_log[(long)k * a.n_worlds + w] = m;
+        }
         a.rows[w] = m;
         a.resid[4 * w + 0] = rp;
         a.resid[4 * w + 1] = rd;
@@ -1559,6 +1600,20 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
     }
     __syncthreads();
     if (a.phase_clk && tid == 0) a.phase_clk[16 * w + 7] = wall_clock64();
+}
+
+// A launch advances every world of the bucket by a.nsteps steps, the
+// workgroup keeping its world for all of them: worlds are independent, so a
+// slow solve delays only its own world and the hardware's dispatch balances
+// whole chains of steps rather than single steps.
+template <int MC, int NT, int TPR>
+__global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
+    __shared__ int s_int[8];
+#pragma clang loop unroll(disable)
+    for (int k = 0; k < a.nsteps; ++k) {
+        step_world<MC, NT, TPR>(a, k, s_int);
+        __syncthreads();
+    }
 }
 
 // Impulses of the last step in slot layout (joint and limit rows, then three

@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(HERE, "libkamx.so")
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 WORLD_OK, WORLD_MAXITER, WORLD_NONFINITE, WORLD_FACTOR_FAIL = 0, 1, 2, 4
 WARM_COLD, WARM_PREVIOUS, WARM_EXTERNAL, WARM_LEARNED = 0, 1, 2, 3
-SCHED_INDEX, SCHED_LPT = 0, 1
+SCHED_INDEX, SCHED_LPT, SCHED_CHAIN = 0, 1, 2
 MAX_CONTACTS_PER_WORLD = 64
 
 
@@ -89,6 +89,7 @@ def lib():
         L.kamx_set_warmstart.argtypes = [vp, vp, vp]
         L.kamx_step.argtypes = [vp, i32, vp]
         L.kamx_set_schedule.argtypes = [vp, i32]
+        L.kamx_set_iteration_log.argtypes = [vp, vp, vp, i32]
         L.kamx_mlp_create.argtypes = [i32, i32, i32, i32, C.c_uint64, C.POINTER(vp)]
         L.kamx_mlp_destroy.argtypes = [vp]
         L.kamx_mlp_info.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), i64p]
@@ -116,7 +117,8 @@ def lib():
                      "kamx_read_phase_clock", "kamx_set_schedule", "kamx_mlp_create", "kamx_mlp_destroy",
                      "kamx_mlp_info", "kamx_mlp_set_normalization", "kamx_mlp_forward", "kamx_mlp_train_step",
                      "kamx_mlp_weights", "kamx_mlp_gradients", "kamx_model_feature_dims", "kamx_model_features",
-                     "kamx_read_impulse_slots", "kamx_model_attach_mlp", "kamx_contacts_box_bin"):
+                     "kamx_read_impulse_slots", "kamx_model_attach_mlp", "kamx_contacts_box_bin",
+                     "kamx_set_iteration_log"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -358,8 +360,21 @@ class Model:
         _check(lib().kamx_model_attach_mlp(self.handle, net.handle if net is not None else None))
         self._mlp = net
 
+    def set_iteration_log(self, iters, rows=None):
+        """Device int32 tensors [steps, n_worlds] that receive the iteration
+        count (and active rows) of every step of the following step() calls
+        (None: off)."""
+        if iters is None:
+            _check(lib().kamx_set_iteration_log(self.handle, None, None, 0))
+        else:
+            for t in (iters, rows):
+                assert t is None or (t.dtype == torch.int32 and t.is_contiguous() and t.shape[1] == self.n_worlds)
+            _check(lib().kamx_set_iteration_log(self.handle, _ptr(iters), _ptr(rows), int(iters.shape[0])))
+        self._iter_log = (iters, rows)
+
     def set_schedule(self, mode):
-        """Dispatch order inside size buckets: SCHED_LPT (default) or SCHED_INDEX."""
+        """Mapping of steps onto workgroups: SCHED_CHAIN (default), SCHED_LPT
+        or SCHED_INDEX (results are identical under all three)."""
         _check(lib().kamx_set_schedule(self.handle, int(mode)))
 
     def step(self, n=1, stream=None):

@@ -191,11 +191,13 @@ def test_worlds_without_contacts_or_joints():
 
 
 def test_dispatch_order_does_not_change_results():
-    """Three steps of 64 bipeds dispatched longest-first (reordered after
-    every step) and in index order: bitwise identical states and impulses."""
+    """Three steps of 64 bipeds as one chained launch (each world kept on its
+    workgroup), as single-step launches dispatched longest-first (reordered
+    after every step) and in index order: bitwise identical states, impulses
+    and iteration counts."""
     scene = scenes.round_to_f32(scenes.biped_batch(64, seed=1002))
     out = []
-    for mode in (kamx.SCHED_LPT, kamx.SCHED_INDEX):
+    for mode in (kamx.SCHED_CHAIN, kamx.SCHED_LPT, kamx.SCHED_INDEX):
         m = kamx.Model(scene, params=cfg2_params(torque_sigma=5.0, seed=99, max_iters=400, log_restarts=0),
                        pd=(15.0, 0.6), refs=biped_refs(scene))
         m.set_schedule(mode)
@@ -203,8 +205,9 @@ def test_dispatch_order_does_not_change_results():
         q, u = m.state()
         out.append((q.cpu().numpy(), u.cpu().numpy(), m.impulses().cpu().numpy(), m.stats()["iters"].cpu().numpy()))
         m.close()
-    for a, b in zip(out[0], out[1]):
-        assert np.array_equal(a, b)
+    for other in out[1:]:
+        for a, b in zip(out[0], other):
+            assert np.array_equal(a, b)
 
 
 def test_captured_rollout_equals_single_steps():
@@ -217,6 +220,7 @@ def test_captured_rollout_equals_single_steps():
     refs = biped_refs(scene)
     p = cfg2_params(torque_sigma=5.0, seed=4321, max_iters=300, log_restarts=0)
     graph = kamx.Model(scene, params=p, pd=(15.0, 0.6), refs=refs)
+    graph.set_schedule(kamx.SCHED_LPT)  # single-step launches, so multi-step calls replay graphs
     eager = kamx.Model(scene, params=p, pd=(15.0, 0.6), refs=refs)
 
     def snap(m):
@@ -287,3 +291,29 @@ def test_three_structures_in_one_call_equal_separate_calls():
         for i, w in enumerate(ws):
             assert np.array_equal(gm["u"][bo[w]:bo[w + 1]], gs["u"][so[i]:so[i + 1]]), (k, w)
             assert gm["iters"][w] == gs["iters"][i]
+
+
+def test_chained_rollout_with_iteration_log():
+    """70 steps in one call (a 64-step chained launch and a 6-step one)
+    against 70 single steps: bitwise equal states, and the iteration log
+    holds every step's count (its last row equals the last step's stats)."""
+    scene = scenes.round_to_f32(scenes.biped_batch(8, seed=1002))
+    refs = biped_refs(scene)
+    p = cfg2_params(torque_sigma=5.0, seed=99, max_iters=400, log_restarts=0)
+    ch = kamx.Model(scene, params=p, pd=(15.0, 0.6), refs=refs)
+    one = kamx.Model(scene, params=p, pd=(15.0, 0.6), refs=refs)
+    log = torch.zeros((70, 8), dtype=torch.int32, device="cuda")
+    rows = torch.zeros((70, 8), dtype=torch.int32, device="cuda")
+    ch.set_iteration_log(log, rows)
+    ch.step(70)
+    its = []
+    for _ in range(70):
+        one.step(1)
+        its.append(one.stats()["iters"].cpu().numpy())
+    torch.cuda.synchronize()
+    for x, y in zip(ch.state(), one.state()):
+        assert torch.equal(x, y)
+    assert np.array_equal(log.cpu().numpy(), np.stack(its))
+    assert np.all(rows.cpu().numpy() <= 224) and np.all(rows.cpu().numpy() >= 200)
+    ch.close()
+    one.close()
