@@ -395,9 +395,12 @@ kamx_status kamx_read_impulse_slots(kamx_model m, float *y_dev, kamx_stream stre
  * batch capacity >= n_worlds; NULL detaches.  The model keeps the pointer
  * (the caller keeps the network alive while steps use it); its weights may
  * change between steps.  With the network attached and warmstart LEARNED,
- * every step runs the feature pass, the network, then the solve warm
- * started from the prediction by slot (Alg. 1 step 2 with the previous-step
- * cache replaced by the prediction). */
+ * every step of every world evaluates the network inside the step kernel
+ * (features as in kamx_model_features, the batched kernels' matrix-core
+ * operand layout and accumulation order, so the prediction equals
+ * kamx_mlp_forward's bit for bit) and warm starts the solve from the
+ * prediction by slot (Alg. 1 step 2 with the previous-step cache replaced
+ * by the prediction).  Works in chained launches too. */
 kamx_status kamx_model_attach_mlp(kamx_model m, kamx_mlp net);
 
 /* Message of the last failed call on this thread ("" if none). */

@@ -24,7 +24,7 @@ int box_bin_max_boxes();
 hipError_t launch_impulse_slots(const WorldInfo *worlds, int n_worlds, int n_contact_slots, int n_slots,
                                 const float *lambda, const int32_t *keys, const int32_t *ncontacts, float *out,
                                 hipStream_t stream);
-kamx_status mlp_forward_internal(kamx_mlp n, const float *x, int batch, float *y, hipStream_t s);
+MlpView mlp_view(kamx_mlp n);
 int mlp_n_in(kamx_mlp n);
 int mlp_n_out(kamx_mlp n);
 int mlp_capacity(kamx_mlp n);
@@ -107,7 +107,7 @@ struct kamx_model_s {
     bool uniform = false;
     int n_feat = 0, n_slots = 0, n_contact_slots = 0;
     kamx_mlp mlp = nullptr;
-    float *d_feat = nullptr, *d_ws = nullptr;
+    float *d_ws = nullptr;  // network prediction by slot [n_worlds * n_slots]
     // generated contacts (boxes in a bin)
     bool box_bin = false;
     float bin_wx = 0.f, bin_wy = 0.f, bin_margin = 0.f;
@@ -586,6 +586,7 @@ static StepArgs step_args(kamx_model m) {
     a.stage = 0;
     a.n_feat = m->n_feat;
     a.ws_slots = m->d_ws;
+    if (m->mlp) a.mlp = mlp_view(m->mlp);
     a.n_contact_slots = m->n_contact_slots;
     return a;
 }
@@ -639,10 +640,6 @@ static kamx_status enqueue_launch(kamx_model m, int n, int pos, hipStream_t s) {
                                       m->bin_margin, m->d_gen, m->d_gen_count, s);
         if (e != hipSuccess) return fail(KAMX_EDEVICE, "contact generation launch: %s", hipGetErrorString(e));
     }
-    if (m->params.warmstart == KAMX_WARM_LEARNED) {
-        K_TRY(enqueue_features(m, m->d_feat, s));
-        K_TRY(mlp_forward_internal(m->mlp, m->d_feat, m->n_worlds, m->d_ws, s));
-    }
     // several buckets run concurrently on the model's bucket streams (fork
     // from s, join back), so the tail of one bucket overlaps the others; a
     // single bucket runs on s itself
@@ -675,9 +672,7 @@ static kamx_status enqueue_launch(kamx_model m, int n, int pos, hipStream_t s) {
     return KAMX_OK;
 }
 
-static bool chained(kamx_model m) {
-    return m->schedule == KAMX_SCHED_CHAIN && !m->box_bin && m->params.warmstart != KAMX_WARM_LEARNED;
-}
+static bool chained(kamx_model m) { return m->schedule == KAMX_SCHED_CHAIN && !m->box_bin; }
 
 // Enqueue nsteps steps from position pos of the current call.
 static kamx_status enqueue_steps(kamx_model m, int nsteps, hipStream_t s, int pos = 0) {
@@ -799,10 +794,7 @@ kamx_status kamx_model_attach_mlp(kamx_model m, kamx_mlp net) {
                     m->n_feat, m->n_slots);
     if (mlp_capacity(net) < m->n_worlds)
         return fail(KAMX_EINVAL, "network batch capacity %d below %d worlds", mlp_capacity(net), m->n_worlds);
-    if (!m->d_feat) {
-        K_TRY(dalloc(m, &m->d_feat, (size_t)m->n_worlds * m->n_feat));
-        K_TRY(dalloc(m, &m->d_ws, (size_t)m->n_worlds * m->n_slots));
-    }
+    if (!m->d_ws) K_TRY(dalloc(m, &m->d_ws, (size_t)m->n_worlds * m->n_slots));
     m->mlp = net;
     return KAMX_OK;
 }

@@ -52,6 +52,29 @@ struct SolverParams {
     int32_t log_restarts;
 };
 
+// ---- learned warm start: numerics shared by the batched network kernels
+// and the per-world inference inside the step kernel, so both produce the
+// same bits
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ inline float gelu(float z) { return 0.5f * z * (1.f + erff(z * 0.70710678118654752f)); }
+
+__device__ inline float gelu_grad(float z) {
+    return 0.5f * (1.f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
+}
+
+__device__ inline __bf16 to_bf16(float v) { return (__bf16)v; }
+
+// Device view of a network's parameters (BF16 weights row-major
+// [out][in_pad], FP32 biases and standardisation).
+struct MlpView {
+    const __bf16 *w1, *w2, *w3;
+    const float *b1, *b2, *b3;
+    const float *mu_in, *s_in, *mu_out, *sd_out;
+    int32_t n_in, fp, H, n_out, op;
+};
+
 struct StepArgs {
     const WorldInfo *worlds;
     const int32_t *bucket_worlds;  // worlds handled by this launch
@@ -99,7 +122,8 @@ struct StepArgs {
     int32_t stage;               // 0: full step; 1: write the features of the coming step and stop
     float *features;             // [n_worlds * n_feat] (stage 1)
     int32_t n_feat;
-    const float *ws_slots;       // network output [n_worlds * slots] (warm start mode LEARNED)
+    float *ws_slots;             // network output [n_worlds * slots] (warm start mode LEARNED)
+    MlpView mlp;                 // the network, run inside the step for warm start mode LEARNED
     int32_t n_contact_slots;     // contact keys with a slot (probes per world, else contact capacity)
 };
 

@@ -20,9 +20,6 @@
 
 namespace kamx {
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-
 namespace {
 
 constexpr int kTileM = 64, kTileN = 64, kTileK = 32;
@@ -49,13 +46,6 @@ struct EpiArgs {
     const float *mu, *sigma;
 };
 
-__device__ inline float gelu(float z) { return 0.5f * z * (1.f + erff(z * 0.70710678118654752f)); }
-
-__device__ inline float gelu_grad(float z) {
-    return 0.5f * (1.f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
-}
-
-__device__ inline __bf16 to_bf16(float v) { return (__bf16)v; }
 
 // Stage a 64 x 32 tile of an operand (rows i0.., columns k0..) into LDS as
 // [row][k] so that every matrix-core operand is one 16-byte LDS read.
@@ -121,7 +111,7 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_kernel(Operand A, Operand B
                 } else if (EPI == kEpiOut) {
                     float yn = v + e.bias[n];
                     if (e.f32) e.f32[m * e.ld + n] = yn;
-                    if (e.y && m < e.batch && n < e.n_out) e.y[m * e.ldy + n] = e.mu[n] + e.sigma[n] * yn;
+                    if (e.y && m < e.batch && n < e.n_out) e.y[m * e.ldy + n] = __builtin_fmaf(e.sigma[n], yn, e.mu[n]);
                 } else if (EPI == kEpiBackward) {
                     float dz = v * gelu_grad(e.z[m * e.ld + n]);
                     e.f32[m * e.ld + n] = dz;
@@ -474,6 +464,25 @@ kamx_status mlp_forward_internal(kamx_mlp n, const float *x, int batch, float *y
     return mlp_forward_rows(n, x, n->n_in, batch, y, n->n_out, false, s);
 }
 int mlp_n_in(kamx_mlp n) { return n->n_in; }
+MlpView mlp_view(kamx_mlp n) {
+    MlpView v;
+    v.w1 = n->wb + n->L.bW1;
+    v.w2 = n->wb + n->L.bW2;
+    v.w3 = n->wb + n->L.bW3;
+    v.b1 = n->w + n->L.ob1;
+    v.b2 = n->w + n->L.ob2;
+    v.b3 = n->w + n->L.ob3;
+    v.mu_in = n->mu_in;
+    v.s_in = n->s_in;
+    v.mu_out = n->mu_out;
+    v.sd_out = n->sd_out;
+    v.n_in = n->n_in;
+    v.fp = n->fp;
+    v.H = n->H;
+    v.n_out = n->n_out;
+    v.op = n->op;
+    return v;
+}
 int mlp_n_out(kamx_mlp n) { return n->n_out; }
 int mlp_capacity(kamx_mlp n) { return n->cap; }
 }  // namespace kamx

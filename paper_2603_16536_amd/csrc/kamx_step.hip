@@ -620,20 +620,19 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
     // ---- feature pass of the learned warm start: the state the step starts
     //      from (positions relative to the reset body), the previous step's
     //      impulses by slot and the generalized forces of this step
-    if (a.stage == 1) {
-        float *f = a.features + (long)w * a.n_feat;
+    // feature t of this world (same layout as kamx_model_features)
+    auto feature = [&](int t) -> float {
         const int rb = W.reset_body;
-        for (int t = tid; t < 13 * nb; t += NT) {
-            const int b = t / 13, c = t - 13 * (t / 13);
-            float v;
-            if (c < 3) v = L.bf(BQ + c, b) - (rb >= 0 ? L.bf(BQ + c, rb) : 0.f);
-            else if (c < 7) v = L.bf(BQ + c, b);
-            else v = L.bf(BU + c - 7, b);
-            f[t] = v;
-        }
         const int rc0 = 5 * nj + W.nlim;
         const int S = rc0 + 3 * a.n_contact_slots;
-        for (int t = tid; t < S; t += NT) {
+        if (t < 13 * nb) {
+            const int b = t / 13, c = t - 13 * (t / 13);
+            if (c < 3) return L.bf(BQ + c, b) - (rb >= 0 ? L.bf(BQ + c, rb) : 0.f);
+            if (c < 7) return L.bf(BQ + c, b);
+            return L.bf(BU + c - 7, b);
+        }
+        t -= 13 * nb;
+        if (t < S) {
             float v = 0.f;
             if (!reset) {
                 if (t < rc0) {
@@ -641,17 +640,59 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
                 } else {
                     const int key = (t - rc0) / 3, e = (t - rc0) - 3 * ((t - rc0) / 3);
                     const int nprev = a.ncontacts_out[w];
-                    for (int k = 0; k < nprev && k < kMaxContacts; ++k)
-                        if (a.keys[w * kMaxContacts + k] == key) {
-                            v = a.lambda[W.row_base + rc0 + 3 * k + e];
+                    for (int q = 0; q < nprev && q < kMaxContacts; ++q)
+                        if (a.keys[w * kMaxContacts + q] == key) {
+                            v = a.lambda[W.row_base + rc0 + 3 * q + e];
                             break;
                         }
                 }
             }
-            f[13 * nb + t] = v;
+            return v;
         }
-        for (int j = tid; j < nj; j += NT) f[13 * nb + S + j] = L.jfld(JTAU, j);
+        return L.jfld(JTAU, t - S);
+    };
+    if (a.stage == 1) {
+        float *f = a.features + (long)w * a.n_feat;
+        for (int t = tid; t < a.n_feat; t += NT) f[t] = feature(t);
         return;
+    }
+
+    // ---- learned warm start: the network predicts this world's impulses by
+    //      slot, on the matrix cores with the batched kernels' operand layout
+    //      and accumulation order (so the prediction has the same bits); the
+    //      features are row 0 of the 16-row operand, the other rows zero.
+    //      The triangle region of LDS is free until the Delassus assembly.
+    if (P.warmstart == KAMX_WARM_LEARNED && !reset) {
+        const MlpView &N = a.mlp;
+        __bf16 *xh = reinterpret_cast<__bf16 *>(A);
+        __bf16 *h1 = xh + N.fp;
+        __bf16 *h2 = h1 + N.H;
+        for (int t = tid; t < N.fp; t += NT) xh[t] = to_bf16(t < N.n_in ? (feature(t) - N.mu_in[t]) * N.s_in[t] : 0.f);
+        __syncthreads();
+        const int lane = tid & 63, wv = tid >> 6, fr = lane & 15, fk = (lane >> 4) * 8;
+        constexpr int NW = NT / 64;
+        const bf16x8 zero8 = {};
+        auto layer = [&](const __bf16 *x, int K, const __bf16 *Wt, int nout_pad, auto &&epilogue) {
+            for (int t = wv; t < nout_pad / 16; t += NW) {
+                floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+                const __bf16 *wrow = Wt + (long)(16 * t + fr) * K + fk;
+                for (int k0 = 0; k0 < K; k0 += 32) {
+                    const bf16x8 av = fr == 0 ? *reinterpret_cast<const bf16x8 *>(x + k0 + fk) : zero8;
+                    const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(wrow + k0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+                }
+                if (fk == 0) epilogue(16 * t + fr, acc[0]);  // row 0 of the block: lanes 0-15, component 0
+            }
+        };
+        layer(xh, N.fp, N.w1, N.H, [&](int n, float v) { h1[n] = to_bf16(gelu(v + N.b1[n])); });
+        __syncthreads();
+        layer(h1, N.H, N.w2, N.H, [&](int n, float v) { h2[n] = to_bf16(gelu(v + N.b2[n])); });
+        __syncthreads();
+        float *ws = a.ws_slots + (long)w * N.n_out;
+        layer(h2, N.H, N.w3, N.op, [&](int n, float v) {
+            if (n < N.n_out) ws[n] = __builtin_fmaf(N.sd_out[n], v + N.b3[n], N.mu_out[n]);
+        });
+        __syncthreads();
     }
 
     // ---- free velocity of every body: u_f = u + dt M^-1 h
@@ -986,7 +1027,7 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
             } else if (wmode == KAMX_WARM_LEARNED) {
                 // network output by slot: joint and limit rows in order, then
                 // three slots per contact key
-                const float *ws = a.ws_slots + (long)w * (row_c0 + 3 * a.n_contact_slots);
+                const float *ws = a.ws_slots + (long)w * a.mlp.n_out;
                 if (i < row_c0) {
                     lw = ws[i];
                 } else {

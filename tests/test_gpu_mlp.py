@@ -313,3 +313,34 @@ def test_learned_warm_start_equals_external_and_matches_oracle():
     for m in (A, B, Cm, D):
         m.close()
     net.close()
+
+
+def test_learned_warm_start_in_chained_launches():
+    """Five steps with the network's warm start as one chained launch and as
+    five single-step launches: bitwise equal states and iteration counts;
+    the prediction inside the step equals the batched network's."""
+    import torch
+    p = dict(BIPED, log_restarts=0, warmstart=kamx.WARM_LEARNED)
+    n = 16
+    scene, A = biped_model(n, p)
+    _, B = biped_model(n, p)
+    nf, ns = A.feature_dims()
+    net = kamx.MLP(nf, ns, n_hidden=256, max_batch=n, seed=12)
+    net.set_normalization(np.zeros(nf), np.ones(nf) * 5.0, np.zeros(ns), np.ones(ns) * 0.01)
+    A.attach_mlp(net)
+    B.attach_mlp(net)
+    B.set_schedule(kamx.SCHED_LPT)
+    log = torch.zeros((5, n), dtype=torch.int32, device="cuda")
+    A.set_iteration_log(log)
+    A.step(5)
+    its = []
+    for _ in range(5):
+        B.step(1)
+        its.append(B.stats()["iters"].cpu().numpy())
+    torch.cuda.synchronize()
+    for x, y in zip(A.state(), B.state()):
+        assert torch.equal(x, y)
+    assert np.array_equal(log.cpu().numpy(), np.stack(its))
+    A.close()
+    B.close()
+    net.close()
