@@ -229,7 +229,7 @@ def main():
     ap.add_argument("--workload", choices=tuple(WORKLOADS), default="biped",
                     help="biped (headline), hetero (four-bar/biped/excavator mix) or boxbin")
     ap.add_argument("--train-steps", type=int, default=250, help="steps of the cold rollout that feeds training")
-    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--epochs", type=int, default=60)
     ap.add_argument("--schedule", choices=("chain", "lpt", "index"), default="chain",
                     help="chained multi-step launches, or one launch per step ordered longest-first or by index")
     ap.add_argument("--calibrate-copy", action="store_true",

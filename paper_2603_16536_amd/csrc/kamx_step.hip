@@ -418,12 +418,40 @@ __device__ inline void reduce4(float &m0, float &m1, float &m2, float &s3, float
 // every x-update and for the dual residual.
 // ---------------------------------------------------------------------------
 
+// Lane permutations inside a row of 16 lanes (DPP): swap neighbours
+// (lane ^ 1), swap pairs (lane ^ 2), mirror within 8 and within 16 lanes.
+// Every lane of the wave must be active where these are used.
+enum { kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppMirror8 = 0x141, kDppMirror16 = 0x140 };
+
+template <int CTRL>
+__device__ inline float dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+template <int CTRL>
+__device__ inline double dpp(double v) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(u & 0xffffffffll), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over aligned groups of 2, 4, 8 or 16 lanes; every lane of a group
+// ends with the same bits (each step adds two values that the partner adds
+// in the other order).
+template <int G, typename T>
+__device__ inline T lane_group_sum(T v) {
+    if (G >= 2) v += dpp<kDppXor1>(v);
+    if (G >= 4) v += dpp<kDppXor2>(v);
+    if (G >= 8) v += dpp<kDppMirror8>(v);
+    if (G >= 16) v += dpp<kDppMirror16>(v);
+    return v;
+}
+
 // Sum over the TPR lanes that share a row (fixed butterfly order).
 template <int TPR, typename T>
 __device__ inline T group_sum(T v) {
-    if (TPR >= 2) v += __shfl_xor(v, 1, 64);
-    if (TPR >= 4) v += __shfl_xor(v, 2, 64);
-    return v;
+    return lane_group_sum<TPR>(v);
 }
 
 // Broadcast a lane's value to the whole wave (lane index uniform).
@@ -453,24 +481,33 @@ __device__ inline float tri_at(const float *A, int r, int c) { return c <= r ? A
 // rows in increasing order.  Ends with a barrier.
 template <int NT, int TPR>
 __device__ inline void delassus_gather(const Lds &L, int nb, const float *vp, const float *x) {
+    // two adjacent threads per (body, component) take alternate rows of the
+    // incidence list; their partial sums meet by one shuffle
     const int tid = threadIdx.x;
-    for (int t = tid; t < 6 * nb; t += NT) {
-        const int b = t / 6, c = t - 6 * (t / 6);
+    const int ntask = 12 * nb;
+    for (int t0 = 0; t0 < ntask; t0 += NT) {
+        const int t = t0 + tid;
+        const int bc = t >> 1, h = t & 1;
+        const int b = bc / 6, c = bc - 6 * (bc / 6);
         double g0 = 0.0, g1 = 0.0;
-        int k = L.inc_off[b];
-        const int k1 = L.inc_off[b + 1];
-        for (; k + 1 < k1; k += 2) {
-            int e0 = L.inc_list[k], e1 = L.inc_list[k + 1];
-            int r0 = e0 >> 1, r1 = e1 >> 1;
-            g0 += (double)L.rf(RJ + 6 * (e0 & 1) + c, r0) * ((double)vp[r0] * (double)x[r0]);
-            g1 += (double)L.rf(RJ + 6 * (e1 & 1) + c, r1) * ((double)vp[r1] * (double)x[r1]);
+        if (t < ntask) {
+            int k = L.inc_off[b] + h;
+            const int k1 = L.inc_off[b + 1];
+            for (; k + 2 < k1; k += 4) {
+                int e0 = L.inc_list[k], e1 = L.inc_list[k + 2];
+                int r0 = e0 >> 1, r1 = e1 >> 1;
+                g0 += (double)L.rf(RJ + 6 * (e0 & 1) + c, r0) * ((double)vp[r0] * (double)x[r0]);
+                g1 += (double)L.rf(RJ + 6 * (e1 & 1) + c, r1) * ((double)vp[r1] * (double)x[r1]);
+            }
+            if (k < k1) {
+                int e0 = L.inc_list[k];
+                int r0 = e0 >> 1;
+                g0 += (double)L.rf(RJ + 6 * (e0 & 1) + c, r0) * ((double)vp[r0] * (double)x[r0]);
+            }
         }
-        if (k < k1) {
-            int e0 = L.inc_list[k];
-            int r0 = e0 >> 1;
-            g0 += (double)L.rf(RJ + 6 * (e0 & 1) + c, r0) * ((double)vp[r0] * (double)x[r0]);
-        }
-        L.wb[c * kMaxBodies + b] = g0 + g1;
+        // partner lane (t ^ 1) is the DPP neighbour in the same wave
+        const double gs = lane_group_sum<2>(g0 + g1);
+        if (t < ntask && h == 0) L.wb[c * kMaxBodies + b] = gs;
     }
     __syncthreads();
 }
@@ -1379,56 +1416,75 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
             }
             __syncthreads();
             KAMX_MARK(2);
-            // x_new = x + X^T t: columns j and m-1-j paired the same way; the
-            // 16 pairs of a wave walk the same rows (consecutive reads); loads
-            // are issued for every row of the walk (in bounds) and masked;
-            // row offsets advance incrementally, four chains per column
+            // x_new = x + X^T t over column quads: quads c and Q-1-c form a
+            // pair (balanced: together they span m + 4 rows); 16 threads per
+            // pair take every 16th row, each reading the row's 4 entries of
+            // the quad as one float4; butterfly sum over the 16 threads
             {
-                float s1 = 0.f, s2 = 0.f;
-                const int p = tid >> 2, q = tid & 3;
-                const int j1 = p, j2 = m - 1 - p;
-                const int pw = p & ~15;  // first pair of this wave
-                if (j1 <= j2 && j1 < m) {
+                const int Q = (m + 3) >> 2;
+                const int g = tid >> 4, kq = tid & 15;
+                const int c1 = g, c2 = Q - 1 - g;
+                float4 s1 = make_float4(0.f, 0.f, 0.f, 0.f), s2 = s1;
+                if (c1 <= c2) {
 #pragma unroll
                     for (int part = 0; part < 2; ++part) {
-                        const int jc = part == 0 ? j1 : j2;
-                        if (part == 1 && j2 == j1) break;
-                        int rs = part == 0 ? pw : m - 1 - (pw + 15);
-                        if (rs < 0) rs = 0;
-                        int r = rs + q;
-                        // rows r, r+4, r+8, r+12 share r & 3; offsets grow by 16a + 16 + 4b
-                        const int bq = r & 3;
-                        int aq = r >> 2;
-                        int off = tri_row_offset(r);
-                        float c0 = 0.f, c1 = 0.f, c2 = 0.f, c3 = 0.f;
-                        for (; r + 12 < m; r += 16) {
-                            const int o1 = off + 16 * aq + 16 + 4 * bq;
-                            const int o2 = o1 + 16 * (aq + 1) + 16 + 4 * bq;
-                            const int o3 = o2 + 16 * (aq + 2) + 16 + 4 * bq;
-                            float x0 = A[off + jc], x1 = A[o1 + jc], x2 = A[o2 + jc], x3 = A[o3 + jc];
-                            float v0 = vt[r], v1 = vt[r + 4], v2 = vt[r + 8], v3 = vt[r + 12];
-                            c0 += (r >= jc ? x0 : 0.f) * v0;
-                            c1 += (r + 4 >= jc ? x1 : 0.f) * v1;
-                            c2 += (r + 8 >= jc ? x2 : 0.f) * v2;
-                            c3 += (r + 12 >= jc ? x3 : 0.f) * v3;
-                            off = o3 + 16 * (aq + 3) + 16 + 4 * bq;
-                            aq += 4;
+                        if (part == 1 && c2 == c1) break;
+                        const int c = part == 0 ? c1 : c2;
+                        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f), acc2 = acc;
+                        int r = 4 * c + kq;
+                        // packed rows are padded to 4 floats and the pads hold 0,
+                        // so the quad that contains the diagonal reads as-is
+                        for (; r + 16 < m; r += 32) {
+                            const float4 xa = *reinterpret_cast<const float4 *>(A + tri_row_offset(r) + 4 * c);
+                            const float4 xb = *reinterpret_cast<const float4 *>(A + tri_row_offset(r + 16) + 4 * c);
+                            const float ta = vt[r], tb = vt[r + 16];
+                            acc.x += xa.x * ta;
+                            acc.y += xa.y * ta;
+                            acc.z += xa.z * ta;
+                            acc.w += xa.w * ta;
+                            acc2.x += xb.x * tb;
+                            acc2.y += xb.y * tb;
+                            acc2.z += xb.z * tb;
+                            acc2.w += xb.w * tb;
                         }
-                        for (; r < m; r += 4) {
-                            float x0 = A[off + jc];
-                            c0 += (r >= jc ? x0 : 0.f) * vt[r];
-                            off += 16 * aq + 16 + 4 * bq;
-                            aq += 1;
+                        if (r < m) {
+                            const float4 xa = *reinterpret_cast<const float4 *>(A + tri_row_offset(r) + 4 * c);
+                            const float ta = vt[r];
+                            acc.x += xa.x * ta;
+                            acc.y += xa.y * ta;
+                            acc.z += xa.z * ta;
+                            acc.w += xa.w * ta;
                         }
-                        if (part == 0) s1 = (c0 + c1) + (c2 + c3);
-                        else s2 = (c0 + c1) + (c2 + c3);
+                        acc.x += acc2.x;
+                        acc.y += acc2.y;
+                        acc.z += acc2.z;
+                        acc.w += acc2.w;
+                        if (part == 0) s1 = acc;
+                        else s2 = acc;
                     }
                 }
-                s1 = group_sum<4>(s1);
-                s2 = group_sum<4>(s2);
-                if (q == 0 && j1 <= j2 && j1 < m) {
-                    vxn[j1] = vx[j1] + s1;
-                    if (j2 > j1) vxn[j2] = vx[j2] + s2;
+                s1.x = lane_group_sum<16>(s1.x);
+                s1.y = lane_group_sum<16>(s1.y);
+                s1.z = lane_group_sum<16>(s1.z);
+                s1.w = lane_group_sum<16>(s1.w);
+                s2.x = lane_group_sum<16>(s2.x);
+                s2.y = lane_group_sum<16>(s2.y);
+                s2.z = lane_group_sum<16>(s2.z);
+                s2.w = lane_group_sum<16>(s2.w);
+                if (kq == 0 && c1 <= c2) {
+                    const float a1[4] = {s1.x, s1.y, s1.z, s1.w}, a2[4] = {s2.x, s2.y, s2.z, s2.w};
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int j = 4 * c1 + e;
+                        if (j < m) vxn[j] = vx[j] + a1[e];
+                    }
+                    if (c2 > c1) {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const int j = 4 * c2 + e;
+                            if (j < m) vxn[j] = vx[j] + a2[e];
+                        }
+                    }
                 }
             }
             __syncthreads();

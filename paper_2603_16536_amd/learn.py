@@ -32,8 +32,14 @@ def collect(model, steps, device="cuda:0"):
 
 
 def normalization(X, Y):
-    """Per-column mean and standard deviation of inputs and targets."""
-    return X.mean(dim=0), X.std(dim=0), Y.mean(dim=0), Y.std(dim=0)
+    """Per-column mean and standard deviation of inputs and targets.  An
+    input's spread is floored at 1e-3 of its root-mean-square value, so
+    nearly constant columns (quaternion components of bodies that hardly
+    turn) are not scaled up to their rounding noise."""
+    mu, sd = X.mean(dim=0), X.std(dim=0)
+    rms = torch.sqrt(mu * mu + sd * sd)
+    sd = torch.sqrt(sd * sd + (1e-3 * rms) ** 2 + 1e-12)
+    return mu, sd, Y.mean(dim=0), Y.std(dim=0)
 
 
 def train(net, X, Y, epochs=20, batch=4096, lr=1e-3, lr_final=1e-5, seed=0, log=None):
@@ -76,7 +82,7 @@ def validation_loss(net, X, Y, batch=4096):
     return se / max(cnt, 1)
 
 
-def fit(model_factory, train_steps, epochs=20, batch=4096, lr=1e-3, seed=0, n_hidden=256, log=None):
+def fit(model_factory, train_steps, epochs=60, batch=4096, lr=1e-3, seed=0, n_hidden=256, log=None):
     """Collect a cold rollout from ``model_factory()`` and train a network
     on it.  Returns (net, info)."""
     m = model_factory()

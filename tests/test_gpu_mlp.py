@@ -344,3 +344,38 @@ def test_learned_warm_start_in_chained_launches():
     A.close()
     B.close()
     net.close()
+
+
+def test_trained_network_cuts_iterations():
+    """Train the network on a short cold rollout (noise seed 2002), then run
+    a rollout with a fresh noise seed cold and warm started by the network:
+    fewer iterations with the network (the answer itself is held to the
+    same residual tolerance either way)."""
+    import torch
+    from paper_2603_16536_amd import learn
+    n, steps = 1024, 60
+    base = dict(BIPED, log_restarts=0, seed=2002)
+
+    def make(seed, warm):
+        sc = scenes.round_to_f32(scenes.biped_batch(n, seed=1002))
+        return kamx.Model(sc, params=dict(base, seed=seed, warmstart=warm), pd=(15.0, 0.6),
+                          refs=np.zeros(sc.n_joints))
+
+    net, info = learn.fit(lambda: make(2002, kamx.WARM_COLD), steps, epochs=30, batch=1024, seed=3)
+    iters = {}
+    for name, warm in (("cold", kamx.WARM_COLD), ("learned", kamx.WARM_LEARNED)):
+        m = make(77, warm)
+        if warm == kamx.WARM_LEARNED:
+            m.attach_mlp(net)
+        m.step(5)
+        log = torch.zeros((20, n), dtype=torch.int32, device="cuda")
+        m.set_iteration_log(log)
+        m.step(20)
+        torch.cuda.synchronize()
+        iters[name] = log.cpu().numpy()
+        m.close()
+    net.close()
+    c, l = iters["cold"].mean(), iters["learned"].mean()
+    print(f"\nheld-out loss {info['val_loss']:.3f}; mean iterations cold {c:.1f}, learned {l:.1f}; "
+          f"median {np.median(iters['cold']):.0f} -> {np.median(iters['learned']):.0f}")
+    assert l < 0.98 * c
