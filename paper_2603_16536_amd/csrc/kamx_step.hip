@@ -377,38 +377,6 @@ __device__ inline void joint_rows(const Lds &L, int type, const JointGeo &g, int
 // index order), results uniform across the workgroup
 // ---------------------------------------------------------------------------
 
-template <int NT>
-__device__ inline void reduce4(float &m0, float &m1, float &m2, float &s3, float *red) {
-    for (int off = 32; off > 0; off >>= 1) {
-        float o0 = __shfl_xor(m0, off, 64);
-        float o1 = __shfl_xor(m1, off, 64);
-        float o2 = __shfl_xor(m2, off, 64);
-        float o3 = __shfl_xor(s3, off, 64);
-        m0 = (o0 > m0 || o0 != o0) ? o0 : m0;
-        m1 = (o1 > m1 || o1 != o1) ? o1 : m1;
-        m2 = (o2 > m2 || o2 != o2) ? o2 : m2;
-        s3 = s3 + o3;
-    }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) {
-        red[4 * wave + 0] = m0;
-        red[4 * wave + 1] = m1;
-        red[4 * wave + 2] = m2;
-        red[4 * wave + 3] = s3;
-    }
-    __syncthreads();
-    m0 = red[0];
-    m1 = red[1];
-    m2 = red[2];
-    s3 = red[3];
-    for (int k = 1; k < NT / 64; ++k) {
-        float a = red[4 * k], b = red[4 * k + 1], c = red[4 * k + 2];
-        m0 = (a > m0 || a != a) ? a : m0;
-        m1 = (b > m1 || b != b) ? b : m1;
-        m2 = (c > m2 || c != c) ? c : m2;
-        s3 = s3 + red[4 * k + 3];
-    }
-}
 
 // ---------------------------------------------------------------------------
 // matrix-free preconditioned Delassus product out = P J M^-1 J^T P x (Eq. 4),
@@ -448,6 +416,18 @@ __device__ inline T lane_group_sum(T v) {
     return v;
 }
 
+// max that propagates NaN (a NaN residual must stop the solve)
+__device__ inline float nanmax(float a, float b) { return (b > a || b != b) ? b : a; }
+
+template <int G>
+__device__ inline float lane_group_max(float v) {
+    if (G >= 2) v = nanmax(v, dpp<kDppXor1>(v));
+    if (G >= 4) v = nanmax(v, dpp<kDppXor2>(v));
+    if (G >= 8) v = nanmax(v, dpp<kDppMirror8>(v));
+    if (G >= 16) v = nanmax(v, dpp<kDppMirror16>(v));
+    return v;
+}
+
 // Sum over the TPR lanes that share a row (fixed butterfly order).
 template <int TPR, typename T>
 __device__ inline T group_sum(T v) {
@@ -457,6 +437,39 @@ __device__ inline T group_sum(T v) {
 // Broadcast a lane's value to the whole wave (lane index uniform).
 __device__ inline float rdlane(float v, int lane) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+template <int NT>
+__device__ inline void reduce4(float &m0, float &m1, float &m2, float &s3, float *red) {
+    // rows of 16 lanes by DPP, then the wave's four rows through readlane,
+    // then the waves in order through LDS; every step combines two values
+    // that the partner combines in the other order, so all lanes agree
+    m0 = lane_group_max<16>(m0);
+    m1 = lane_group_max<16>(m1);
+    m2 = lane_group_max<16>(m2);
+    s3 = lane_group_sum<16>(s3);
+    m0 = nanmax(nanmax(rdlane(m0, 0), rdlane(m0, 16)), nanmax(rdlane(m0, 32), rdlane(m0, 48)));
+    m1 = nanmax(nanmax(rdlane(m1, 0), rdlane(m1, 16)), nanmax(rdlane(m1, 32), rdlane(m1, 48)));
+    m2 = nanmax(nanmax(rdlane(m2, 0), rdlane(m2, 16)), nanmax(rdlane(m2, 32), rdlane(m2, 48)));
+    s3 = (rdlane(s3, 0) + rdlane(s3, 16)) + (rdlane(s3, 32) + rdlane(s3, 48));
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[4 * wave + 0] = m0;
+        red[4 * wave + 1] = m1;
+        red[4 * wave + 2] = m2;
+        red[4 * wave + 3] = s3;
+    }
+    __syncthreads();
+    m0 = red[0];
+    m1 = red[1];
+    m2 = red[2];
+    s3 = red[3];
+    for (int k = 1; k < NT / 64; ++k) {
+        m0 = nanmax(m0, red[4 * k]);
+        m1 = nanmax(m1, red[4 * k + 1]);
+        m2 = nanmax(m2, red[4 * k + 2]);
+        s3 = s3 + red[4 * k + 3];
+    }
 }
 
 __device__ inline float dot4(const float *a, const float *b) {
@@ -1365,10 +1378,10 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
         if ((k) > 0) sub[(k) > 0 ? (k) - 1 : 0] += now_ - tmark; \
         tmark = now_;                                 \
     }
-        for (it = 1; it <= N; ++it) {
-            KAMX_MARK(0);
-            // steps 4-5: rhs = -v~_f - Gamma(z^) + eta x + rho y^ + z^, and its
-            // residual against the current x
+        // steps 4-5: rhs = -v~_f - Gamma(z^) + eta x + rho y^ + z^, and its
+        // residual against the current x (rows of this thread's block; the
+        // owner computes it for the next iteration at the end of the update)
+        auto own_rhs = [&]() {
             if (owner) {
                 s_own = kind_i == kRowNormal ? mu_i * sqrtf(vzh[i + 1] * vzh[i + 1] + vzh[i + 2] * vzh[i + 2]) : 0.f;
                 _Pragma("unroll") for (int e = 0; e < 3; ++e) if (e < blk) {
@@ -1378,6 +1391,10 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
                     vrhs[i + e] = rhs - (vdx[i + e] + (eta + rr) * xe);
                 }
             }
+        };
+        own_rhs();
+        for (it = 1; it <= N; ++it) {
+            KAMX_MARK(0);
             __syncthreads();
             KAMX_MARK(1);
             // t = X r: rows i and m-1-i form a pair handled by four threads, so
@@ -1573,6 +1590,7 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
                     vzp[i + e] = zb[e];
                 }
             }
+            own_rhs();  // for the next iteration
             KAMX_MARK(6);
             if (tid == 0 && a.rlog && P.log_restarts && it <= P.max_iters)
                 a.rlog[(size_t)w * P.max_iters + (it - 1)] = (uint8_t)restart;
