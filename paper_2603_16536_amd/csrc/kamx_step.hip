@@ -1724,9 +1724,14 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
 template <int MC, int NT, int TPR>
 __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
     __shared__ int s_int[8];
+    // the arguments in LDS: the per-step function takes them by reference,
+    // which would otherwise copy them to every lane's private stack
+    __shared__ StepArgs sa;
+    if (threadIdx.x == 0) sa = a;
+    __syncthreads();
 #pragma clang loop unroll(disable)
-    for (int k = 0; k < a.nsteps; ++k) {
-        step_world<MC, NT, TPR>(a, k, s_int);
+    for (int k = 0; k < sa.nsteps; ++k) {
+        step_world<MC, NT, TPR>(sa, k, s_int);
         __syncthreads();
     }
 }
