@@ -68,10 +68,11 @@ def algorithmic_flops(rows, iters, sum_kb2):
     return m ** 3 / 3.0 + k * (2 * m * m + 30 * m) + 12.0 * sum_kb2 + 2 * m * m
 
 
-def measured_traffic():
+def measured_traffic(steps_per_launch):
     """HBM bytes per step-kernel launch from the committed rocprofv3 FETCH_SIZE
-    and WRITE_SIZE runs (scaled by a plain copy of known size), or None when
-    the kernel source has changed since they were taken."""
+    and WRITE_SIZE runs (scaled by a plain copy of known size, recorded per
+    step of the batch, times the steps one launch advances), or None when the
+    kernel source has changed since they were taken."""
     import hashlib
     here = os.path.dirname(os.path.abspath(__file__))
     rec = os.path.join(here, "profiles", "step_kernel_biped4096_traffic.txt")
@@ -81,7 +82,7 @@ def measured_traffic():
     kv = dict(line.split(": ", 1) for line in open(rec).read().splitlines() if ": " in line)
     if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != kv.get("kernel_sha256_prefix"):
         return None
-    return int(kv["fetch_bytes_per_launch"]) + int(kv["write_bytes_per_launch"])
+    return round((int(kv["fetch_bytes_per_step"]) + int(kv["write_bytes_per_step"])) * steps_per_launch)
 
 
 def make_model(workload, n_worlds, warmstart, schedule, seed=None):
@@ -281,7 +282,7 @@ def main():
                                 "index": "one launch per step, world index order"}[args.schedule]},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VALU_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 5),
-                     "traffic": measured_traffic() if args.workload == "biped" and args.worlds == 4096 else None,
+                     "traffic": measured_traffic(cold["steps_per_launch"]) if args.workload == "biped" and args.worlds == 4096 else None,
                      "kernel": "step_kernel<224,512,2>" if args.workload == "biped" else "all step kernels",
                      "avg_launch_ms": round(1e3 * avg_launch_s, 4), "steps_per_launch": cold["steps_per_launch"]},
         "solver": {"iters_mean": round(float(it.mean()), 1), "iters_p50": float(np.percentile(it, 50)),
