@@ -112,7 +112,7 @@ def make_model(workload, n_worlds, warmstart, schedule, seed=None):
     return scene, model
 
 
-def run_gpu(n_worlds, steps, warmup, warmstart, schedule, net=None, seed=None, workload="biped"):
+def run_gpu(n_worlds, steps, warmup, warmstart, schedule, net=None, seed=None, workload="biped", autotune=True):
     """Warm-up steps, then one timed call of `steps` steps (chained launches
     where the mode allows, single-step launches otherwise), bracketed by HIP
     events on the launch stream; per-step iteration and row counts come
@@ -125,6 +125,11 @@ def run_gpu(n_worlds, steps, warmup, warmstart, schedule, net=None, seed=None, w
     stream = torch.cuda.current_stream()
     model.step(warmup)
     torch.cuda.synchronize()
+    # untimed: each size bucket keeps its fastest workgroup-size variant (the
+    # state is restored, so the timed rollout continues from the warm-up)
+    if autotune and any(len(b["variants"]) > 1 for b in model.buckets()):
+        model.autotune(8)
+    bucket_table = [f'{b["rows"]} rows x {b["worlds"]} worlds: {b["threads"]} threads' for b in model.buckets()]
     nw = scene.n_worlds
     iters = torch.zeros((steps, nw), dtype=torch.int32, device="cuda")
     rows = torch.zeros((steps, nw), dtype=torch.int32, device="cuda")
@@ -140,12 +145,12 @@ def run_gpu(n_worlds, steps, warmup, warmstart, schedule, net=None, seed=None, w
     t1 = time.perf_counter()
     model.set_iteration_log(None)
     status = model.stats()["status"].cpu().numpy()
-    chained = schedule == kamx_sched_chain() and workload != "boxbin" and net is None
+    chained = schedule == kamx_sched_chain() and workload != "boxbin"
     launches = -(-steps // 64) if chained else steps
     out = dict(
         wall_s=t1 - t0, event_ms=e0.elapsed_time(e1), launches=launches, steps_per_launch=steps / launches,
         iters=iters.cpu().numpy(), rows=rows.cpu().numpy(), status_last=status,
-        resets=model.reset_count() - resets0, buckets=model.n_buckets,
+        resets=model.reset_count() - resets0, buckets=model.n_buckets, bucket_table=bucket_table,
         sum_kb2=incidence_sq(scene) if workload == "biped" else 0.0,
     )
     model.close()
@@ -233,6 +238,8 @@ def main():
     ap.add_argument("--epochs", type=int, default=60)
     ap.add_argument("--schedule", choices=("chain", "lpt", "index"), default="chain",
                     help="chained multi-step launches, or one launch per step ordered longest-first or by index")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep every size bucket's default workgroup size instead of the autotuner's choice")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the run, copy a 256 MiB buffer once (a plain copy kernel of known traffic "
                          "for scaling HBM byte counters)")
@@ -254,10 +261,12 @@ def main():
     if args.workload != "biped":
         args.no_learned = True
         args.no_cpu = True
-    cold = run_gpu(args.worlds, args.steps, args.warmup, kamx.WARM_COLD, sched, workload=args.workload)
+    cold = run_gpu(args.worlds, args.steps, args.warmup, kamx.WARM_COLD, sched, workload=args.workload,
+                   autotune=not args.no_autotune)
+    cap = CFG2["max_iters"] if args.workload == "biped" else 200
     value = args.worlds * args.steps / cold["wall_s"]
     it = cold["iters"]
-    conv = float((it < CFG2["max_iters"]).mean())
+    conv = float((it < cap).mean())
     flops_total = float(algorithmic_flops(cold["rows"], it, cold["sum_kb2"]).sum())
     avg_launch_s = cold["event_ms"] / 1e3 / cold["launches"]
     achieved = flops_total / cold["launches"] / avg_launch_s / 1e12
@@ -279,11 +288,12 @@ def main():
                    "warm_start": "cold (plain ADMM)",
                    "dispatch": {"chain": "each world kept on its workgroup for up to 64 steps per launch",
                                 "lpt": "one launch per step, longest previous solve first",
-                                "index": "one launch per step, world index order"}[args.schedule]},
+                                "index": "one launch per step, world index order"}[args.schedule],
+                   "buckets": cold["bucket_table"]},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VALU_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 5),
                      "traffic": measured_traffic(cold["steps_per_launch"]) if args.workload == "biped" and args.worlds == 4096 else None,
-                     "kernel": "step_kernel<224,512,2>" if args.workload == "biped" else "all step kernels",
+                     "kernel": "step_kernel<224,512>" if args.workload == "biped" else "all step kernels",
                      "avg_launch_ms": round(1e3 * avg_launch_s, 4), "steps_per_launch": cold["steps_per_launch"]},
         "solver": {"iters_mean": round(float(it.mean()), 1), "iters_p50": float(np.percentile(it, 50)),
                    "iters_p99": float(np.percentile(it, 99)), "converged_fraction": round(conv, 5),
@@ -291,14 +301,15 @@ def main():
     }
     if not args.no_previous:
         print("[bench] previous-step warm-start rollout", file=sys.stderr, flush=True)
-        prev = run_gpu(args.worlds, args.steps, args.warmup, kamx.WARM_PREVIOUS, sched, workload=args.workload)
+        prev = run_gpu(args.worlds, args.steps, args.warmup, kamx.WARM_PREVIOUS, sched, workload=args.workload,
+                       autotune=not args.no_autotune)
         pit = prev["iters"]
         result["warm_previous"] = {
             "value": round(args.worlds * args.steps / prev["wall_s"], 1),
             "ms_per_step": round(1e3 * prev["wall_s"] / args.steps, 4),
             "iters_mean": round(float(pit.mean()), 1), "iters_p50": float(np.percentile(pit, 50)),
             "iters_p99": float(np.percentile(pit, 99)),
-            "converged_fraction": round(float((pit < CFG2["max_iters"]).mean()), 5)}
+            "converged_fraction": round(float((pit < cap).mean()), 5)}
     if not args.no_learned:
         from paper_2603_16536_amd import learn
         print(f"[bench] learned warm start: {args.train_steps}-step cold rollout for data (noise seed "

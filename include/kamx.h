@@ -254,9 +254,43 @@ kamx_status kamx_set_warmstart(kamx_model m, const float *lambda_dev, kamx_strea
  * steps, so a slow solve delays only its own world and the hardware
  * balances whole chains.  Chains apply to calls of kamx_step with
  * nsteps > 1 when every step's inputs are on the device already (no
- * generated contacts, no learned warm start); otherwise steps are launched
- * one by one.  Host-side, synchronous; EINVAL on an unknown mode. */
+ * generated contacts); otherwise steps are launched one by one.  Host-side,
+ * synchronous; EINVAL on an unknown mode. */
 kamx_status kamx_set_schedule(kamx_model m, int32_t mode);
+
+/* Size buckets (Sec. 5.2: worlds of different sizes share one call; each
+ * bucket is padded to a row capacity of 32, 64, ..., 224 and runs its own
+ * kernel instantiation, largest bucket first).  kamx_bucket_count gives
+ * their number.  kamx_bucket_info reports bucket b: its row capacity, its
+ * number of worlds, the workgroup size its kernel currently runs with, and
+ * the sizes it is built for (n_variants of them, at most 4, written to
+ * variants[4] when that is not NULL; the first is the default).  Any
+ * output pointer may be NULL.  EINVAL on a bucket index out of range. */
+kamx_status kamx_bucket_count(kamx_model m, int32_t *n_buckets);
+kamx_status kamx_bucket_info(kamx_model m, int32_t bucket, int32_t *rows_cap, int32_t *n_worlds,
+                             int32_t *threads, int32_t *n_variants, int32_t *variants);
+
+/* Workgroup size of bucket b's step kernel: one of its variants.  A smaller
+ * workgroup lets more worlds share a compute unit (every kernel keeps two
+ * waves per SIMD); a larger one gives each world more threads.  Results are
+ * bitwise the same for every variant.  Drops captured graphs.  EINVAL on a
+ * bucket out of range or a size the bucket is not built for. */
+kamx_status kamx_set_bucket_threads(kamx_model m, int32_t bucket, int32_t threads);
+
+/* Autotuner: for every bucket with more than one variant, time trial_steps
+ * steps of that bucket alone (1 to 64; chained when the schedule allows)
+ * under each variant, from the model's current state, and keep the fastest.
+ * Each trial runs twice and the second run is timed.  The state the steps
+ * change (poses, twists, impulse caches, contact keys, statistics, step
+ * counter, generated contacts, reset counts) is saved before and restored
+ * after every trial, so the model continues exactly as if the call had not
+ * been made; an iteration log set by kamx_set_iteration_log is not written.
+ * Synchronous (waits for the device); allocates a snapshot of the state for
+ * the duration of the call.  ms_out, when not NULL, is a host array
+ * [n_buckets * 4] that receives the timed milliseconds of each bucket's
+ * variants in kamx_bucket_info order (0 for a bucket with one variant or an
+ * unused entry).  EINVAL when trial_steps is outside 1..64. */
+kamx_status kamx_autotune(kamx_model m, int32_t trial_steps, float *ms_out);
 
 /* Advance every world by nsteps steps (asynchronous on stream).  nsteps = 1
  * enqueues the step's kernels directly.  nsteps > 1 either runs chained

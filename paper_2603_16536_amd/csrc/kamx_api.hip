@@ -13,7 +13,8 @@
 #include "kamx_internal.h"
 
 namespace kamx {
-hipError_t launch_step(const StepArgs &args, int mc, int n, hipStream_t stream);
+hipError_t launch_step(const StepArgs &args, int mc, int nt, int n, hipStream_t stream);
+int step_threads_variants(int mc, int out[4]);
 int bucket_capacity(int rows);
 size_t step_smem_bytes(int mc);
 hipError_t launch_lpt_order(const int32_t *worlds, int n, const int32_t *iters, int32_t *order, hipStream_t stream);
@@ -64,6 +65,7 @@ kamx_status mlp_fail(kamx_status st, const char *fmt, ...) {
 
 struct Bucket {
     int mc;
+    int nt;             // workgroup size of the bucket's step kernel
     int n;
     int32_t *d_worlds;  // the bucket's worlds in index order
     int32_t *d_order;   // dispatch order of the next step (a permutation of d_worlds)
@@ -437,6 +439,9 @@ kamx_status kamx_model_create(const kamx_body_desc *bodies, int32_t nb, const ka
         if (groups[s].empty()) continue;
         Bucket b;
         b.mc = 32 * (s + 1);
+        int nts[4];
+        if (step_threads_variants(b.mc, nts) < 1) return cleanup_fail(fail(KAMX_EINVAL, "no kernel for %d rows", b.mc));
+        b.nt = nts[0];
         b.n = (int)groups[s].size();
         b.d_worlds = nullptr;
         M_TRY(dalloc(m, &b.d_worlds, groups[s].size()));
@@ -614,7 +619,7 @@ static kamx_status enqueue_features(kamx_model m, float *x, hipStream_t s) {
     for (const Bucket &b : m->buckets) {
         a.bucket_worlds = b.d_worlds;
         a.n_bucket_worlds = b.n;
-        hipError_t e = launch_step(a, b.mc, b.n, s);
+        hipError_t e = launch_step(a, b.mc, b.nt, b.n, s);
         if (e != hipSuccess) return fail(KAMX_EDEVICE, "feature launch (bucket %d rows): %s", b.mc, hipGetErrorString(e));
     }
     return KAMX_OK;
@@ -656,7 +661,7 @@ static kamx_status enqueue_launch(kamx_model m, int n, int pos, hipStream_t s) {
         StepArgs a = base;
         a.bucket_worlds = lpt ? b.d_order : b.d_worlds;
         a.n_bucket_worlds = b.n;
-        hipError_t e = launch_step(a, b.mc, b.n, bs);
+        hipError_t e = launch_step(a, b.mc, b.nt, b.n, bs);
         if (e != hipSuccess) return fail(KAMX_EDEVICE, "step launch (bucket %d rows): %s", b.mc, hipGetErrorString(e));
         if (lpt && b.n > 1) {
             e = launch_lpt_order(b.d_worlds, b.n, m->d_iters, b.d_order, bs);
@@ -746,6 +751,190 @@ kamx_status kamx_step(kamx_model m, int32_t nsteps, kamx_stream stream) {
     return KAMX_OK;
 }
 
+kamx_status kamx_bucket_count(kamx_model m, int32_t *n_buckets) {
+    if (!m) return fail(KAMX_EINVAL, "model is NULL");
+    if (n_buckets) *n_buckets = (int32_t)m->buckets.size();
+    return KAMX_OK;
+}
+
+kamx_status kamx_bucket_info(kamx_model m, int32_t bucket, int32_t *rows_cap, int32_t *n_worlds, int32_t *threads,
+                             int32_t *n_variants, int32_t *variants) {
+    if (!m) return fail(KAMX_EINVAL, "model is NULL");
+    if (bucket < 0 || bucket >= (int32_t)m->buckets.size()) return fail(KAMX_EINVAL, "bucket %d out of range", bucket);
+    const Bucket &b = m->buckets[bucket];
+    int nts[4] = {0, 0, 0, 0};
+    const int nv = step_threads_variants(b.mc, nts);
+    if (rows_cap) *rows_cap = b.mc;
+    if (n_worlds) *n_worlds = b.n;
+    if (threads) *threads = b.nt;
+    if (n_variants) *n_variants = nv;
+    if (variants)
+        for (int k = 0; k < 4; ++k) variants[k] = k < nv ? nts[k] : 0;
+    return KAMX_OK;
+}
+
+kamx_status kamx_set_bucket_threads(kamx_model m, int32_t bucket, int32_t threads) {
+    if (!m) return fail(KAMX_EINVAL, "model is NULL");
+    if (bucket < 0 || bucket >= (int32_t)m->buckets.size()) return fail(KAMX_EINVAL, "bucket %d out of range", bucket);
+    Bucket &b = m->buckets[bucket];
+    int nts[4];
+    const int nv = step_threads_variants(b.mc, nts);
+    for (int k = 0; k < nv; ++k)
+        if (nts[k] == threads) {
+            drop_graphs(m);
+            b.nt = threads;
+            return KAMX_OK;
+        }
+    return fail(KAMX_EINVAL, "bucket of %d rows has no kernel for %d threads", b.mc, threads);
+}
+
+namespace {
+struct StateSpan {
+    void *p;
+    size_t bytes;
+};
+}  // namespace
+
+// Every device buffer a step writes (the state the autotuner restores).
+static std::vector<StateSpan> step_state(kamx_model m) {
+    std::vector<StateSpan> v;
+    auto add = [&](void *p, size_t bytes) {
+        if (p && bytes) v.push_back({p, bytes});
+    };
+    const size_t nw = (size_t)m->n_worlds;
+    add(m->d_q, sizeof(float) * 7 * (size_t)m->nb);
+    add(m->d_u, sizeof(float) * 6 * (size_t)m->nb);
+    add(m->d_lambda, sizeof(float) * (size_t)m->rows_cap);
+    add(m->d_keys, sizeof(int32_t) * nw * kMaxContacts);
+    add(m->d_iters, sizeof(int32_t) * nw);
+    add(m->d_status, sizeof(int32_t) * nw);
+    add(m->d_rows, sizeof(int32_t) * nw);
+    add(m->d_resid, sizeof(float) * 4 * nw);
+    add(m->d_tau, sizeof(float) * (size_t)std::max(m->nj, 1));
+    add(m->d_contacts_out, sizeof(kamx_contact) * nw * kMaxContacts);
+    add(m->d_ncontacts, sizeof(int32_t) * nw);
+    add(m->d_reset_count, sizeof(int32_t) * nw);
+    add(m->d_step, sizeof(uint32_t));
+    add(m->d_ws, sizeof(float) * nw * (size_t)m->n_slots);
+    add(m->d_gen, sizeof(kamx_contact) * nw * kMaxContacts);
+    add(m->d_gen_count, sizeof(int32_t) * nw);
+    add(m->d_rlog, nw * (size_t)m->rlog_stride);
+    add(m->d_phase_clk, sizeof(uint64_t) * 16 * nw);
+    for (const Bucket &b : m->buckets) add(b.d_order, sizeof(int32_t) * (size_t)b.n);
+    return v;
+}
+
+static kamx_status copy_state(const std::vector<StateSpan> &spans, char *snap, bool save, hipStream_t s) {
+    size_t off = 0;
+    for (const StateSpan &sp : spans) {
+        void *dst = save ? (void *)(snap + off) : sp.p;
+        const void *src = save ? (const void *)sp.p : (const void *)(snap + off);
+        HIP_TRY(hipMemcpyAsync(dst, src, sp.bytes, hipMemcpyDeviceToDevice, s));
+        off += (sp.bytes + 255) & ~(size_t)255;
+    }
+    return KAMX_OK;
+}
+
+// trial_steps steps of bucket bi alone, in the model's dispatch (one chained
+// launch, or single steps with contact generation when contacts are
+// generated); the step counter advances as in kamx_step.
+static kamx_status enqueue_bucket_trial(kamx_model m, int bi, int steps, hipStream_t s) {
+    const Bucket &b = m->buckets[bi];
+    StepArgs a = step_args(m);
+    a.bucket_worlds = b.d_worlds;
+    a.n_bucket_worlds = b.n;
+    const bool chain = chained(m);
+    for (int k = 0; k < steps;) {
+        const int n = chain ? steps - k : 1;
+        if (m->box_bin) {
+            hipError_t e = launch_box_bin(m->d_worlds, m->n_worlds, m->d_q, m->d_box_geom, m->bin_wx, m->bin_wy,
+                                          m->bin_margin, m->d_gen, m->d_gen_count, s);
+            if (e != hipSuccess) return fail(KAMX_EDEVICE, "contact generation launch: %s", hipGetErrorString(e));
+        }
+        a.nsteps = n;
+        hipError_t e = launch_step(a, b.mc, b.nt, b.n, s);
+        if (e != hipSuccess) return fail(KAMX_EDEVICE, "step launch (bucket %d rows): %s", b.mc, hipGetErrorString(e));
+        e = launch_advance_step(m->d_step, (uint32_t)n, s);
+        if (e != hipSuccess) return fail(KAMX_EDEVICE, "counter launch: %s", hipGetErrorString(e));
+        k += n;
+    }
+    return KAMX_OK;
+}
+
+kamx_status kamx_autotune(kamx_model m, int32_t trial_steps, float *ms_out) {
+    if (!m) return fail(KAMX_EINVAL, "model is NULL");
+    if (trial_steps < 1 || trial_steps > kChainSteps) return fail(KAMX_EINVAL, "trial_steps must be 1..%d", kChainSteps);
+    if (m->params.warmstart == KAMX_WARM_LEARNED && !m->mlp)
+        return fail(KAMX_ESTATE, "warm start LEARNED needs a network (kamx_model_attach_mlp)");
+    K_TRY(check_device());
+    if (m->params.log_restarts) K_TRY(ensure_rlog(m));
+    const int nbk = (int)m->buckets.size();
+    if (ms_out)
+        for (int k = 0; k < 4 * nbk; ++k) ms_out[k] = 0.f;
+    if (!m->capture_stream) HIP_TRY(hipStreamCreateWithFlags(&m->capture_stream, hipStreamNonBlocking));
+    hipStream_t s = m->capture_stream;
+    HIP_TRY(hipDeviceSynchronize());
+    const std::vector<StateSpan> spans = step_state(m);
+    size_t total = 0;
+    for (const StateSpan &sp : spans) total += (sp.bytes + 255) & ~(size_t)255;
+    char *snap = nullptr;
+    {
+        hipError_t e = hipMalloc((void **)&snap, std::max<size_t>(total, 1));
+        if (e != hipSuccess) return fail(KAMX_ENOMEM, "autotune snapshot (%zu bytes): %s", total, hipGetErrorString(e));
+    }
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    kamx_status st = KAMX_OK;
+    auto run = [&]() -> kamx_status {
+        HIP_TRY(hipEventCreate(&t0));
+        HIP_TRY(hipEventCreate(&t1));
+        K_TRY(copy_state(spans, snap, true, s));
+        for (int bi = 0; bi < nbk; ++bi) {
+            Bucket &b = m->buckets[bi];
+            int nts[4];
+            const int nv = step_threads_variants(b.mc, nts);
+            if (nv < 2) continue;
+            const int keep = b.nt;
+            int best = keep;
+            float best_ms = INFINITY;
+            for (int v = 0; v < nv; ++v) {
+                b.nt = nts[v];
+                float ms = 0.f;
+                for (int rep = 0; rep < 2; ++rep) {
+                    K_TRY(copy_state(spans, snap, false, s));
+                    HIP_TRY(hipEventRecord(t0, s));
+                    kamx_status e = enqueue_bucket_trial(m, bi, trial_steps, s);
+                    if (e != KAMX_OK) {
+                        b.nt = keep;
+                        return e;
+                    }
+                    HIP_TRY(hipEventRecord(t1, s));
+                    HIP_TRY(hipEventSynchronize(t1));
+                    HIP_TRY(hipEventElapsedTime(&ms, t0, t1));
+                }
+                if (ms_out) ms_out[4 * bi + v] = ms;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = nts[v];
+                }
+            }
+            b.nt = best;
+        }
+        return KAMX_OK;
+    };
+    st = run();
+    // the state as it was before the call, whatever happened above
+    kamx_status rs = copy_state(spans, snap, false, s);
+    hipError_t se = hipStreamSynchronize(s);
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+    (void)hipFree(snap);
+    drop_graphs(m);
+    if (st != KAMX_OK) return st;
+    if (rs != KAMX_OK) return rs;
+    if (se != hipSuccess) return fail(KAMX_EDEVICE, "autotune: %s", hipGetErrorString(se));
+    return KAMX_OK;
+}
+
 kamx_status kamx_set_iteration_log(kamx_model m, int32_t *iters_dev, int32_t *rows_dev, int32_t steps) {
     if (!m) return fail(KAMX_EINVAL, "model is NULL");
     if (iters_dev && steps < 1) return fail(KAMX_EINVAL, "steps must be positive");
@@ -794,6 +983,15 @@ kamx_status kamx_model_attach_mlp(kamx_model m, kamx_mlp net) {
                     m->n_feat, m->n_slots);
     if (mlp_capacity(net) < m->n_worlds)
         return fail(KAMX_EINVAL, "network batch capacity %d below %d worlds", mlp_capacity(net), m->n_worlds);
+    {
+        // the step kernel evaluates the network with its activations (BF16:
+        // input, two hidden layers) in the LDS region of the Delassus triangle
+        const MlpView v = mlp_view(net);
+        for (const Bucket &b : m->buckets)
+            if (2 * (size_t)(v.fp + 2 * v.H) > sizeof(float) * (size_t)tri_row_offset(b.mc))
+                return fail(KAMX_EUNSUPPORTED, "network activations (%d + 2 x %d) exceed the %d-row bucket's LDS", v.fp,
+                            v.H, b.mc);
+    }
     if (!m->d_ws) K_TRY(dalloc(m, &m->d_ws, (size_t)m->n_worlds * m->n_slots));
     m->mlp = net;
     return KAMX_OK;

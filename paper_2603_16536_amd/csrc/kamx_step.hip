@@ -428,10 +428,10 @@ __device__ inline float lane_group_max(float v) {
     return v;
 }
 
-// Sum over the TPR lanes that share a row (fixed butterfly order).
-template <int TPR, typename T>
+// Sum over the G lanes that share a row (fixed butterfly order).
+template <int G, typename T>
 __device__ inline T group_sum(T v) {
-    return lane_group_sum<TPR>(v);
+    return lane_group_sum<G>(v);
 }
 
 // Broadcast a lane's value to the whole wave (lane index uniform).
@@ -492,7 +492,7 @@ __device__ inline float tri_at(const float *A, int r, int c) { return c <= r ? A
 // Body gather of the matrix-free product: g_b = sum over the rows incident
 // to body b of J_{r,b}^T p_r x_r, one thread per (body, component), FP64,
 // rows in increasing order.  Ends with a barrier.
-template <int NT, int TPR>
+template <int NT>
 __device__ inline void delassus_gather(const Lds &L, int nb, const float *vp, const float *x) {
     // two adjacent threads per (body, component) take alternate rows of the
     // incidence list; their partial sums meet by one shuffle
@@ -560,9 +560,9 @@ __device__ inline float delassus_row(const Lds &L, const float *vp, int r) {
 }
 
 // Full product out = D~ x (gather, then every row).  Ends with a barrier.
-template <int NT, int TPR>
+template <int NT>
 __device__ inline void delassus_apply(const Lds &L, int m, int nb, const float *vp, const float *x, float *out) {
-    delassus_gather<NT, TPR>(L, nb, vp, x);
+    delassus_gather<NT>(L, nb, vp, x);
     for (int r = threadIdx.x; r < m; r += NT) out[r] = delassus_row(L, vp, r);
     __syncthreads();
 }
@@ -574,7 +574,7 @@ __device__ inline void delassus_apply(const Lds &L, int m, int nb, const float *
 // One step of world w (every phase of the step; the workgroup owns the
 // world).  step is the step index that keys the actuation noise; k the
 // position of the step inside the launch.
-template <int MC, int NT, int TPR>
+template <int MC, int NT>
 __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, int *s_int) {
     extern __shared__ float4 smem4[];
     float *sm = reinterpret_cast<float *>(smem4);
@@ -1115,7 +1115,7 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
             }
         }
         __syncthreads();
-        delassus_apply<NT, TPR>(L, m, nb, vp, vyp, vdx);  // D~ y0 (x0 = y0)
+        delassus_apply<NT>(L, m, nb, vp, vyp, vdx);  // D~ y0 (x0 = y0)
         if (owner) {
             float v0 = vdx[i] + vvt[i];
             if (kind_i == kRowNormal) {
@@ -1145,7 +1145,6 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
     //      trailing tiles get their rank-16 update on the matrix cores.  With
     //      one step of lookahead, wave 0 updates and factors the next
     //      diagonal tile while the other waves update the rest.
-    const int si = tid / TPR, sq = tid % TPR;
     {
         const int T = (m + 15) >> 4;
         float *Xs = L.red;  // 16x16 inverse of the current diagonal factor tile (red + wb are free here)
@@ -1508,7 +1507,7 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
             KAMX_MARK(3);
             // v~ - v~_f = D~ x_new (matrix-free, FP64): bodies gather here,
             // each block owner evaluates its own rows below
-            delassus_gather<NT, TPR>(L, nb, vp, vxn);
+            delassus_gather<NT>(L, nb, vp, vxn);
             KAMX_MARK(4);
             // steps 6-7 and the residuals of step 9 (block owners)
             float lrp = 0.f, lrd = 0.f, lrc = 0.f, lcc = 0.f;
@@ -1612,7 +1611,7 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
         if (P.fixed_iters <= 0 && !converged && status == 0) status = KAMX_WORLD_MAXITER;
         __syncthreads();
         // natural-map residual of the NCP at the returned y (Eq. 3)
-        delassus_apply<NT, TPR>(L, m, nb, vp, vyp, vaux);
+        delassus_apply<NT>(L, m, nb, vp, vyp, vaux);
         float lncp = 0.f;
         if (owner) {
             float v[3], o[3], y[3], nm[3];
@@ -1721,8 +1720,11 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
 // workgroup keeping its world for all of them: worlds are independent, so a
 // slow solve delays only its own world and the hardware's dispatch balances
 // whole chains of steps rather than single steps.
-template <int MC, int NT, int TPR>
-__global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
+// At most 256 VGPRs (two waves per SIMD): the per-step function needs 248,
+// and a workgroup smaller than 512 threads then leaves room on its compute
+// unit for another world's workgroup.
+template <int MC, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void step_kernel(StepArgs a) {
     __shared__ int s_int[8];
     // the arguments in LDS: the per-step function takes them by reference,
     // which would otherwise copy them to every lane's private stack
@@ -1731,7 +1733,7 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
     __syncthreads();
 #pragma clang loop unroll(disable)
     for (int k = 0; k < sa.nsteps; ++k) {
-        step_world<MC, NT, TPR>(sa, k, s_int);
+        step_world<MC, NT>(sa, k, s_int);
         __syncthreads();
     }
 }
@@ -1777,21 +1779,18 @@ hipError_t launch_impulse_slots(const WorldInfo *worlds, int n_worlds, int n_con
 // launch table
 // ---------------------------------------------------------------------------
 
-template <int MC>
+template <int MC, int NT>
 static hipError_t launch_mc(const StepArgs &args, int n, hipStream_t stream) {
-    // threads per row: 4 for small worlds; 2 for the large buckets, where the
-    // register budget of 1024-thread groups (128 VGPRs) would spill
-    constexpr int TPR = MC >= 160 ? 2 : 4;
-    constexpr int NT = TPR * ((MC + 63) / 64) * 64;
+    static_assert(NT % 64 == 0 && NT >= 128 && NT >= 2 * MC && NT <= 512, "unsupported workgroup size");
     size_t bytes = sizeof(float) * (size_t)smem_floats(MC);
     static bool configured = false;
     if (!configured) {
-        hipError_t e = hipFuncSetAttribute((const void *)step_kernel<MC, NT, TPR>,
+        hipError_t e = hipFuncSetAttribute((const void *)step_kernel<MC, NT>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         if (e != hipSuccess) return e;
         configured = true;
     }
-    hipLaunchKernelGGL((step_kernel<MC, NT, TPR>), dim3(n), dim3(NT), bytes, stream, args);
+    hipLaunchKernelGGL((step_kernel<MC, NT>), dim3(n), dim3(NT), bytes, stream, args);
     return hipGetLastError();
 }
 
@@ -1802,15 +1801,41 @@ int bucket_capacity(int rows) {
     return -1;
 }
 
-hipError_t launch_step(const StepArgs &args, int mc, int n, hipStream_t stream) {
+// Workgroup sizes each row bucket is built for.  Every iteration pass gives
+// each pair of rows (and each pair of column quads) its own threads, so a
+// workgroup has at least two threads per row and at least two waves; the
+// larger size runs the passes with more threads, the smaller one lets more
+// worlds share a compute unit where LDS allows.  The first entry is the
+// default.  Results do not depend on the choice: every row, tile and
+// reduction is evaluated in the same order at every size.
+int step_threads_variants(int mc, int out[4]) {
     switch (mc) {
-    case 32: return launch_mc<32>(args, n, stream);
-    case 64: return launch_mc<64>(args, n, stream);
-    case 96: return launch_mc<96>(args, n, stream);
-    case 128: return launch_mc<128>(args, n, stream);
-    case 160: return launch_mc<160>(args, n, stream);
-    case 192: return launch_mc<192>(args, n, stream);
-    case 224: return launch_mc<224>(args, n, stream);
+    case 32: out[0] = 256; out[1] = 128; return 2;
+    case 64: out[0] = 256; out[1] = 128; return 2;
+    case 96: out[0] = 512; out[1] = 256; return 2;
+    case 128: out[0] = 512; out[1] = 256; return 2;
+    case 160: out[0] = 384; out[1] = 512; return 2;
+    case 192: out[0] = 384; out[1] = 512; return 2;
+    case 224: out[0] = 512; return 1;
+    default: return 0;
+    }
+}
+
+hipError_t launch_step(const StepArgs &args, int mc, int nt, int n, hipStream_t stream) {
+    switch (mc * 1024 + nt) {
+    case 32 * 1024 + 128: return launch_mc<32, 128>(args, n, stream);
+    case 32 * 1024 + 256: return launch_mc<32, 256>(args, n, stream);
+    case 64 * 1024 + 128: return launch_mc<64, 128>(args, n, stream);
+    case 64 * 1024 + 256: return launch_mc<64, 256>(args, n, stream);
+    case 96 * 1024 + 256: return launch_mc<96, 256>(args, n, stream);
+    case 96 * 1024 + 512: return launch_mc<96, 512>(args, n, stream);
+    case 128 * 1024 + 256: return launch_mc<128, 256>(args, n, stream);
+    case 128 * 1024 + 512: return launch_mc<128, 512>(args, n, stream);
+    case 160 * 1024 + 384: return launch_mc<160, 384>(args, n, stream);
+    case 160 * 1024 + 512: return launch_mc<160, 512>(args, n, stream);
+    case 192 * 1024 + 384: return launch_mc<192, 384>(args, n, stream);
+    case 192 * 1024 + 512: return launch_mc<192, 512>(args, n, stream);
+    case 224 * 1024 + 512: return launch_mc<224, 512>(args, n, stream);
     default: return hipErrorInvalidValue;
     }
 }

@@ -89,6 +89,10 @@ def lib():
         L.kamx_set_warmstart.argtypes = [vp, vp, vp]
         L.kamx_step.argtypes = [vp, i32, vp]
         L.kamx_set_schedule.argtypes = [vp, i32]
+        L.kamx_bucket_count.argtypes = [vp, C.POINTER(C.c_int32)]
+        L.kamx_bucket_info.argtypes = [vp, i32] + [C.POINTER(C.c_int32)] * 5
+        L.kamx_set_bucket_threads.argtypes = [vp, i32, i32]
+        L.kamx_autotune.argtypes = [vp, i32, C.POINTER(C.c_float)]
         L.kamx_set_iteration_log.argtypes = [vp, vp, vp, i32]
         L.kamx_mlp_create.argtypes = [i32, i32, i32, i32, C.c_uint64, C.POINTER(vp)]
         L.kamx_mlp_destroy.argtypes = [vp]
@@ -376,6 +380,33 @@ class Model:
         """Mapping of steps onto workgroups: SCHED_CHAIN (default), SCHED_LPT
         or SCHED_INDEX (results are identical under all three)."""
         _check(lib().kamx_set_schedule(self.handle, int(mode)))
+
+    def buckets(self):
+        """Size buckets as dicts: rows (capacity), worlds, threads (current
+        workgroup size) and variants (the sizes the bucket is built for)."""
+        n = C.c_int32()
+        _check(lib().kamx_bucket_count(self.handle, C.byref(n)))
+        out = []
+        for b in range(n.value):
+            rows, worlds, threads, nv = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+            var = (C.c_int32 * 4)()
+            _check(lib().kamx_bucket_info(self.handle, b, C.byref(rows), C.byref(worlds), C.byref(threads),
+                                          C.byref(nv), var))
+            out.append(dict(rows=rows.value, worlds=worlds.value, threads=threads.value,
+                            variants=[var[k] for k in range(nv.value)]))
+        return out
+
+    def set_bucket_threads(self, bucket, threads):
+        _check(lib().kamx_set_bucket_threads(self.handle, int(bucket), int(threads)))
+
+    def autotune(self, trial_steps=8):
+        """Time every bucket's workgroup-size variants on trial_steps steps
+        from the current state (restored afterwards) and keep the fastest.
+        Returns the milliseconds per bucket and variant."""
+        n = len(self.buckets())
+        ms = (C.c_float * max(4 * n, 1))()
+        _check(lib().kamx_autotune(self.handle, int(trial_steps), ms))
+        return [[ms[4 * b + v] for v in range(len(bk["variants"]))] for b, bk in enumerate(self.buckets())]
 
     def step(self, n=1, stream=None):
         _check(lib().kamx_step(self.handle, int(n), _stream(stream)))

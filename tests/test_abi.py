@@ -58,3 +58,12 @@ def test_defaults_and_host_side_validation(libkamx):
 def test_schedule_mode_validation(libkamx):
     from paper_2603_16536_amd import kamx
     assert kamx.lib().kamx_set_schedule(None, kamx.SCHED_LPT) == kamx.EINVAL
+
+
+def test_bucket_and_autotune_validation(libkamx):
+    from paper_2603_16536_amd import kamx
+    n = C.c_int32()
+    assert kamx.lib().kamx_bucket_count(None, C.byref(n)) == kamx.EINVAL
+    assert kamx.lib().kamx_bucket_info(None, 0, None, None, None, None, None) == kamx.EINVAL
+    assert kamx.lib().kamx_set_bucket_threads(None, 0, 256) == kamx.EINVAL
+    assert kamx.lib().kamx_autotune(None, 8, None) == kamx.EINVAL
