@@ -1352,8 +1352,18 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
     //      matrix-free residual, so the fixed point solves the linear system
     //      to the accuracy of the residual, not to cond(D~) times FP32 epsilon.
     const float eta = P.eta;
-    const float rho_i = i < m ? vrho[i] : 1.f;
     const float mu_i = i < m ? L.rf(RMU, i) : 0.f;
+    // Inside the iteration loop row io = tid / 2 belongs to the lane pair
+    // (2 io, 2 io + 1): the pair evaluates the row's matrix-free product
+    // (even lane body a's side, odd lane body b's), and the even lane of a
+    // block's first row owns the block, so owner work spreads over every
+    // wave and a contact's three rows go to three pairs.
+    const int io = tid >> 1, hh = tid & 1;
+    const int kind_o = io < m ? L.ri(RKIND, io) : -1;
+    const bool owner_o = io < m && kind_o != kRowTangent && hh == 0;
+    const int blk_o = kind_o == kRowNormal ? 3 : 1;
+    const float rho_o = io < m ? vrho[io] : 1.f;
+    const float mu_o = io < m ? L.rf(RMU, io) : 0.f;
     float a_k = 1.f, c_prev = INFINITY;
     int it = 0, status = 0;
     float rp = 0.f, rd = 0.f, rc = 0.f, rncp = 0.f;
@@ -1381,13 +1391,13 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
         // residual against the current x (rows of this thread's block; the
         // owner computes it for the next iteration at the end of the update)
         auto own_rhs = [&]() {
-            if (owner) {
-                s_own = kind_i == kRowNormal ? mu_i * sqrtf(vzh[i + 1] * vzh[i + 1] + vzh[i + 2] * vzh[i + 2]) : 0.f;
-                _Pragma("unroll") for (int e = 0; e < 3; ++e) if (e < blk) {
-                    float rr = e == 0 ? rho_i : vrho[i + e];
-                    float xe = vx[i + e];
-                    float rhs = -vvt[i + e] - (e == 0 ? s_own : 0.f) + eta * xe + rr * vyh[i + e] + vzh[i + e];
-                    vrhs[i + e] = rhs - (vdx[i + e] + (eta + rr) * xe);
+            if (owner_o) {
+                s_own = kind_o == kRowNormal ? mu_o * sqrtf(vzh[io + 1] * vzh[io + 1] + vzh[io + 2] * vzh[io + 2]) : 0.f;
+                _Pragma("unroll") for (int e = 0; e < 3; ++e) if (e < blk_o) {
+                    float rr = e == 0 ? rho_o : vrho[io + e];
+                    float xe = vx[io + e];
+                    float rhs = -vvt[io + e] - (e == 0 ? s_own : 0.f) + eta * xe + rr * vyh[io + e] + vzh[io + e];
+                    vrhs[io + e] = rhs - (vdx[io + e] + (eta + rr) * xe);
                 }
             }
         };
@@ -1512,43 +1522,54 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
             // steps 6-7 and the residuals of step 9 (block owners)
             float lrp = 0.f, lrd = 0.f, lrc = 0.f, lcc = 0.f;
             float yb[3], zb[3];
-            if (owner) {
-                float xn[3], zh[3], yh[3], rr[3], vv[3];
-                double wa[6], wbv[6];
-                const int oa = L.ri(RIA, i), ob = L.ri(RIB, i);  // a block shares its two bodies
-                body_minv64(L, oa, wa);
-                if (ob >= 0) body_minv64(L, ob, wbv);
-                _Pragma("unroll") for (int e = 0; e < 3; ++e) if (e < blk) {
-                    float dx = delassus_row_w(L, vp, i + e, wa, wbv, ob >= 0);
-                    vdx[i + e] = dx;
-                    xn[e] = vxn[i + e];
-                    zh[e] = vzh[i + e];
-                    yh[e] = vyh[i + e];
-                    rr[e] = e == 0 ? rho_i : vrho[i + e];
-                    vv[e] = dx + vvt[i + e];
+            // v~ - v~_f of row io in FP64: J_a M_a^-1 g_a on the even lane,
+            // J_b M_b^-1 g_b on the odd lane, added by the pair sum
+            {
+                double side = 0.0;
+                if (io < m) {
+                    const int sb = hh == 0 ? L.ri(RIA, io) : L.ri(RIB, io);
+                    if (sb >= 0) {
+                        double wv[6];
+                        body_minv64(L, sb, wv);
+                        for (int c = 0; c < 6; ++c) side += (double)L.rf(RJ + 6 * hh + c, io) * wv[c];
+                    }
                 }
-                if (kind_i == kRowNormal) {
-                    proj_cone(mu_i, xn[0] - zh[0] / rr[0], xn[1] - zh[1] / rr[1], xn[2] - zh[2] / rr[2], yb[0], yb[1],
+                side = lane_group_sum<2>(side);
+                if (hh == 0 && io < m) vdx[io] = (float)(side * (double)vp[io]);
+            }
+            __syncthreads();
+            if (owner_o) {
+                float xn[3], zh[3], yh[3], rr[3], vv[3];
+                _Pragma("unroll") for (int e = 0; e < 3; ++e) if (e < blk_o) {
+                    const float dx = vdx[io + e];
+                    xn[e] = vxn[io + e];
+                    zh[e] = vzh[io + e];
+                    yh[e] = vyh[io + e];
+                    rr[e] = e == 0 ? rho_o : vrho[io + e];
+                    vv[e] = dx + vvt[io + e];
+                }
+                if (kind_o == kRowNormal) {
+                    proj_cone(mu_o, xn[0] - zh[0] / rr[0], xn[1] - zh[1] / rr[1], xn[2] - zh[2] / rr[2], yb[0], yb[1],
                               yb[2]);
-                } else if (kind_i == kRowLimit) {
+                } else if (kind_o == kRowLimit) {
                     yb[0] = fmaxf(xn[0] - zh[0] / rr[0], 0.f);
                 } else {
                     yb[0] = xn[0] - zh[0] / rr[0];
                 }
-                _Pragma("unroll") for (int e = 0; e < 3; ++e) if (e < blk) {
+                _Pragma("unroll") for (int e = 0; e < 3; ++e) if (e < blk_o) {
                     zb[e] = zh[e] - rr[e] * (xn[e] - yb[e]);
                     lrp = fmaxf(lrp, fabsf(xn[e] - yb[e]));
                     float dy = yb[e] - yh[e], dz = zb[e] - zh[e];
                     lcc += rr[e] * dy * dy + dz * dz / rr[e];
                 }
-                float g = kind_i == kRowNormal ? mu_i * sqrtf(vv[1] * vv[1] + vv[2] * vv[2]) : 0.f;
-                _Pragma("unroll") for (int e = 0; e < 3; ++e) if (e < blk) {
+                float g = kind_o == kRowNormal ? mu_o * sqrtf(vv[1] * vv[1] + vv[2] * vv[2]) : 0.f;
+                _Pragma("unroll") for (int e = 0; e < 3; ++e) if (e < blk_o) {
                     float d = vv[e] + (e == 0 ? g : 0.f) - zb[e];
                     lrd = fmaxf(lrd, fabsf(d));
                     if (d != d) lrd = d;
                 }
-                if (kind_i == kRowNormal) lrc = fabsf(yb[0] * (vv[0] + g) + yb[1] * vv[1] + yb[2] * vv[2]);
-                else if (kind_i == kRowLimit) lrc = fabsf(yb[0] * vv[0]);
+                if (kind_o == kRowNormal) lrc = fabsf(yb[0] * (vv[0] + g) + yb[1] * vv[1] + yb[2] * vv[2]);
+                else if (kind_o == kRowLimit) lrc = fabsf(yb[0] * vv[0]);
                 if (lrp != lrp || lcc != lcc) lrp = NAN;
             }
             reduce4<NT>(lrp, lrd, lrc, lcc, L.red);
@@ -1571,22 +1592,22 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
                     c_prev = c_prev / P.restart_factor;
                 }
             }
-            if (owner) {
-                _Pragma("unroll") for (int e = 0; e < 3; ++e) if (e < blk) {
-                    float yo = vyp[i + e], zo = vzp[i + e];
+            if (owner_o) {
+                _Pragma("unroll") for (int e = 0; e < 3; ++e) if (e < blk_o) {
+                    float yo = vyp[io + e], zo = vzp[io + e];
                     if (!P.accel) {
-                        vyh[i + e] = yb[e];
-                        vzh[i + e] = zb[e];
+                        vyh[io + e] = yb[e];
+                        vzh[io + e] = zb[e];
                     } else if (!restart) {
-                        vyh[i + e] = yb[e] + beta * (yb[e] - yo);
-                        vzh[i + e] = zb[e] + beta * (zb[e] - zo);
+                        vyh[io + e] = yb[e] + beta * (yb[e] - yo);
+                        vzh[io + e] = zb[e] + beta * (zb[e] - zo);
                     } else {
-                        vyh[i + e] = yo;
-                        vzh[i + e] = zo;
+                        vyh[io + e] = yo;
+                        vzh[io + e] = zo;
                     }
-                    vx[i + e] = vxn[i + e];
-                    vyp[i + e] = yb[e];
-                    vzp[i + e] = zb[e];
+                    vx[io + e] = vxn[io + e];
+                    vyp[io + e] = yb[e];
+                    vzp[io + e] = zb[e];
                 }
             }
             own_rhs();  // for the next iteration
