@@ -91,14 +91,15 @@ def compare_world(scene, params, g, w, replay=True, oracle_over=None, warm=None,
     import oracle.contacts as OC
     inp = dict(g.get("inputs") or {})
     inp.update(inputs or {})
+    # contacts of world w only (they depend on that world's state alone)
+    sw = scene.subset([w])
     if inp.get("box_bin") is not None:
         wx, wy, margin, cap = inp["box_bin"]
-        csc = OC.box_bin_contacts(scene, scene.q, wx, wy, margin, cap)
+        sub = OC.box_bin_contacts(sw, sw.q, wx, wy, margin, cap)
     elif inp.get("explicit", True):
-        csc = scene
+        sub = sw
     else:
-        csc = OC.probe_contacts(scene, scene.q, float(params.contact_margin))
-    sub = csc.subset([w])
+        sub = OC.probe_contacts(sw, sw.q, float(params.contact_margin))
     gsub = g["used_scene"].subset([w])
     assert np.array_equal(np.sort(gsub.contact_key), np.sort(sub.contact_key)), "contact sets differ"
     # the GPU's contact order (by key) mapped onto the oracle's
