@@ -21,6 +21,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32_VALU_TFLOPS = 157.3   # MI355X published FP32 vector peak
 PEAK_HBM_GBS = 8000.0
+PEAK_BF16_MFMA_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak
 
 
 def biped_workload(n_worlds, seed=1002):
@@ -155,6 +156,43 @@ def run_gpu(n_worlds, steps, warmup, warmstart, schedule, net=None, seed=None, w
     )
     model.close()
     return out
+
+
+def mlp_throughput(net, batch=4096, reps=50):
+    """Matrix-core throughput of the network's kernels on a resident batch:
+    the batched forward pass and the training step (forward, backward and
+    Adam), timed with HIP events on the launch stream.  Algorithmic flops:
+    2 x batch x (n_in H + H H + H n_out) per forward, 8/3 of that per
+    training step (three forward products; two weight-gradient and one
+    activation-gradient product per layer but the first).  The training
+    steps run at learning rate 0 (weights unchanged)."""
+    import torch
+
+    n_in, n_out, H = net.n_in, net.n_out, net.n_hidden
+    g = torch.Generator(device="cuda")
+    g.manual_seed(7)
+    x = torch.randn((batch, n_in), generator=g, device="cuda")
+    y = torch.randn((batch, n_out), generator=g, device="cuda")
+    out = torch.empty((batch, n_out), device="cuda")
+    loss = torch.zeros(1, device="cuda")
+    fwd = 2.0 * batch * (n_in * H + H * H + H * n_out)
+    stream = torch.cuda.current_stream()
+    res = {}
+    for name, fn, flops in [("forward", lambda: net.forward(x, out=out), fwd),
+                            ("train_step", lambda: net.train_step(x, y, 0.0, loss=loss), fwd * 8.0 / 3.0)]:
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        tf = flops / (ms * 1e-3) / 1e12
+        res[name] = {"ms": round(ms, 4), "tflops": round(tf, 3), "frac": round(tf / PEAK_BF16_MFMA_TFLOPS, 5)}
+    res.update({"bound": "mfma", "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s", "batch": batch})
+    return res
 
 
 def kamx_sched_chain():
@@ -338,7 +376,8 @@ def main():
             "network": "667 -> 256 -> 256 -> 224 (GELU), BF16 matrix-core kernels, FP32 accumulation",
             "training": {"samples": info["samples"], "held_out": info["held_out"], "epochs": args.epochs,
                          "final_train_loss": round(info["train_loss"][-1], 5), "val_loss": round(info["val_loss"], 5),
-                         "data_and_training_s": round(t_train, 2), "noise_seed": TRAIN_SEED}}
+                         "data_and_training_s": round(t_train, 2), "noise_seed": TRAIN_SEED},
+            "network_kernels": mlp_throughput(net, batch=min(4096, args.worlds))}
         net.close()
     if args.calibrate_copy:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")

@@ -25,6 +25,17 @@ namespace {
 constexpr int kTileM = 64, kTileN = 64, kTileK = 32;
 constexpr int kLdsRow = kTileK + 8;  // bf16 per LDS tile row (16-byte pad)
 constexpr int kGemmThreads = 256;
+constexpr int kColBlocks = 32;  // row blocks of the bias-gradient column sums
+
+// Weight gradients are sums over the batch (K): split K so that the
+// launch has about 512 workgroups, each slice at least 128 rows long.
+inline int grad_splits(int M, int N, int K) {
+    const int tiles = (M / kTileM) * (N / kTileN);
+    int s = 1;
+    while (tiles * s < 512 && K % (2 * s * kTileK) == 0 && K / (2 * s) >= 128) s *= 2;
+    return s;
+}
+
 
 // element (i, k) of an operand at p[i * si + k * sk]; one of the strides is 1
 struct Operand {
@@ -44,6 +55,7 @@ struct EpiArgs {
     long ldy;
     int batch, n_out;
     const float *mu, *sigma;
+    long split;         // store: stride between the K slices' partial results
 };
 
 
@@ -79,7 +91,9 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_kernel(Operand A, Operand B
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < K; k0 += kTileK) {
+    // split K: slice blockIdx.z of gridDim.z takes K / gridDim.z of the sum
+    const int kspan = K / (int)gridDim.z, kb = (int)blockIdx.z * kspan;
+    for (int k0 = kb; k0 < kb + kspan; k0 += kTileK) {
         __syncthreads();
         stage(A, m0, k0, As);
         stage(B, n0, k0, Bs);
@@ -117,7 +131,7 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_kernel(Operand A, Operand B
                     e.f32[m * e.ld + n] = dz;
                     e.b16[m * e.ld + n] = to_bf16(dz);
                 } else {
-                    e.f32[m * e.ld + n] = v;
+                    e.f32[(long)blockIdx.z * e.split + m * e.ld + n] = v;
                 }
             }
 }
@@ -174,22 +188,30 @@ __global__ void loss_final_kernel(const float *partial, int n, float scale, floa
     if (threadIdx.x == 0) loss[0] = red[0] * scale;
 }
 
-// Column sums of a [rows, n] FP32 matrix (bias gradients): 64 columns per
-// block, 16 row groups summed in a fixed order.
-__global__ __launch_bounds__(1024) void colsum_kernel(const float *a, int rows, int n, float *out) {
-    __shared__ float red[16][64];
+// Column sums of a [rows, n] FP32 matrix (bias gradients) in two passes
+// with a fixed order: block (x, y) sums rows y*rows/ny .. of 64 columns in
+// 4 row groups into partial[y][col]; then every column adds its ny partials.
+__global__ __launch_bounds__(256) void colsum_partial_kernel(const float *a, int rows, int n, float *partial) {
+    __shared__ float red[4][64];
     const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
     const int col = blockIdx.x * 64 + c;
+    const int span = rows / (int)gridDim.y, r0 = (int)blockIdx.y * span;
     float s = 0.f;
     if (col < n)
-        for (int r = g; r < rows; r += 16) s += a[(long)r * n + col];
+        for (int r = r0 + g; r < r0 + span; r += 4) s += a[(long)r * n + col];
     red[g][c] = s;
     __syncthreads();
-    if (g == 0 && col < n) {
-        float t = 0.f;
-        for (int k = 0; k < 16; ++k) t += red[k][c];
-        out[col] = t;
-    }
+    if (g == 0 && col < n) partial[(long)blockIdx.y * n + col] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
+}
+
+// out[i] = sum over s of part[s * stride + i], s in order (the partial
+// results of a split sum)
+__global__ void sum_slices_kernel(const float *part, long stride, int ns, long n, float *out) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float t = 0.f;
+    for (int k = 0; k < ns; ++k) t += part[(long)k * stride + i];
+    out[i] = t;
 }
 
 struct Layout {
@@ -260,6 +282,8 @@ struct kamx_mlp_s {
     __bf16 *xh = nullptr, *h1 = nullptr, *h2 = nullptr, *dyb = nullptr, *dz2b = nullptr, *dz1b = nullptr;
     float *z1 = nullptr, *z2 = nullptr, *yn = nullptr, *dy = nullptr, *dz2 = nullptr, *dz1 = nullptr;
     float *partial = nullptr;
+    float *ws = nullptr;  // partial sums of split weight gradients and bias gradients
+    long ws_floats = 0;
     std::vector<void *> allocs;
 };
 
@@ -358,6 +382,14 @@ extern "C" kamx_status kamx_mlp_create(int32_t n_in, int32_t n_hidden, int32_t n
     C_TRY(mlp_alloc(n, &n->dz2, R * H));
     C_TRY(mlp_alloc(n, &n->dz1, R * H));
     C_TRY(mlp_alloc(n, &n->partial, (R * std::max<long>(op, 1) + 255) / 256));
+    {
+        // split-K weight gradients: each of M x N outputs gets up to
+        // grad_splits(...) partials; bias gradients up to kColBlocks
+        const long a = (long)grad_splits(op, H, (int)R) * op * H, b = (long)grad_splits(H, H, (int)R) * H * H,
+                   c = (long)grad_splits(H, fp, (int)R) * H * fp, d = (long)kColBlocks * std::max(H, op);
+        n->ws_floats = std::max(std::max(a, b), std::max(c, d));
+        C_TRY(mlp_alloc(n, &n->ws, n->ws_floats));
+    }
     // initial weights U(-1/sqrt(fan_in), 1/sqrt(fan_in)) on the active
     // entries, zero on padding; identity normalisation
     std::vector<float> w(L.total, 0.f), one_in(fp, 1.f), one_out(op, 1.f);
@@ -420,6 +452,39 @@ template <int EPI>
 static hipError_t gemm(const Operand &A, const Operand &B, int M, int N, int K, const EpiArgs &e, hipStream_t s) {
     if (M % kTileM || N % kTileN || K % kTileK || M <= 0 || N <= 0 || K <= 0) return hipErrorInvalidValue;
     hipLaunchKernelGGL(gemm_kernel<EPI>, dim3(N / kTileN, M / kTileM), dim3(kGemmThreads), 0, s, A, B, M, N, K, e);
+    return hipGetLastError();
+}
+
+// C = A B^T summed over K into c (ldc = N), split over K with the partial
+// results reduced in slice order
+static hipError_t gemm_store(kamx_mlp n, const Operand &A, const Operand &B, int M, int N, int K, float *c,
+                             hipStream_t s) {
+    if (M % kTileM || N % kTileN || K % kTileK || M <= 0 || N <= 0 || K <= 0) return hipErrorInvalidValue;
+    const int ns = grad_splits(M, N, K);
+    if ((long)ns * M * N > n->ws_floats) return hipErrorInvalidValue;
+    EpiArgs e{};
+    e.f32 = ns > 1 ? n->ws : c;
+    e.ld = N;
+    e.split = (long)M * N;
+    hipLaunchKernelGGL(gemm_kernel<kEpiStore>, dim3(N / kTileN, M / kTileM, ns), dim3(kGemmThreads), 0, s, A, B, M,
+                       N, K, e);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess || ns == 1) return err;
+    const long cnt = (long)M * N;
+    hipLaunchKernelGGL(sum_slices_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, n->ws, cnt, ns, cnt,
+                       c);
+    return hipGetLastError();
+}
+
+// bias gradient: column sums of a [rows, cols] matrix
+static hipError_t colsum(kamx_mlp n, const float *a, int rows, int cols, float *out, hipStream_t s) {
+    int nb = kColBlocks;
+    while (nb > 1 && rows % nb) nb >>= 1;
+    hipLaunchKernelGGL(colsum_partial_kernel, dim3((cols + 63) / 64, nb), dim3(256), 0, s, a, rows, cols, n->ws);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(sum_slices_kernel, dim3((unsigned)((cols + 255) / 256)), dim3(256), 0, s, n->ws, (long)cols, nb,
+                       (long)cols, out);
     return hipGetLastError();
 }
 
@@ -515,11 +580,8 @@ extern "C" kamx_status kamx_mlp_train_step(kamx_mlp n, const float *x, const flo
     }
     EpiArgs e{};
     // layer 3: dW3 = dy^T h2, db3 = sum dy, dz2 = (dy W3) gelu'(z2)
-    e.f32 = n->g + L.oW3;
-    e.ld = H;
-    MLP_HIP((gemm<kEpiStore>(Operand{n->dyb, 1, op}, Operand{n->h2, 1, H}, op, H, R, e, s)));
-    hipLaunchKernelGGL(colsum_kernel, dim3(op / 64), dim3(1024), 0, s, n->dy, R, op, n->g + L.ob3);
-    MLP_HIP(hipGetLastError());
+    MLP_HIP(gemm_store(n, Operand{n->dyb, 1, op}, Operand{n->h2, 1, H}, op, H, R, n->g + L.oW3, s));
+    MLP_HIP(colsum(n, n->dy, R, op, n->g + L.ob3, s));
     e = EpiArgs{};
     e.z = n->z2;
     e.f32 = n->dz2;
@@ -527,12 +589,8 @@ extern "C" kamx_status kamx_mlp_train_step(kamx_mlp n, const float *x, const flo
     e.ld = H;
     MLP_HIP((gemm<kEpiBackward>(Operand{n->dyb, op, 1}, Operand{n->wb + L.bW3, 1, H}, R, H, op, e, s)));
     // layer 2
-    e = EpiArgs{};
-    e.f32 = n->g + L.oW2;
-    e.ld = H;
-    MLP_HIP((gemm<kEpiStore>(Operand{n->dz2b, 1, H}, Operand{n->h1, 1, H}, H, H, R, e, s)));
-    hipLaunchKernelGGL(colsum_kernel, dim3(H / 64), dim3(1024), 0, s, n->dz2, R, H, n->g + L.ob2);
-    MLP_HIP(hipGetLastError());
+    MLP_HIP(gemm_store(n, Operand{n->dz2b, 1, H}, Operand{n->h1, 1, H}, H, H, R, n->g + L.oW2, s));
+    MLP_HIP(colsum(n, n->dz2, R, H, n->g + L.ob2, s));
     e = EpiArgs{};
     e.z = n->z1;
     e.f32 = n->dz1;
@@ -540,12 +598,8 @@ extern "C" kamx_status kamx_mlp_train_step(kamx_mlp n, const float *x, const flo
     e.ld = H;
     MLP_HIP((gemm<kEpiBackward>(Operand{n->dz2b, H, 1}, Operand{n->wb + L.bW2, 1, H}, R, H, H, e, s)));
     // layer 1
-    e = EpiArgs{};
-    e.f32 = n->g + L.oW1;
-    e.ld = fp;
-    MLP_HIP((gemm<kEpiStore>(Operand{n->dz1b, 1, H}, Operand{n->xh, 1, fp}, H, fp, R, e, s)));
-    hipLaunchKernelGGL(colsum_kernel, dim3(H / 64), dim3(1024), 0, s, n->dz1, R, H, n->g + L.ob1);
-    MLP_HIP(hipGetLastError());
+    MLP_HIP(gemm_store(n, Operand{n->dz1b, 1, H}, Operand{n->xh, 1, fp}, H, fp, R, n->g + L.oW1, s));
+    MLP_HIP(colsum(n, n->dz1, R, H, n->g + L.ob1, s));
     // Adam
     n->t += 1;
     const float c1 = (float)(1.0 - pow(0.9, n->t)), c2 = (float)(1.0 - pow(0.999, n->t));
