@@ -552,6 +552,39 @@ def fourbar_world(rng, with_box=True, dt=1e-3, origin=(0.0, 0.0, 0.6), box_mu=0.
     return s
 
 
+def free_fourbar_world(rng, dt=1e-3, origin=(0.0, 0.0, 0.6), v_scale=0.3, w_scale=1.0):
+    """Four dynamic links (the four-bar's ground link as a body too) joined
+    in one closed loop, attached to nothing, with random twists (not
+    consistent with the joints) and no gravity: every constraint impulse is
+    internal to the mechanism."""
+    geo = fourbar_geometry(rng)
+    O = np.asarray(origin, np.float64)
+
+    def w3(p2):
+        return O + np.array([p2[0], 0.0, p2[1]])
+
+    A, P, Q, D = w3(np.zeros(2)), w3(geo["P"]), w3(geo["Q"]), w3(geo["D"])
+    masses = rng.uniform(0.1, 2.0, 4)
+    B = _Builder()
+    ground = _rod_body(B, A, D, masses[3])
+    crank = _rod_body(B, A, P, masses[0])
+    coupler = _rod_body(B, P, Q, masses[1])
+    rocker = _rod_body(B, D, Q, masses[2])
+    y = (0.0, 1.0, 0.0)
+    B.joint(REVOLUTE, crank, ground, A, y)
+    B.joint(REVOLUTE, coupler, crank, P, y)
+    B.joint(REVOLUTE, rocker, coupler, Q, y)
+    B.joint(REVOLUTE, rocker, ground, D, y)
+    s = B.scene(dt, gravity=(0.0, 0.0, 0.0))
+    s.u = np.concatenate([rng.normal(0.0, v_scale, (s.n_bodies, 3)), rng.normal(0.0, w_scale, (s.n_bodies, 3))], axis=1)
+    return s
+
+
+def free_fourbar_batch(n_worlds, seed=1006, dt=1e-3):
+    rng = np.random.default_rng(seed)
+    return concat([free_fourbar_world(rng, dt) for _ in range(n_worlds)])
+
+
 def fourbar_batch(n_worlds, seed=1001, with_box=True, dt=1e-3):
     rng = np.random.default_rng(seed)
     return concat([fourbar_world(rng, with_box, dt) for _ in range(n_worlds)])
