@@ -1320,15 +1320,29 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
             for (int q = 0; q < 2; ++q) {
                 const int Tj = wv + q * NW;
                 if (Tj >= Ti) continue;
-                mfx4 acc = {0.f, 0.f, 0.f, 0.f};
-                for (int Tk = Tj; Tk < Ti; ++Tk) {
-                    const float *Mr = A + tri_row_offset(i0 + fr) + 16 * Tk;
+                // the diagonal tile X_jj (lower triangular) first, then the full
+                // tiles below it with unconditional loads, alternating between
+                // two accumulators so consecutive products do not wait on
+                // each other
+                mfx4 acc = {0.f, 0.f, 0.f, 0.f}, accb = {0.f, 0.f, 0.f, 0.f};
+                const float *Mr = A + tri_row_offset(i0 + fr);
+                const int jc = 16 * Tj + fr;
+#pragma unroll
+                for (int ch = 0; ch < 4; ++ch) {
+                    const int kr = 16 * Tj + 4 * ch + fk;
+                    acc = mfma4(Mr[16 * Tj + 4 * ch + fk], tri_at(A, kr, jc), acc);
+                }
+                for (int Tk = Tj + 1; Tk < Ti; ++Tk) {
 #pragma unroll
                     for (int ch = 0; ch < 4; ++ch) {
-                        const int kr = 16 * Tk + 4 * ch + fk, jc = 16 * Tj + fr;
-                        acc = mfma4(Mr[4 * ch + fk], tri_at(A, kr, jc), acc);
+                        const int kr = 16 * Tk + 4 * ch + fk;
+                        const float mv = Mr[16 * Tk + 4 * ch + fk], xv = A[tri_row_offset(kr) + jc];
+                        if (ch & 1) accb = mfma4(mv, xv, accb);
+                        else acc = mfma4(mv, xv, acc);
                     }
                 }
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[c] += accb[c];
                 if (q == 0) acc0 = acc;
                 else acc1 = acc;
             }
