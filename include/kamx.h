@@ -230,8 +230,11 @@ kamx_status kamx_contacts_upload(kamx_model m, const kamx_contact *contacts_dev,
  * of the world.  Candidates with gap below margin are kept, the deepest
  * first (ties by key), up to max_contacts_per_world.  At most 20 boxes per
  * world.  Replaces probe and uploaded contacts until kamx_contacts_upload is
- * called; boxes = NULL turns generation off.  EINVAL on bad geometry or a
- * model without contact capacity. */
+ * called; boxes = NULL turns generation off.  When every size bucket holds
+ * at least 160 rows, each step kernel generates its world's contacts from
+ * the poses the step starts from (and multi-step calls run chained);
+ * otherwise a generation kernel runs before every step.  EINVAL on bad
+ * geometry or a model without contact capacity. */
 kamx_status kamx_contacts_box_bin(kamx_model m, const kamx_box_desc *boxes, float half_x, float half_y,
                                   float margin);
 
@@ -253,9 +256,9 @@ kamx_status kamx_set_warmstart(kamx_model m, const float *lambda_dev, kamx_strea
  * slow steps recur.  CHAIN keeps each world on one workgroup for a run of
  * steps, so a slow solve delays only its own world and the hardware
  * balances whole chains.  Chains apply to calls of kamx_step with
- * nsteps > 1 when every step's inputs are on the device already (no
- * generated contacts); otherwise steps are launched one by one.  Host-side,
- * synchronous; EINVAL on an unknown mode. */
+ * nsteps > 1 unless contacts come from a generation kernel launched before
+ * every step (boxes in a bin with buckets below 160 rows); then steps are
+ * launched one by one.  Host-side, synchronous; EINVAL on an unknown mode. */
 kamx_status kamx_set_schedule(kamx_model m, int32_t mode);
 
 /* Size buckets (Sec. 5.2: worlds of different sizes share one call; each

@@ -22,6 +22,7 @@ hipError_t launch_advance_step(uint32_t *ctr, uint32_t inc, hipStream_t stream);
 hipError_t launch_box_bin(const WorldInfo *worlds, int n_worlds, const float *q, const float *box_geom, float wx,
                           float wy, float margin, kamx_contact *out, int32_t *count, hipStream_t stream);
 int box_bin_max_boxes();
+bool step_generates_box_contacts(int mc);
 hipError_t launch_impulse_slots(const WorldInfo *worlds, int n_worlds, int n_contact_slots, int n_slots,
                                 const float *lambda, const int32_t *keys, const int32_t *ncontacts, float *out,
                                 hipStream_t stream);
@@ -112,6 +113,7 @@ struct kamx_model_s {
     float *d_ws = nullptr;  // network prediction by slot [n_worlds * n_slots]
     // generated contacts (boxes in a bin)
     bool box_bin = false;
+    bool box_fused = false;  // every bucket's step kernel generates the contacts itself
     float bin_wx = 0.f, bin_wy = 0.f, bin_margin = 0.f;
     float *d_box_geom = nullptr;
     kamx_contact *d_gen = nullptr;
@@ -568,6 +570,12 @@ static StepArgs step_args(kamx_model m) {
     a.ext_tau = m->d_ext;
     a.pbody = m->d_pbody;
     a.pf = m->d_pf;
+    if (m->box_bin && m->box_fused) {
+        a.box_geom = m->d_box_geom;
+        a.bin_wx = m->bin_wx;
+        a.bin_wy = m->bin_wy;
+        a.bin_margin = m->bin_margin;
+    }
     a.contacts = m->box_bin ? m->d_gen : m->d_contacts;
     a.coff = m->d_coff;
     a.ccount = m->box_bin ? m->d_gen_count : nullptr;
@@ -640,7 +648,7 @@ static kamx_status enqueue_launch(kamx_model m, int n, int pos, hipStream_t s) {
         base.iter_log_rows = m->iter_log_rows - pos;
     }
     const bool lpt = n == 1 && m->schedule != KAMX_SCHED_INDEX;
-    if (m->box_bin) {
+    if (m->box_bin && !m->box_fused) {
         hipError_t e = launch_box_bin(m->d_worlds, m->n_worlds, m->d_q, m->d_box_geom, m->bin_wx, m->bin_wy,
                                       m->bin_margin, m->d_gen, m->d_gen_count, s);
         if (e != hipSuccess) return fail(KAMX_EDEVICE, "contact generation launch: %s", hipGetErrorString(e));
@@ -677,7 +685,7 @@ static kamx_status enqueue_launch(kamx_model m, int n, int pos, hipStream_t s) {
     return KAMX_OK;
 }
 
-static bool chained(kamx_model m) { return m->schedule == KAMX_SCHED_CHAIN && !m->box_bin; }
+static bool chained(kamx_model m) { return m->schedule == KAMX_SCHED_CHAIN && (!m->box_bin || m->box_fused); }
 
 // Enqueue nsteps steps from position pos of the current call.
 static kamx_status enqueue_steps(kamx_model m, int nsteps, hipStream_t s, int pos = 0) {
@@ -846,7 +854,7 @@ static kamx_status enqueue_bucket_trial(kamx_model m, int bi, int steps, hipStre
     const bool chain = chained(m);
     for (int k = 0; k < steps;) {
         const int n = chain ? steps - k : 1;
-        if (m->box_bin) {
+        if (m->box_bin && !m->box_fused) {
             hipError_t e = launch_box_bin(m->d_worlds, m->n_worlds, m->d_q, m->d_box_geom, m->bin_wx, m->bin_wy,
                                           m->bin_margin, m->d_gen, m->d_gen_count, s);
             if (e != hipSuccess) return fail(KAMX_EDEVICE, "contact generation launch: %s", hipGetErrorString(e));
@@ -1035,6 +1043,8 @@ kamx_status kamx_contacts_box_bin(kamx_model m, const kamx_box_desc *boxes, floa
     m->bin_wy = half_y;
     m->bin_margin = margin;
     m->box_bin = true;
+    m->box_fused = true;
+    for (const Bucket &b : m->buckets) m->box_fused = m->box_fused && step_generates_box_contacts(b.mc);
     return KAMX_OK;
 }
 

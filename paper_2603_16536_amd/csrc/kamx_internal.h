@@ -94,6 +94,8 @@ struct StepArgs {
     const int32_t *pbody;  // [np] local body
     const float *pf;       // [np*4]: point, mu
     // explicit contacts
+    const float *box_geom;         // non-null: contacts generated in the step (boxes in a bin)
+    float bin_wx, bin_wy, bin_margin;
     const kamx_contact *contacts;  // null: use probes
     const int32_t *coff;           // [n_worlds+1]
     const int32_t *ccount;         // non-null: contacts of world w at w * kMaxContacts, ccount[w] of them

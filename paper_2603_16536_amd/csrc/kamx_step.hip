@@ -19,6 +19,7 @@
 //   output: lambda = P y, u+ = u_f + M^-1 J^T lambda, SO(3) exponential map.
 #include <math.h>
 
+#include "kamx_boxbin.h"
 #include "kamx_internal.h"
 
 namespace kamx {
@@ -781,7 +782,33 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
     // ---- contacts: explicit list, or probes below the margin (compacted in
     //      probe order by a wave ballot)
     int *cint = reinterpret_cast<int *>(L.c);
-    if (a.contacts) {
+    constexpr bool kBoxFits = (long)sizeof(float) * (8L * (MC / 4) * (MC / 4 + 1)) >= (long)sizeof(BoxLds);
+    if (kBoxFits && a.box_geom) {
+        // boxes in a bin: contacts generated here from the poses the step
+        // starts from, with the candidates in the LDS of the Delassus
+        // triangle (free until the assembly)
+        if constexpr (kBoxFits) {
+            BoxLds &S = *reinterpret_cast<BoxLds *>(A);
+            const int n = box_bin_generate<NT>(
+                S, nb, a.box_geom + 4 * (long)W.b0, a.bin_wx, a.bin_wy, a.bin_margin, W.contact_cap,
+                [&](int b, float c[3], float qt[4]) {
+                    for (int e = 0; e < 3; ++e) c[e] = L.bf(BQ + e, b);
+                    for (int e = 0; e < 4; ++e) qt[e] = L.bf(BQ + 3 + e, b);
+                },
+                [&](int c, int key, float gap, const float p[3], const float nn[3], float mu, int la, int lb) {
+                    for (int e = 0; e < 3; ++e) {
+                        L.cf(CP + e, c) = p[e];
+                        L.cf(CN + e, c) = nn[e];
+                    }
+                    L.cf(CGAP, c) = gap;
+                    L.cf(CMU, c) = mu;
+                    cint[CA * kMaxContacts + c] = la;
+                    cint[CB * kMaxContacts + c] = lb;
+                    cint[CKEY * kMaxContacts + c] = key;
+                });
+            if (tid == 0) s_int[1] = n;
+        }
+    } else if (a.contacts) {
         int c0 = a.ccount ? w * kMaxContacts : a.coff[w];
         int n = a.ccount ? a.ccount[w] : a.coff[w + 1] - c0;
         if (n > W.contact_cap) n = W.contact_cap;
@@ -1876,5 +1903,11 @@ hipError_t launch_step(const StepArgs &args, int mc, int nt, int n, hipStream_t 
 }
 
 size_t step_smem_bytes(int mc) { return sizeof(float) * (size_t)smem_floats(mc); }
+
+// whether the step kernel of a row bucket can generate box-bin contacts
+// itself (the candidates must fit in the LDS of its Delassus triangle)
+bool step_generates_box_contacts(int mc) {
+    return sizeof(float) * (size_t)tri_row_offset(mc) >= sizeof(BoxLds);
+}
 
 }  // namespace kamx

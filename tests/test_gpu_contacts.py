@@ -22,8 +22,8 @@ HALF = scenes.BIN_HALF
 PARAMS = dict(dt=2e-3, eta=1e-4, rho_bilateral=1e-4, rho_contact=0.3, eps=1e-6, max_iters=2000, log_restarts=1)
 
 
-def run_one_step(scene, params=PARAMS):
-    m = kamx.Model(scene, params=params, max_contacts=64)
+def run_one_step(scene, params=PARAMS, cap=64):
+    m = kamx.Model(scene, params=params, max_contacts=cap)
     m.contacts_box_bin(HALF, MARGIN)
     m.step(1)
     torch.cuda.synchronize()
@@ -32,16 +32,20 @@ def run_one_step(scene, params=PARAMS):
     g = dict(u=m.state()[1].cpu().numpy().astype(np.float64), lam=m.impulses().cpu().numpy().astype(np.float64),
              row_offsets=m.row_offsets, restart_log=m.restart_log().cpu().numpy(),
              used_scene=kamx.contacts_to_scene(scene, raw, cnt),
-             inputs=dict(box_bin=(HALF[0], HALF[1], MARGIN, 64), ext=None, step=0), **st)
+             inputs=dict(box_bin=(HALF[0], HALF[1], MARGIN, cap), ext=None, step=0), **st)
     m.close()
     return g
 
 
-def test_box_bin_contacts_match_oracle_generator():
+@pytest.mark.parametrize("cap", [64, 16])
+def test_box_bin_contacts_match_oracle_generator(cap):
+    """cap 64 (192-row bucket): the step kernel generates the contacts
+    itself; cap 16 (48 rows, a 64-row bucket): the generation kernel runs
+    before the step.  Both keep the deepest contacts up to the cap."""
     scene = scenes.round_to_f32(scenes.box_bin_resting_batch(16, seed=1005))
-    g = run_one_step(scene)
+    g = run_one_step(scene, cap=cap)
     dev = g["used_scene"]
-    ref = OC.box_bin_contacts(scene, scene.q, HALF[0], HALF[1], MARGIN, 64)
+    ref = OC.box_bin_contacts(scene, scene.q, HALF[0], HALF[1], MARGIN, cap)
     dco, rco = dev.contact_offsets(), ref.contact_offsets()
     for w in range(16):
         dk = dev.contact_key[dco[w]:dco[w + 1]]
