@@ -39,6 +39,8 @@ WORKLOADS = {
               "concurrent size buckets, dt 2 ms, PADMM to 1e-6 (cap 200)",
     "boxbin": "box-bin-{n}: 20 boxes per world falling into a 0.3 m bin, vertex-face contacts generated every "
               "step (at most 64, 192 rows), dt 2 ms, PADMM to 1e-6 (cap 200)",
+    "fourbar": "four-bar-{n}: closed four-bar (3 dynamic links, 20 rows) and a 1 kg cube sliding on the ground "
+               "(4 contacts, 12 rows), dt 1 ms, exactly 50 PADMM iterations",
 }
 TRAIN_SEED = 2002  # noise seed of the rollout that feeds training (the timed rollouts use CFG2's)
 
@@ -103,6 +105,13 @@ def make_model(workload, n_worlds, warmstart, schedule, seed=None):
         # per-joint gains of each structure; a 200-iteration budget (the
         # excavator's rounded loops keep a residual floor above 1e-6)
         model = kamx.Model(scene, params=dict(params, max_iters=200))
+    elif workload == "fourbar":
+        scene = scenes.round_to_f32(scenes.fourbar_batch(n_worlds, seed=1001))
+        # the cube's corner probes give its contacts every step
+        model = kamx.Model(scene, params=dict(dt=1e-3, eta=1e-4, rho_bilateral=1e-6, rho_contact=1.0, fixed_iters=50,
+                                              max_iters=50, torque_sigma=0.0, contact_margin=0.02,
+                                              warmstart=warmstart),
+                           max_contacts=4)
     elif workload == "boxbin":
         scene = scenes.round_to_f32(scenes.box_bin_batch(n_worlds, seed=1005))
         model = kamx.Model(scene, params=dict(params, torque_sigma=0.0, max_iters=200), max_contacts=64)
@@ -303,7 +312,7 @@ def main():
         args.no_cpu = True
     cold = run_gpu(args.worlds, args.steps, args.warmup, kamx.WARM_COLD, sched, workload=args.workload,
                    autotune=not args.no_autotune)
-    cap = CFG2["max_iters"] if args.workload == "biped" else 200
+    cap = {"biped": CFG2["max_iters"], "fourbar": 51}.get(args.workload, 200)
     value = args.worlds * args.steps / cold["wall_s"]
     it = cold["iters"]
     conv = float((it < cap).mean())
