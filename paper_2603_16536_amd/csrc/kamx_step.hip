@@ -1485,8 +1485,9 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
             KAMX_MARK(2);
             // x_new = x + X^T t over column quads: quads c and Q-1-c form a
             // pair (balanced: together they span m + 4 rows); 16 threads per
-            // pair take every 16th row, each reading the row's 4 entries of
-            // the quad as one float4; butterfly sum over the 16 threads
+            // pair take every 16th group of 4 rows, each reading a group's t
+            // and the 4 rows' entries of the quad as float4s; butterfly sum
+            // over the 16 threads
             {
                 const int Q = (m + 3) >> 2;
                 const int g = tid >> 4, kq = tid & 15;
@@ -1498,29 +1499,33 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
                         if (part == 1 && c2 == c1) break;
                         const int c = part == 0 ? c1 : c2;
                         float4 acc = make_float4(0.f, 0.f, 0.f, 0.f), acc2 = acc;
-                        int r = 4 * c + kq;
-                        // packed rows are padded to 4 floats and the pads hold 0,
-                        // so the quad that contains the diagonal reads as-is
-                        for (; r + 16 < m; r += 32) {
-                            const float4 xa = *reinterpret_cast<const float4 *>(A + tri_row_offset(r) + 4 * c);
-                            const float4 xb = *reinterpret_cast<const float4 *>(A + tri_row_offset(r + 16) + 4 * c);
-                            const float ta = vt[r], tb = vt[r + 16];
-                            acc.x += xa.x * ta;
-                            acc.y += xa.y * ta;
-                            acc.z += xa.z * ta;
-                            acc.w += xa.w * ta;
-                            acc2.x += xb.x * tb;
-                            acc2.y += xb.y * tb;
-                            acc2.z += xb.z * tb;
-                            acc2.w += xb.w * tb;
-                        }
-                        if (r < m) {
-                            const float4 xa = *reinterpret_cast<const float4 *>(A + tri_row_offset(r) + 4 * c);
-                            const float ta = vt[r];
-                            acc.x += xa.x * ta;
-                            acc.y += xa.y * ta;
-                            acc.z += xa.z * ta;
-                            acc.w += xa.w * ta;
+                        // four consecutive rows per step (one float4 of t), every
+                        // 64th row group; packed rows are padded to 4 floats and
+                        // the pads hold 0, so the quad that contains the diagonal
+                        // reads as-is, and t is 0 past row m (the rows there, up
+                        // to the next multiple of 4, hold finite values)
+                        for (int r = 4 * c + 4 * kq; r < m; r += 64) {
+                            const float4 tv = *reinterpret_cast<const float4 *>(vt + r);
+                            const float4 x0 = *reinterpret_cast<const float4 *>(A + tri_row_offset(r) + 4 * c);
+                            const float4 x1 = *reinterpret_cast<const float4 *>(A + tri_row_offset(r + 1) + 4 * c);
+                            const float4 x2 = *reinterpret_cast<const float4 *>(A + tri_row_offset(r + 2) + 4 * c);
+                            const float4 x3 = *reinterpret_cast<const float4 *>(A + tri_row_offset(r + 3) + 4 * c);
+                            acc.x += x0.x * tv.x;
+                            acc.y += x0.y * tv.x;
+                            acc.z += x0.z * tv.x;
+                            acc.w += x0.w * tv.x;
+                            acc2.x += x1.x * tv.y;
+                            acc2.y += x1.y * tv.y;
+                            acc2.z += x1.z * tv.y;
+                            acc2.w += x1.w * tv.y;
+                            acc.x += x2.x * tv.z;
+                            acc.y += x2.y * tv.z;
+                            acc.z += x2.z * tv.z;
+                            acc.w += x2.w * tv.z;
+                            acc2.x += x3.x * tv.w;
+                            acc2.y += x3.y * tv.w;
+                            acc2.z += x3.z * tv.w;
+                            acc2.w += x3.w * tv.w;
                         }
                         acc.x += acc2.x;
                         acc.y += acc2.y;
