@@ -1,0 +1,96 @@
+"""Loop structure of the synthetic workloads.
+
+Independent closed kinematic chains are the cyclomatic number of the joint
+graph (bodies and the world as nodes, joints as edges): E - V + C.  The count
+is pinned against the paper's own systems table (Sec. 6.1, Tab. 1;
+`golden/systems_tab1.txt`), then used to check that every seeded generator
+builds the topology its workload recipe states (joints, bodies, loops)."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2603_16536_amd import scenes
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def read_tab1():
+    rows = []
+    for line in open(os.path.join(HERE, "golden", "systems_tab1.txt")):
+        line = line.split("#", 1)[0].split()
+        if line:
+            name, nb, na, npas, loops, base = line
+            rows.append((name, int(nb), int(na), int(npas), int(loops), base))
+    return rows
+
+
+def cyclomatic(n_nodes, edges):
+    """E - V + C of an undirected multigraph (union-find over the nodes)."""
+    parent = list(range(n_nodes))
+
+    def find(a):
+        while parent[a] != a:
+            parent[a] = parent[parent[a]]
+            a = parent[a]
+        return a
+
+    for a, b in edges:
+        ra, rb = find(a), find(b)
+        if ra != rb:
+            parent[ra] = rb
+    comps = len({find(a) for a in range(n_nodes)})
+    return len(edges) - n_nodes + comps
+
+
+def world_topology(scene, w):
+    """(bodies, joints by type, loops) of world w; node 0 is the fixed world."""
+    bo, jo = scene.body_offsets(), scene.joint_offsets()
+    b0, b1, j0, j1 = bo[w], bo[w + 1], jo[w], jo[w + 1]
+    edges = []
+    for a, b in scene.joint_body[j0:j1]:
+        edges.append((0 if a < 0 else a - b0 + 1, 0 if b < 0 else b - b0 + 1))
+    types = np.bincount(scene.joint_type[j0:j1], minlength=2)
+    return b1 - b0, types, cyclomatic(b1 - b0 + 1, edges)
+
+
+def test_cyclomatic_number_reproduces_the_paper_table():
+    rows = read_tab1()
+    assert [r[0] for r in rows] == ["DR_Legs", "BDX", "Olaf", "Iron_Man"]
+    for name, nb, na, npas, loops, base in rows:
+        joints = na + npas
+        if base == "tree":
+            assert loops == 0, name
+            continue
+        # one connected system: the world joins as a node only when a joint reaches it
+        nodes = nb + (1 if base == "fixed" else 0)
+        assert joints - nodes + 1 == loops, name
+
+
+def test_cyclomatic_number_on_small_graphs():
+    assert cyclomatic(4, [(0, 1), (1, 2), (2, 3), (3, 0)]) == 1       # one ring
+    assert cyclomatic(5, [(0, 1), (1, 2), (2, 3), (3, 0)]) == 1       # plus an isolated node
+    assert cyclomatic(3, [(0, 1), (0, 1), (1, 2)]) == 1               # parallel joints close a loop
+    assert cyclomatic(6, [(0, 1), (1, 2), (2, 0), (3, 4), (4, 5), (5, 3)]) == 2
+    assert cyclomatic(4, [(0, 1), (1, 2), (2, 3)]) == 0               # a chain
+
+
+@pytest.mark.parametrize("make,bodies,revolute,prismatic,loops", [
+    (lambda: scenes.fourbar_batch(8, seed=1001), 4, 4, 0, 1),        # three links + cube, ground = world
+    (lambda: scenes.free_fourbar_batch(8, seed=1006), 4, 4, 0, 1),
+    (lambda: scenes.biped_batch(8, seed=1002), 31, 40, 0, 10),
+    (lambda: scenes.excavator_batch(8, seed=1003), 12, 13, 3, 4),
+    (lambda: scenes.box_bin_batch(4, seed=1005), 20, 0, 0, 0),
+])
+def test_generators_build_the_stated_topology(make, bodies, revolute, prismatic, loops):
+    scene = make()
+    for w in range(scene.n_worlds):
+        nb, types, cyc = world_topology(scene, w)
+        assert (nb, int(types[scenes.REVOLUTE]), int(types[scenes.PRISMATIC]), cyc) == \
+            (bodies, revolute, prismatic, loops), w
+
+
+def test_heterogeneous_batch_mixes_the_three_topologies():
+    scene = scenes.heterogeneous_batch(12, seed=1003)
+    seen = {world_topology(scene, w)[2] for w in range(scene.n_worlds)}
+    assert seen == {1, 10, 4}
