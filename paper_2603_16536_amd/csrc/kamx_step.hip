@@ -1091,7 +1091,7 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
     //      z = v~(y) + Gamma(v~(y)) on unilateral rows, 0 on bilateral rows
     float *vx = L.vec(VX), *vyh = L.vec(VYH), *vzh = L.vec(VZH), *vyp = L.vec(VYP), *vzp = L.vec(VZP);
     float *vrhs = L.vec(VRHS), *vt = L.vec(VT), *vxn = L.vec(VXN), *vws = L.vec(VWS), *vaux = L.vec(VAUX);
-    float *vcol = L.vec(VCOL), *vdx = L.vec(VDX);
+    float *vrinv = L.vec(VCOL), *vdx = L.vec(VDX);  // vrinv: 1/rho per row inside the iteration loop
     const int wmode = reset ? KAMX_WARM_COLD : P.warmstart;
     const int kind_i = i < m ? L.ri(RKIND, i) : -1;
     const bool owner = i < m && kind_i != kRowTangent;
@@ -1409,6 +1409,7 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
     int it = 0, status = 0;
     float rp = 0.f, rd = 0.f, rc = 0.f, rncp = 0.f;
     const int N = P.fixed_iters > 0 ? P.fixed_iters : P.max_iters;
+    if (i < m) vrinv[i] = 1.f / vrho[i];  // rho is fixed for the solve: divide once
     if (factor_fail) {
         status = KAMX_WORLD_FACTOR_FAIL;
         rp = rd = rc = rncp = NAN;
@@ -1585,28 +1586,29 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
             }
             __syncthreads();
             if (owner_o) {
-                float xn[3], zh[3], yh[3], rr[3], vv[3];
+                float xn[3], zh[3], yh[3], rr[3], ri[3], vv[3];
                 _Pragma("unroll") for (int e = 0; e < 3; ++e) if (e < blk_o) {
                     const float dx = vdx[io + e];
                     xn[e] = vxn[io + e];
                     zh[e] = vzh[io + e];
                     yh[e] = vyh[io + e];
                     rr[e] = e == 0 ? rho_o : vrho[io + e];
+                    ri[e] = vrinv[io + e];
                     vv[e] = dx + vvt[io + e];
                 }
                 if (kind_o == kRowNormal) {
-                    proj_cone(mu_o, xn[0] - zh[0] / rr[0], xn[1] - zh[1] / rr[1], xn[2] - zh[2] / rr[2], yb[0], yb[1],
+                    proj_cone(mu_o, xn[0] - zh[0] * ri[0], xn[1] - zh[1] * ri[1], xn[2] - zh[2] * ri[2], yb[0], yb[1],
                               yb[2]);
                 } else if (kind_o == kRowLimit) {
-                    yb[0] = fmaxf(xn[0] - zh[0] / rr[0], 0.f);
+                    yb[0] = fmaxf(xn[0] - zh[0] * ri[0], 0.f);
                 } else {
-                    yb[0] = xn[0] - zh[0] / rr[0];
+                    yb[0] = xn[0] - zh[0] * ri[0];
                 }
                 _Pragma("unroll") for (int e = 0; e < 3; ++e) if (e < blk_o) {
                     zb[e] = zh[e] - rr[e] * (xn[e] - yb[e]);
                     lrp = fmaxf(lrp, fabsf(xn[e] - yb[e]));
                     float dy = yb[e] - yh[e], dz = zb[e] - zh[e];
-                    lcc += rr[e] * dy * dy + dz * dz / rr[e];
+                    lcc += rr[e] * dy * dy + dz * dz * ri[e];
                 }
                 float g = kind_o == kRowNormal ? mu_o * sqrtf(vv[1] * vv[1] + vv[2] * vv[2]) : 0.f;
                 _Pragma("unroll") for (int e = 0; e < 3; ++e) if (e < blk_o) {
