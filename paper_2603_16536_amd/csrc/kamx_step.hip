@@ -117,8 +117,14 @@ __device__ inline void tangents(const float n[3], float t1[3], float t2[3]) {
 }
 
 // Projection on the Coulomb cone K_mu = {|l_t| <= mu l_n}.
+// Square root and reciprocal by the hardware instructions (within 1 ulp;
+// the correctly rounded forms take about ten instructions each), for the
+// scalars the iteration recomputes every step.
+__device__ inline float hw_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ inline float hw_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 __device__ inline void proj_cone(float mu, float w0, float w1, float w2, float &o0, float &o1, float &o2) {
-    float tn = sqrtf(w1 * w1 + w2 * w2);
+    float tn = hw_sqrt(w1 * w1 + w2 * w2);
     if (tn <= mu * w0) {
         o0 = w0;
         o1 = w1;
@@ -126,8 +132,8 @@ __device__ inline void proj_cone(float mu, float w0, float w1, float w2, float &
     } else if (mu * tn <= -w0) {
         o0 = o1 = o2 = 0.f;
     } else {
-        float ln = (mu * tn + w0) / (1.f + mu * mu);
-        float s = tn > 0.f ? mu * ln / tn : 0.f;
+        float ln = (mu * tn + w0) * hw_rcp(1.f + mu * mu);
+        float s = tn > 0.f ? mu * ln * hw_rcp(tn) : 0.f;
         o0 = ln;
         o1 = s * w1;
         o2 = s * w2;
@@ -1434,7 +1440,7 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
         // owner computes it for the next iteration at the end of the update)
         auto own_rhs = [&]() {
             if (owner_o) {
-                s_own = kind_o == kRowNormal ? mu_o * sqrtf(vzh[io + 1] * vzh[io + 1] + vzh[io + 2] * vzh[io + 2]) : 0.f;
+                s_own = kind_o == kRowNormal ? mu_o * hw_sqrt(vzh[io + 1] * vzh[io + 1] + vzh[io + 2] * vzh[io + 2]) : 0.f;
                 _Pragma("unroll") for (int e = 0; e < 3; ++e) if (e < blk_o) {
                     float rr = e == 0 ? rho_o : vrho[io + e];
                     float xe = vx[io + e];
@@ -1610,7 +1616,7 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
                     float dy = yb[e] - yh[e], dz = zb[e] - zh[e];
                     lcc += rr[e] * dy * dy + dz * dz * ri[e];
                 }
-                float g = kind_o == kRowNormal ? mu_o * sqrtf(vv[1] * vv[1] + vv[2] * vv[2]) : 0.f;
+                float g = kind_o == kRowNormal ? mu_o * hw_sqrt(vv[1] * vv[1] + vv[2] * vv[2]) : 0.f;
                 _Pragma("unroll") for (int e = 0; e < 3; ++e) if (e < blk_o) {
                     float d = vv[e] + (e == 0 ? g : 0.f) - zb[e];
                     lrd = fmaxf(lrd, fabsf(d));
@@ -1631,8 +1637,8 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
             if (P.accel) {
                 restart = !(lcc < P.restart_factor * c_prev);
                 if (!restart) {
-                    float a_next = 0.5f * (1.f + sqrtf(1.f + 4.f * a_k * a_k));
-                    beta = (a_k - 1.f) / a_next;
+                    float a_next = 0.5f * (1.f + hw_sqrt(1.f + 4.f * a_k * a_k));
+                    beta = (a_k - 1.f) * hw_rcp(a_next);
                     a_k = a_next;
                     c_prev = lcc;
                 } else {
