@@ -423,15 +423,22 @@ __device__ inline T lane_group_sum(T v) {
     return v;
 }
 
-// max that propagates NaN (a NaN residual must stop the solve)
-__device__ inline float nanmax(float a, float b) { return (b > a || b != b) ? b : a; }
+// Maximum of values that are +0 or above, or NaN of either sign: as
+// unsigned integers their bit patterns order like the numbers and every NaN
+// lies above +inf, so one integer max keeps a NaN (a NaN residual must stop
+// the solve). Negative numbers and -0 would compare wrongly: callers pass
+// absolute values.
+__device__ inline float max_nonneg(float a, float b) {
+    const unsigned ua = __float_as_uint(a), ub = __float_as_uint(b);
+    return __uint_as_float(ub > ua ? ub : ua);
+}
 
 template <int G>
 __device__ inline float lane_group_max(float v) {
-    if (G >= 2) v = nanmax(v, dpp<kDppXor1>(v));
-    if (G >= 4) v = nanmax(v, dpp<kDppXor2>(v));
-    if (G >= 8) v = nanmax(v, dpp<kDppMirror8>(v));
-    if (G >= 16) v = nanmax(v, dpp<kDppMirror16>(v));
+    if (G >= 2) v = max_nonneg(v, dpp<kDppXor1>(v));
+    if (G >= 4) v = max_nonneg(v, dpp<kDppXor2>(v));
+    if (G >= 8) v = max_nonneg(v, dpp<kDppMirror8>(v));
+    if (G >= 16) v = max_nonneg(v, dpp<kDppMirror16>(v));
     return v;
 }
 
@@ -450,14 +457,15 @@ template <int NT>
 __device__ inline void reduce4(float &m0, float &m1, float &m2, float &s3, float *red) {
     // rows of 16 lanes by DPP, then the wave's four rows through readlane,
     // then the waves in order through LDS; every step combines two values
-    // that the partner combines in the other order, so all lanes agree
+    // that the partner combines in the other order, so all lanes agree.
+    // m0, m1, m2 are +0 or above, or NaN (maxima of absolute values)
     m0 = lane_group_max<16>(m0);
     m1 = lane_group_max<16>(m1);
     m2 = lane_group_max<16>(m2);
     s3 = lane_group_sum<16>(s3);
-    m0 = nanmax(nanmax(rdlane(m0, 0), rdlane(m0, 16)), nanmax(rdlane(m0, 32), rdlane(m0, 48)));
-    m1 = nanmax(nanmax(rdlane(m1, 0), rdlane(m1, 16)), nanmax(rdlane(m1, 32), rdlane(m1, 48)));
-    m2 = nanmax(nanmax(rdlane(m2, 0), rdlane(m2, 16)), nanmax(rdlane(m2, 32), rdlane(m2, 48)));
+    m0 = max_nonneg(max_nonneg(rdlane(m0, 0), rdlane(m0, 16)), max_nonneg(rdlane(m0, 32), rdlane(m0, 48)));
+    m1 = max_nonneg(max_nonneg(rdlane(m1, 0), rdlane(m1, 16)), max_nonneg(rdlane(m1, 32), rdlane(m1, 48)));
+    m2 = max_nonneg(max_nonneg(rdlane(m2, 0), rdlane(m2, 16)), max_nonneg(rdlane(m2, 32), rdlane(m2, 48)));
     s3 = (rdlane(s3, 0) + rdlane(s3, 16)) + (rdlane(s3, 32) + rdlane(s3, 48));
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0) {
@@ -472,9 +480,9 @@ __device__ inline void reduce4(float &m0, float &m1, float &m2, float &s3, float
     m2 = red[2];
     s3 = red[3];
     for (int k = 1; k < NT / 64; ++k) {
-        m0 = nanmax(m0, red[4 * k]);
-        m1 = nanmax(m1, red[4 * k + 1]);
-        m2 = nanmax(m2, red[4 * k + 2]);
+        m0 = max_nonneg(m0, red[4 * k]);
+        m1 = max_nonneg(m1, red[4 * k + 1]);
+        m2 = max_nonneg(m2, red[4 * k + 2]);
         s3 = s3 + red[4 * k + 3];
     }
 }
