@@ -540,6 +540,60 @@ __device__ inline void delassus_gather(const Lds &L, int nb, const float *vp, co
     __syncthreads();
 }
 
+// The gather with the bodies balanced over the threads: bodies with long
+// incidence lists take four threads per component, the others two, so every
+// thread walks about the same number of rows. gorder[0] = nh, the count of
+// four-thread bodies (passed as nh), and gorder[1..nb] the bodies in task
+// order, those nh first. With nh > 0 the caller guarantees 12 (nb + nh) <= NT; with nh = 0
+// this is the two-thread gather over chunks of NT tasks. The lanes of a
+// body's component form an aligned group of 4 or 2 within one wave.
+template <int NT>
+__device__ inline void delassus_gather_bal(const Lds &L, int nb, int nh, const unsigned char *gorder,
+                                           const float *vp, const float *x) {
+    const int nheavy = 24 * nh, ntask = nheavy + 12 * (nb - nh);
+    for (int t0 = 0; t0 < ntask; t0 += NT) {
+        const int t = t0 + threadIdx.x;
+        const bool heavy = t < nheavy;
+        int j, c, h, S;
+        if (heavy) {
+            j = t / 24;
+            const int r = t - 24 * j;
+            c = r >> 2;
+            h = r & 3;
+            S = 4;
+        } else {
+            const int u = t - nheavy, q = u / 12, r = u - 12 * q;
+            j = nh + q;
+            c = r >> 1;
+            h = r & 1;
+            S = 2;
+        }
+        double g0 = 0.0, g1 = 0.0;
+        int b = 0;
+        if (t < ntask) {
+            b = gorder[1 + j];
+            int k = L.inc_off[b] + h;
+            const int k1 = L.inc_off[b + 1];
+            for (; k + S < k1; k += 2 * S) {
+                int e0 = L.inc_list[k], e1 = L.inc_list[k + S];
+                int r0 = e0 >> 1, r1 = e1 >> 1;
+                g0 += (double)L.rf(RJ + 6 * (e0 & 1) + c, r0) * ((double)vp[r0] * (double)x[r0]);
+                g1 += (double)L.rf(RJ + 6 * (e1 & 1) + c, r1) * ((double)vp[r1] * (double)x[r1]);
+            }
+            if (k < k1) {
+                int e0 = L.inc_list[k];
+                int r0 = e0 >> 1;
+                g0 += (double)L.rf(RJ + 6 * (e0 & 1) + c, r0) * ((double)vp[r0] * (double)x[r0]);
+            }
+        }
+        double gs = g0 + g1;
+        gs += dpp<kDppXor1>(gs);
+        const double g4 = gs + dpp<kDppXor2>(gs);
+        if (t < ntask && h == 0) L.wb[c * kMaxBodies + b] = heavy ? g4 : gs;
+    }
+    __syncthreads();
+}
+
 // w = M_b^-1 g_b in FP64 (body frame: R diag(I^-1) R^T for the angular part)
 __device__ inline void body_minv64(const Lds &L, int b, double w[6]) {
     double g[6];
@@ -1434,7 +1488,29 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
         }
         bool converged = false;
         float s_own = 0.f;
+        // gather balance for the loop: bodies with more than half the longest
+        // incidence list go first and take four threads per component, as
+        // far as 12 (nb + nh) <= NT allows; the order is bytes in the aux
+        // field (free inside the loop). Wave 0 builds it, lane b for body b
+        // (nb <= 64): a wave max, then ranks from ballots.
+        static_assert(kMaxBodies <= 64 && kMaxBodies + 1 <= 4 * MC, "gather order: one lane per body, bytes in aux");
+        unsigned char *gorder = reinterpret_cast<unsigned char *>(vaux);
+        if (tid < 64) {
+            const int kb = tid < nb ? L.inc_off[tid + 1] - L.inc_off[tid] : 0;
+            int kmax = kb;
+            for (int o = 32; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o));
+            const unsigned long long below = (1ull << tid) - 1ull;
+            const unsigned long long hv = __ballot(tid < nb && 2 * kb > kmax);
+            const int cap = max(NT / 12 - nb, 0);
+            const bool heavy = ((hv >> tid) & 1ull) && __popcll(hv & below) < cap;
+            const unsigned long long hm = __ballot(heavy);
+            const int nh = __popcll(hm);
+            if (tid < nb)
+                gorder[1 + (heavy ? __popcll(hm & below) : nh + tid - __popcll(hm & below))] = (unsigned char)tid;
+            if (tid == 0) gorder[0] = (unsigned char)nh;
+        }
         __syncthreads();
+        const int gnh = gorder[0];
         uint64_t sub[6] = {0, 0, 0, 0, 0, 0}, tmark = 0;
         const bool timing = a.phase_clk && tid == 0;
 #define KAMX_MARK(k)                                  \
@@ -1578,7 +1654,7 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
             KAMX_MARK(3);
             // v~ - v~_f = D~ x_new (matrix-free, FP64): bodies gather here,
             // each block owner evaluates its own rows below
-            delassus_gather<NT>(L, nb, vp, vxn);
+            delassus_gather_bal<NT>(L, nb, gnh, gorder, vp, vxn);
             KAMX_MARK(4);
             // steps 6-7 and the residuals of step 9 (block owners)
             float lrp = 0.f, lrd = 0.f, lrc = 0.f, lcc = 0.f;
