@@ -1626,28 +1626,26 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
                         else s2 = acc;
                     }
                 }
-                s1.x = lane_group_sum<16>(s1.x);
-                s1.y = lane_group_sum<16>(s1.y);
-                s1.z = lane_group_sum<16>(s1.z);
-                s1.w = lane_group_sum<16>(s1.w);
-                s2.x = lane_group_sum<16>(s2.x);
-                s2.y = lane_group_sum<16>(s2.y);
-                s2.z = lane_group_sum<16>(s2.z);
-                s2.w = lane_group_sum<16>(s2.w);
-                if (kq == 0 && c1 <= c2) {
-                    const float a1[4] = {s1.x, s1.y, s1.z, s1.w}, a2[4] = {s2.x, s2.y, s2.z, s2.w};
+                // reduce-scatter over the 16 lanes: halve the eight sums at each
+                // exchange (row mirror, half-row mirror, then pairs), so that
+                // lanes 2k and 2k+1 end with sum 4 b3 + 2 b2 + b1 of the bits
+                // of k; the even lane writes it
+                const bool b3 = kq & 8, b2 = kq & 4, b1 = kq & 2;
+                const float v8[8] = {s1.x, s1.y, s1.z, s1.w, s2.x, s2.y, s2.z, s2.w};
+                float u4[4];
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const int j = 4 * c1 + e;
-                        if (j < m) vxn[j] = vx[j] + a1[e];
-                    }
-                    if (c2 > c1) {
+                for (int k = 0; k < 4; ++k)
+                    u4[k] = (b3 ? v8[k + 4] : v8[k]) + dpp<kDppMirror16>(b3 ? v8[k] : v8[k + 4]);
+                float u2[2];
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            const int j = 4 * c2 + e;
-                            if (j < m) vxn[j] = vx[j] + a2[e];
-                        }
-                    }
+                for (int k = 0; k < 2; ++k)
+                    u2[k] = (b2 ? u4[k + 2] : u4[k]) + dpp<kDppMirror8>(b2 ? u4[k] : u4[k + 2]);
+                float z = (b1 ? u2[1] : u2[0]) + dpp<kDppXor2>(b1 ? u2[0] : u2[1]);
+                z += dpp<kDppXor1>(z);
+                if (!(kq & 1) && c1 <= c2) {
+                    const int idx = (b3 ? 4 : 0) + (b2 ? 2 : 0) + (b1 ? 1 : 0);
+                    const int j = 4 * (b3 ? c2 : c1) + (idx & 3);
+                    if (j < m && (!b3 || c2 > c1)) vxn[j] = vx[j] + z;
                 }
             }
             __syncthreads();
