@@ -1566,11 +1566,13 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
                         for (; c < n2; c += 4) a2 += dot4(R2 + 4 * c, vrhs + 4 * c);
                     }
                 }
-                float t1 = group_sum<4>(a1 + b1), t2 = group_sum<4>(a2 + b2);
-                if (q == 0 && i1 <= i2 && i1 < m) {
-                    vt[i1] = t1;
-                    if (i2 > i1) vt[i2] = t2;
-                }
+                // reduce-scatter over the four lanes: lanes 0-1 end with row
+                // i1's sum, lanes 2-3 with row i2's; lanes 0 and 2 write
+                const bool hi = q & 2;
+                const float v1 = a1 + b1, v2 = a2 + b2;
+                float tq = (hi ? v2 : v1) + dpp<kDppXor2>(hi ? v1 : v2);
+                tq += dpp<kDppXor1>(tq);
+                if (!(q & 1) && i1 <= i2 && i1 < m && (!hi || i2 > i1)) vt[hi ? i2 : i1] = tq;
             }
             __syncthreads();
             KAMX_MARK(2);
