@@ -1538,41 +1538,70 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
             KAMX_MARK(0);
             __syncthreads();
             KAMX_MARK(1);
-            // t = X r: rows i and m-1-i form a pair handled by four threads, so
-            // every group walks m+1 entries (balanced); two chains per row
+            // t = X r over groups of 4 rows: groups g and Q-1-g form a pair
+            // (balanced: together they span Q+1 column quads); 16 threads per
+            // pair take every 16th column quad, reading the quad of r once
+            // for the 4 rows of a group. The rows of a group lie back to back,
+            // 4(G+1) floats apart; the pads of the diagonal quad hold 0 and r
+            // is 0 past row m, and rows past m (up to the next multiple of 16)
+            // hold finite values whose sums are not stored. The eight sums
+            // are reduce-scattered over the 16 lanes as in the x update.
             {
-                float a1 = 0.f, b1 = 0.f, a2 = 0.f, b2 = 0.f;
-                const int p = tid >> 2, q = tid & 3;
-                const int i1 = p, i2 = m - 1 - p;
-                if (i1 < i2 || (i1 == i2)) {
-                    if (i1 < m) {
-                        const float *R1 = A + tri_row_offset(i1);
-                        const int n1 = (i1 + 4) >> 2;
-                        int c = q;
-                        for (; c + 4 < n1; c += 8) {
-                            a1 += dot4(R1 + 4 * c, vrhs + 4 * c);
-                            b1 += dot4(R1 + 4 * (c + 4), vrhs + 4 * (c + 4));
+                const int Q = (m + 3) >> 2;
+                const int g = tid >> 4, kq = tid & 15;
+                const int g1 = g, g2 = Q - 1 - g;
+                float4 s1 = make_float4(0.f, 0.f, 0.f, 0.f), s2 = s1;
+                if (g1 <= g2) {
+#pragma unroll
+                    for (int part = 0; part < 2; ++part) {
+                        if (part == 1 && g2 == g1) break;
+                        const int G = part == 0 ? g1 : g2;
+                        const float *R = A + tri_row_offset(4 * G);
+                        const int rl = 4 * (G + 1);
+                        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+                        for (int c = kq; c <= G; c += 16) {
+                            const float4 rv = *reinterpret_cast<const float4 *>(vrhs + 4 * c);
+                            const float4 x0 = *reinterpret_cast<const float4 *>(R + 4 * c);
+                            const float4 x1 = *reinterpret_cast<const float4 *>(R + rl + 4 * c);
+                            const float4 x2 = *reinterpret_cast<const float4 *>(R + 2 * rl + 4 * c);
+                            const float4 x3 = *reinterpret_cast<const float4 *>(R + 3 * rl + 4 * c);
+                            acc.x += x0.x * rv.x;
+                            acc.y += x1.x * rv.x;
+                            acc.z += x2.x * rv.x;
+                            acc.w += x3.x * rv.x;
+                            acc.x += x0.y * rv.y;
+                            acc.y += x1.y * rv.y;
+                            acc.z += x2.y * rv.y;
+                            acc.w += x3.y * rv.y;
+                            acc.x += x0.z * rv.z;
+                            acc.y += x1.z * rv.z;
+                            acc.z += x2.z * rv.z;
+                            acc.w += x3.z * rv.z;
+                            acc.x += x0.w * rv.w;
+                            acc.y += x1.w * rv.w;
+                            acc.z += x2.w * rv.w;
+                            acc.w += x3.w * rv.w;
                         }
-                        for (; c < n1; c += 4) a1 += dot4(R1 + 4 * c, vrhs + 4 * c);
-                    }
-                    if (i2 > i1 && i2 >= 0) {
-                        const float *R2 = A + tri_row_offset(i2);
-                        const int n2 = (i2 + 4) >> 2;
-                        int c = q;
-                        for (; c + 4 < n2; c += 8) {
-                            a2 += dot4(R2 + 4 * c, vrhs + 4 * c);
-                            b2 += dot4(R2 + 4 * (c + 4), vrhs + 4 * (c + 4));
-                        }
-                        for (; c < n2; c += 4) a2 += dot4(R2 + 4 * c, vrhs + 4 * c);
+                        if (part == 0) s1 = acc;
+                        else s2 = acc;
                     }
                 }
-                // reduce-scatter over the four lanes: lanes 0-1 end with row
-                // i1's sum, lanes 2-3 with row i2's; lanes 0 and 2 write
-                const bool hi = q & 2;
-                const float v1 = a1 + b1, v2 = a2 + b2;
-                float tq = (hi ? v2 : v1) + dpp<kDppXor2>(hi ? v1 : v2);
-                tq += dpp<kDppXor1>(tq);
-                if (!(q & 1) && i1 <= i2 && i1 < m && (!hi || i2 > i1)) vt[hi ? i2 : i1] = tq;
+                const bool b3 = kq & 8, b2 = kq & 4, b1 = kq & 2;
+                const float v8[8] = {s1.x, s1.y, s1.z, s1.w, s2.x, s2.y, s2.z, s2.w};
+                float u4[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    u4[k] = (b3 ? v8[k + 4] : v8[k]) + dpp<kDppMirror16>(b3 ? v8[k] : v8[k + 4]);
+                float u2[2];
+#pragma unroll
+                for (int k = 0; k < 2; ++k)
+                    u2[k] = (b2 ? u4[k + 2] : u4[k]) + dpp<kDppMirror8>(b2 ? u4[k] : u4[k + 2]);
+                float z = (b1 ? u2[1] : u2[0]) + dpp<kDppXor2>(b1 ? u2[0] : u2[1]);
+                z += dpp<kDppXor1>(z);
+                if (!(kq & 1) && g1 <= g2) {
+                    const int i = 4 * (b3 ? g2 : g1) + (b2 ? 2 : 0) + (b1 ? 1 : 0);
+                    if (i < m && (!b3 || g2 > g1)) vt[i] = z;
+                }
             }
             __syncthreads();
             KAMX_MARK(2);
