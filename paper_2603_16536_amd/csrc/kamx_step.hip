@@ -551,8 +551,9 @@ template <int NT>
 __device__ inline void delassus_gather_bal(const Lds &L, int nb, int nh, const unsigned char *gorder,
                                            const float *vp, const float *x) {
     const int nheavy = 24 * nh, ntask = nheavy + 12 * (nb - nh);
-    for (int t0 = 0; t0 < ntask; t0 += NT) {
-        const int t = t0 + threadIdx.x;
+    // one task per thread; the first chunk is straight-line code, the
+    // rest (only for nh = 0 and more than NT tasks) loops
+    auto task = [&](const int t) {
         const bool heavy = t < nheavy;
         int j, c, h, S;
         if (heavy) {
@@ -590,7 +591,9 @@ __device__ inline void delassus_gather_bal(const Lds &L, int nb, int nh, const u
         gs += dpp<kDppXor1>(gs);
         const double g4 = gs + dpp<kDppXor2>(gs);
         if (t < ntask && h == 0) L.wb[c * kMaxBodies + b] = heavy ? g4 : gs;
-    }
+    };
+    task(threadIdx.x);
+    for (int t0 = NT; t0 < ntask; t0 += NT) task(t0 + threadIdx.x);
     __syncthreads();
 }
 
