@@ -1690,7 +1690,7 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
             KAMX_MARK(4);
             // steps 6-7 and the residuals of step 9 (block owners)
             float lrp = 0.f, lrd = 0.f, lrc = 0.f, lcc = 0.f;
-            float yb[3], zb[3];
+            float yb[3], zb[3], xn[3], rr[3];
             // v~ - v~_f of row io in FP64: J_a M_a^-1 g_a on the even lane,
             // J_b M_b^-1 g_b on the odd lane, added by the pair sum
             {
@@ -1708,7 +1708,7 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
             }
             __syncthreads();
             if (owner_o) {
-                float xn[3], zh[3], yh[3], rr[3], ri[3], vv[3];
+                float zh[3], yh[3], ri[3], vv[3];
                 _Pragma("unroll") for (int e = 0; e < 3; ++e) if (e < blk_o) {
                     const float dx = vdx[io + e];
                     xn[e] = vxn[io + e];
@@ -1763,24 +1763,32 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
                 }
             }
             if (owner_o) {
+                float yn[3] = {0.f, 0.f, 0.f}, zn[3] = {0.f, 0.f, 0.f};
                 _Pragma("unroll") for (int e = 0; e < 3; ++e) if (e < blk_o) {
                     float yo = vyp[io + e], zo = vzp[io + e];
                     if (!P.accel) {
-                        vyh[io + e] = yb[e];
-                        vzh[io + e] = zb[e];
+                        yn[e] = yb[e];
+                        zn[e] = zb[e];
                     } else if (!restart) {
-                        vyh[io + e] = yb[e] + beta * (yb[e] - yo);
-                        vzh[io + e] = zb[e] + beta * (zb[e] - zo);
+                        yn[e] = yb[e] + beta * (yb[e] - yo);
+                        zn[e] = zb[e] + beta * (zb[e] - zo);
                     } else {
-                        vyh[io + e] = yo;
-                        vzh[io + e] = zo;
+                        yn[e] = yo;
+                        zn[e] = zo;
                     }
-                    vx[io + e] = vxn[io + e];
+                    vyh[io + e] = yn[e];
+                    vzh[io + e] = zn[e];
+                    vx[io + e] = xn[e];
                     vyp[io + e] = yb[e];
                     vzp[io + e] = zb[e];
                 }
+                // the next right-hand side (as own_rhs) from the values in registers
+                s_own = kind_o == kRowNormal ? mu_o * hw_sqrt(zn[1] * zn[1] + zn[2] * zn[2]) : 0.f;
+                _Pragma("unroll") for (int e = 0; e < 3; ++e) if (e < blk_o) {
+                    float rhs = -vvt[io + e] - (e == 0 ? s_own : 0.f) + eta * xn[e] + rr[e] * yn[e] + zn[e];
+                    vrhs[io + e] = rhs - (vdx[io + e] + (eta + rr[e]) * xn[e]);
+                }
             }
-            own_rhs();  // for the next iteration
             KAMX_MARK(6);
             if (tid == 0 && a.rlog && P.log_restarts && it <= P.max_iters)
                 a.rlog[(size_t)w * P.max_iters + (it - 1)] = (uint8_t)restart;
