@@ -281,9 +281,10 @@ def tangent_basis(n):
     return t1, t2
 
 
-def solve_ncp(D, vf, kind, mu, params: Params, lambda_ws=None):
+def solve_ncp(D, vf, kind, mu, params: Params, lambda_ws=None, log_iters=None):
     """PADMM on an explicit dual problem (Eq. 3): returns lambda, lambda_tilde,
-    iterations, residuals, status."""
+    iterations, residuals, status and, when ``log_iters`` is given, the
+    restart decision of each of the first log_iters iterations."""
     D = np.ascontiguousarray(D, np.float64)
     vf = np.ascontiguousarray(vf, np.float64)
     kind = np.ascontiguousarray(kind, np.int32)
@@ -293,6 +294,79 @@ def solve_ncp(D, vf, kind, mu, params: Params, lambda_ws=None):
     it = C.c_int()
     ws = np.ascontiguousarray(lambda_ws, np.float64) if lambda_ws is not None else None
     pp = params.replace(warmstart=1 if ws is not None else 0)._c()
+    log = np.zeros(max(int(log_iters or 0), params.fixed_iters or params.max_iters), np.uint8) if log_iters else None
     st = lib().orc_solve_ncp(m, _p(D), _p(vf), _p(kind), _p(mu), C.byref(pp), _p(ws) if ws is not None else None,
-                             _p(lam), _p(lt), C.byref(it), _p(res), None, None)
-    return dict(lam=lam, lam_tilde=lt, iters=it.value, resid=res, status=st)
+                             _p(lam), _p(lt), C.byref(it), _p(res), None, _p(log) if log is not None else None)
+    out = dict(lam=lam, lam_tilde=lt, iters=it.value, resid=res, status=st)
+    if log is not None:
+        out["restart_log"] = log[:int(log_iters)]
+    return out
+
+
+def preconditioner(D, kind, enabled=True):
+    """Sec. 4.1 Jacobi scales: D_ii^-1/2 per bilateral or limit row, one
+    (trace of the 3 x 3 block / 3)^-1/2 per contact."""
+    m = D.shape[0]
+    p = np.ones(m)
+    if not enabled:
+        return p
+    i = 0
+    while i < m:
+        if kind[i] == ROW_NORMAL:
+            t = np.trace(D[i:i + 3, i:i + 3]) / 3.0
+            p[i:i + 3] = 1.0 / np.sqrt(t) if t > 0 else 1.0
+            i += 3
+        else:
+            p[i] = 1.0 / np.sqrt(D[i, i]) if D[i, i] > 0 else 1.0
+            i += 1
+    return p
+
+
+def floor_report(scene, params: Params, w, q=None, u=None, joint_torque=None, rel_tol=1e-9):
+    """Where lambda is not unique and where the dual residual has a floor
+    (the paper's redundant loop rows, Sec. 3 and Sec. 4, are not discussed
+    there; this is the reading used here).
+
+    With J the world's constraint Jacobian, D~ = P J M^-1 J^T P and the
+    bilateral rows B:
+
+    * rank_J, rank_JB: numerical ranks of J and of its bilateral rows
+      (singular values above rel_tol times the largest);
+    * null_dim: m - rank_J, the dimension of the impulses that move no body
+      (lambda is unique only when it is 0);
+    * floor_inf: a lower bound on the infinity norm of the bilateral part of
+      D~ lambda~ + v~_f for every lambda~.  Because J_B M^-1 J_C^T maps into
+      the range of P_B J_B, the bilateral rows of D~ lambda~ stay in
+      range(D~_BB) whatever the contact impulses; with n = P_N v~_f,B the
+      component of the bilateral free velocity in null(D~_BB), every such
+      vector w has <w, n> = |n|_2^2, hence |w|_inf >= |n|_2^2 / |n|_1.  The
+      dual residual r_d of Alg. 1 cannot go below it (z = 0 on bilateral
+      rows);
+    * floor_2: |n|_2.
+
+    Built on numpy's symmetric eigendecomposition of D~_BB (FP64)."""
+    S = world_system(scene, params, w, q=q, u=u, joint_torque=joint_torque)
+    J, D, vf, kind = S["J"], S["D"], S["vf"], S["kind"]
+    m = J.shape[0]
+    out = dict(m=m, rank_J=0, rank_JB=0, null_dim=0, floor_inf=0.0, floor_2=0.0)
+    if m == 0:
+        return out
+    sv = np.linalg.svd(J, compute_uv=False)
+    out["rank_J"] = int(np.sum(sv > rel_tol * sv.max())) if sv.size and sv.max() > 0 else 0
+    out["null_dim"] = m - out["rank_J"]
+    B = np.where(kind == ROW_BILATERAL)[0]
+    if B.size == 0:
+        return out
+    svb = np.linalg.svd(J[B], compute_uv=False)
+    out["rank_JB"] = int(np.sum(svb > rel_tol * svb.max())) if svb.max() > 0 else 0
+    p = preconditioner(D, kind, params.precond)
+    Dt = p[:, None] * D * p[None, :]
+    DB = Dt[np.ix_(B, B)]
+    ev, V = np.linalg.eigh(DB)
+    N = V[:, ev <= rel_tol * max(ev.max(), 1e-300)]
+    vt = (p * vf)[B]
+    n = N @ (N.T @ vt) if N.shape[1] else np.zeros_like(vt)
+    n2 = float(np.linalg.norm(n))
+    out["floor_2"] = n2
+    out["floor_inf"] = n2 * n2 / float(np.abs(n).sum()) if n2 > 0 else 0.0
+    return out
