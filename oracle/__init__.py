@@ -42,6 +42,7 @@ class _Params(C.Structure):
         ("max_iters", C.c_int32), ("fixed_iters", C.c_int32), ("accel", C.c_int32),
         ("restart_factor", C.c_double), ("precond", C.c_int32), ("baumgarte", C.c_double),
         ("warmstart", C.c_int32), ("replay", C.c_int32), ("log_stride", C.c_int32),
+        ("integrator", C.c_int32),
     ]
 
 
@@ -53,7 +54,7 @@ class _Batch(C.Structure):
         ("joint_body", C.c_void_p), ("joint_frame", C.c_void_p), ("joint_limit", C.c_void_p),
         ("n_contacts", C.c_int32), ("contact_world", C.c_void_p), ("contact_body", C.c_void_p),
         ("contact_point", C.c_void_p), ("contact_normal", C.c_void_p), ("contact_gap", C.c_void_p),
-        ("contact_mu", C.c_void_p),
+        ("contact_mu", C.c_void_p), ("joint_drive", C.c_void_p),
     ]
 
 
@@ -83,6 +84,7 @@ class Params:
     precond: int = 1
     baumgarte: float = 0.2
     warmstart: int = 0
+    integrator: int = 0  # 0 semi-implicit Euler, 1 Moreau-Jean midpoint (Sec. 3)
 
     def replace(self, **kw):
         return dataclasses.replace(self, **kw)
@@ -96,6 +98,7 @@ class Params:
         p.max_iters, p.fixed_iters, p.accel = self.max_iters, self.fixed_iters, self.accel
         p.restart_factor, p.precond, p.baumgarte = self.restart_factor, self.precond, self.baumgarte
         p.warmstart, p.replay, p.log_stride = self.warmstart, replay, log_stride
+        p.integrator = self.integrator
         return p
 
 
@@ -113,7 +116,8 @@ def lib():
         L.orc_row_offsets.argtypes = [C.POINTER(_Batch), C.c_void_p]
         L.orc_world_dims.argtypes = [C.POINTER(_Batch), C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.orc_world_system.restype = C.c_int
-        L.orc_world_system.argtypes = [C.POINTER(_Batch), C.POINTER(_Params)] + [C.c_void_p] * 3 + [C.c_int] + [C.c_void_p] * 9
+        L.orc_world_system.argtypes = [C.POINTER(_Batch), C.POINTER(_Params)] + [C.c_void_p] * 3 + [C.c_int] + [C.c_void_p] * 10
+        L.orc_step_configuration.argtypes = [C.POINTER(_Batch), C.POINTER(_Params)] + [C.c_void_p] * 3
         L.orc_joint_coordinate.restype = C.c_double
         L.orc_joint_coordinate.argtypes = [C.POINTER(_Batch), C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
         L.orc_cholesky.restype = C.c_int
@@ -164,6 +168,9 @@ def _batch(scene, keep):
     b.contact_normal = _p(keep(scene.contact_normal, np.float64))
     b.contact_gap = _p(keep(scene.contact_gap, np.float64))
     b.contact_mu = _p(keep(scene.contact_mu, np.float64))
+    drive = getattr(scene, "joint_drive", None)
+    b.joint_drive = _p(keep(drive, np.float64)) if drive is not None and drive.shape[0] == scene.n_joints and \
+        scene.n_joints and np.any(drive[:, :4] != 0.0) else None
     return b
 
 
@@ -230,8 +237,10 @@ def world_dims(scene, w):
 
 
 def world_system(scene, params: Params, w, q=None, u=None, joint_torque=None):
-    """Assembled quantities of world ``w``: J, f, vstar, kind, mu, Minv
-    (nb x 6 x 6), uf, D, vf."""
+    """Assembled quantities of world ``w`` at the configuration of the step
+    (the pre-step poses, or the half-step poses of the Moreau-Jean variant):
+    J, f, vstar, kind, mu, Minv (nb x 6 x 6), uf, D (including R), vf and
+    R (the diagonal regularisation of drive rows)."""
     keep = _Keep()
     b = _batch(scene, keep)
     nb, m = world_dims(scene, w)
@@ -240,14 +249,28 @@ def world_system(scene, params: Params, w, q=None, u=None, joint_torque=None):
     jt = keep(joint_torque, np.float64) if joint_torque is not None else None
     o = dict(J=np.zeros((m, 6 * nb)), f=np.zeros(m), vstar=np.zeros(m), kind=np.zeros(m, np.int32),
              mu=np.zeros(m), Minv=np.zeros((nb, 6, 6)), uf=np.zeros(6 * nb), D=np.zeros((m, m)),
-             vf=np.zeros(m))
+             vf=np.zeros(m), R=np.zeros(m))
     pp = params._c()
     rc = lib().orc_world_system(C.byref(b), C.byref(pp), _p(q), _p(u), _p(jt) if jt is not None else None, w,
                                 _p(o["J"]), _p(o["f"]), _p(o["vstar"]), _p(o["kind"]), _p(o["mu"]),
-                                _p(o["Minv"]), _p(o["uf"]), _p(o["D"]), _p(o["vf"]))
+                                _p(o["Minv"]), _p(o["uf"]), _p(o["D"]), _p(o["vf"]), _p(o["R"]))
     if rc != 0:
         raise MemoryError("oracle world_system failed")
     return o
+
+
+def step_configuration(scene, params: Params, q=None, u=None):
+    """Poses at which the step evaluates constraints, forces and contacts:
+    the pre-step poses (semi-implicit Euler) or the poses advanced by dt/2
+    with the pre-step twists (Moreau-Jean midpoint)."""
+    keep = _Keep()
+    b = _batch(scene, keep)
+    q = keep(scene.q if q is None else q, np.float64)
+    u = keep(scene.u if u is None else u, np.float64)
+    qm = np.zeros((scene.n_bodies, 7))
+    pp = params._c()
+    lib().orc_step_configuration(C.byref(b), C.byref(pp), _p(q), _p(u), _p(qm))
+    return qm
 
 
 def joint_coordinate(scene, q, j):

@@ -16,6 +16,10 @@
  *   Sec. 4, Alg. 1    Proximal-ADMM (PADMM)
  *   Sec. 4.1          Nesterov acceleration with restart, Jacobi
  *                     preconditioning, three infinity-norm residuals
+ *   Sec. 3, Eq. 2     joint-space drives (implicit PD, armature, viscous
+ *                     damping) as regularised rows: R on the diagonal of
+ *                     D, their targets in v*
+ *   Sec. 3            the Moreau-Jean midpoint variant of the time step
  * Where the paper is silent the readings are stated next to the code that
  * uses them.  Everything is written for clarity: dense J (m x 6 n_b), dense
  * D = J M^-1 J^T, a textbook Cholesky and two triangular solves per
@@ -62,6 +66,7 @@ typedef struct {
     int32_t warmstart;     /* 0 cold, 1 from lambda_ws                     */
     int32_t replay;        /* 1: restart decisions read from restart_log   */
     int32_t log_stride;    /* bytes per world in restart_log               */
+    int32_t integrator;    /* 0 semi-implicit Euler, 1 Moreau-Jean midpoint */
 } orc_params;
 
 typedef struct {
@@ -83,6 +88,8 @@ typedef struct {
     const double *contact_normal;   /* [nc*3] unit, from b to a         */
     const double *contact_gap;      /* [nc]                            */
     const double *contact_mu;       /* [nc]                            */
+    const double *joint_drive;      /* [nj*5] kp, kd, damping, armature,
+                                       ref of implicit drives, or NULL   */
 } orc_batch;
 
 typedef struct {
@@ -188,6 +195,7 @@ typedef struct {
     double *mu;             /* [m] friction (contact rows)     */
     double *Minv;           /* [nb][6][6]                      */
     double *uf;             /* [6 nb] free velocity of bodies  */
+    double *Rreg;           /* [m] diagonal regularisation R   */
 } world_sys;
 
 static int joint_rows(int type) {
@@ -196,6 +204,13 @@ static int joint_rows(int type) {
 }
 
 static int has_limit(const double *lim) { return !isnan(lim[0]) || !isnan(lim[1]); }
+
+/* a joint has a drive row when any of its drive gains is nonzero */
+static int has_drive(const orc_batch *B, int j) {
+    if (!B->joint_drive) return 0;
+    const double *d = B->joint_drive + 5 * (size_t)j;
+    return d[0] != 0.0 || d[1] != 0.0 || d[2] != 0.0 || d[3] != 0.0;
+}
 
 /* the world-local body index of global body b (or -1 for the world) */
 static int local_body(int b, int b0) { return b < 0 ? -1 : b - b0; }
@@ -461,6 +476,7 @@ static int world_rows(const orc_batch *B, const world_range *R) {
     int m = 0;
     for (int j = R->j0; j < R->j1; ++j) m += joint_rows(B->joint_type[j]);
     for (int j = R->j0; j < R->j1; ++j) m += has_limit(B->joint_limit + 2 * (size_t)j);
+    for (int j = R->j0; j < R->j1; ++j) m += has_drive(B, j);
     m += 3 * (R->c1 - R->c0);
     return m;
 }
@@ -473,12 +489,16 @@ static void sys_free(world_sys *S) {
     free(S->mu);
     free(S->Minv);
     free(S->uf);
+    free(S->Rreg);
 }
 
 /* Body quantities (Sec. 3, Eq. 1 and the Newton-Euler forces h) and the
- * rows of one world; v* per Sec. 3 Baumgarte stabilisation. */
+ * rows of one world at the configuration q; v* per Sec. 3 Baumgarte
+ * stabilisation.  hz is the time from q to the end of the step over which
+ * the position-level terms act: dt for semi-implicit Euler, dt / 2 for the
+ * Moreau-Jean midpoint (q is then the half-step configuration). */
 static int build_world(const orc_batch *B, const orc_params *P, const double *q, const double *u,
-                       const double *joint_torque, int w, world_sys *S) {
+                       const double *joint_torque, int w, double hz, world_sys *S) {
     world_range R = get_range(B, w);
     S->b0 = R.b0;
     S->nb = R.b1 - R.b0;
@@ -491,7 +511,8 @@ static int build_world(const orc_batch *B, const orc_params *P, const double *q,
     S->mu = calloc((size_t)m + 1, sizeof(double));
     S->Minv = calloc((size_t)nb * 36 + 1, sizeof(double));
     S->uf = calloc((size_t)n6 + 1, sizeof(double));
-    if (!S->J || !S->f || !S->vstar || !S->kind || !S->mu || !S->Minv || !S->uf) return -1;
+    S->Rreg = calloc((size_t)m + 1, sizeof(double));
+    if (!S->J || !S->f || !S->vstar || !S->kind || !S->mu || !S->Minv || !S->uf || !S->Rreg) return -1;
 
     /* generalized forces h: gravity, gyroscopic, joint actuation */
     double *hw = calloc((size_t)n6 + 1, sizeof(double));
@@ -552,7 +573,7 @@ static int build_world(const orc_batch *B, const orc_params *P, const double *q,
     free(hw);
     free(Iw);
 
-    /* rows: joints, then limits, then contacts */
+    /* rows: joints, then limits, then drives, then contacts */
     int r = 0;
     for (int j = R.j0; j < R.j1; ++j) {
         assemble_joint(B, q, j, S, r);
@@ -560,19 +581,62 @@ static int build_world(const orc_batch *B, const orc_params *P, const double *q,
     }
     for (int j = R.j0; j < R.j1; ++j)
         if (has_limit(B->joint_limit + 2 * (size_t)j)) assemble_limit(B, q, j, S, r++);
+    const int r_drive0 = r;
+    for (int j = R.j0; j < R.j1; ++j)
+        if (has_drive(B, j)) {
+            double Ja[6], Jb[6];
+            joint_coordinate(B, q, j, Ja, Jb);
+            put_row(S, r, local_body(B->joint_body[2 * j], S->b0), Ja, local_body(B->joint_body[2 * j + 1], S->b0),
+                    Jb);
+            S->kind[r] = ORC_ROW_BILATERAL;
+            ++r;
+        }
+    const int r_drive1 = r;
     for (int c = R.c0; c < R.c1; ++c) {
         assemble_contact(B, q, c, S, r);
         r += 3;
     }
-    /* Baumgarte bias: bilateral rows beta f / dt; unilateral rows f / dt
-     * while separated (speculative) and beta f / dt when penetrating. */
+    /* Baumgarte bias: bilateral rows beta f / hz; unilateral rows f / hz
+     * while separated (speculative) and beta f / hz when penetrating. */
     for (int i = 0; i < m; ++i) {
         double fi = S->f[i];
         switch (S->kind[i]) {
-        case ORC_ROW_BILATERAL: S->vstar[i] = P->baumgarte * fi / P->dt; break;
+        case ORC_ROW_BILATERAL: S->vstar[i] = P->baumgarte * fi / hz; break;
         case ORC_ROW_LIMIT:
-        case ORC_ROW_NORMAL: S->vstar[i] = (fi >= 0.0 ? fi : P->baumgarte * fi) / P->dt; break;
+        case ORC_ROW_NORMAL: S->vstar[i] = (fi >= 0.0 ? fi : P->baumgarte * fi) / hz; break;
         default: S->vstar[i] = 0.0;
+        }
+    }
+    /* Joint-space drive rows (Sec. 3 implicit PD, armature, viscous
+     * damping; Eq. 2 R and v*).  Along the joint coordinate c with rate
+     * cdot = J_c u the drive applies, over the step, the impulse
+     *   lambda = dt [kp (ref - c - hz cdot+) - (kd + d) cdot+
+     *                - I_a (cdot+ - cdot-) / dt],
+     * PD on the coordinate reached at the end of the step (c + hz cdot+),
+     * damping on the new rate, the rotor inertia I_a opposing the change of
+     * rate.  Solved for cdot+ with K = kp hz + kd + d + I_a / dt:
+     *   J_c u+ + lambda / (dt K) - (kp (ref - c) + I_a cdot- / dt) / K = 0,
+     * a bilateral row with R = 1 / (dt K) and v* = -(kp (ref - c) +
+     * I_a cdot- / dt) / K. */
+    {
+        int rr = r_drive0;
+        for (int j = R.j0; j < R.j1 && rr < r_drive1; ++j) {
+            if (!has_drive(B, j)) continue;
+            const double *d = B->joint_drive + 5 * (size_t)j;
+            const double kp = d[0], kd = d[1], damp = d[2], arm = d[3], ref = d[4];
+            double Ja[6], Jb[6];
+            const double c = joint_coordinate(B, q, j, Ja, Jb);
+            const int a = B->joint_body[2 * j], b = B->joint_body[2 * j + 1];
+            double rate = 0.0;
+            for (int k = 0; k < 6; ++k) {
+                rate += Ja[k] * u[6 * (size_t)a + k];
+                if (b >= 0) rate += Jb[k] * u[6 * (size_t)b + k];
+            }
+            const double K = kp * hz + kd + damp + arm / P->dt;
+            S->Rreg[rr] = 1.0 / (P->dt * K);
+            S->vstar[rr] = -(kp * (ref - c) + arm * rate / P->dt) / K;
+            S->f[rr] = 0.0;
+            ++rr;
         }
     }
     return 0;
@@ -598,6 +662,7 @@ static void delassus(const world_sys *S, double *D, double *vf) {
             for (int c = 0; c < n6; ++c) s += S->J[(size_t)a * n6 + c] * MJt[(size_t)c * m + b];
             D[(size_t)a * m + b] = s;
         }
+    for (int a = 0; a < m; ++a) D[(size_t)a * m + a] += S->Rreg[a]; /* D = J M^-1 J^T + R */
     for (int a = 0; a < m; ++a) {
         double s = 0.0;
         for (int c = 0; c < n6; ++c) s += S->J[(size_t)a * n6 + c] * S->uf[c];
@@ -936,7 +1001,28 @@ done:
 /* angular velocity), then renormalised.                                     */
 /* ------------------------------------------------------------------------ */
 
-static void integrate(const world_sys *S, const orc_params *P, const double *q, const double *lam,
+/* Pose update over the time hz with u+ from the configuration q (the
+ * pre-step pose for semi-implicit Euler, hz = dt; the half-step pose for
+ * the Moreau-Jean midpoint, hz = dt / 2). */
+static void advance_pose(const double *qi, const double *un, double hz, double *qo) {
+    for (int k = 0; k < 3; ++k) qo[k] = qi[k] + hz * un[k];
+    double wn = sqrt(un[3] * un[3] + un[4] * un[4] + un[5] * un[5]);
+    double dq[4] = {0, 0, 0, 1};
+    if (wn > 0.0) {
+        double half = 0.5 * hz * wn;
+        double sh = sin(half) / wn;
+        dq[0] = un[3] * sh;
+        dq[1] = un[4] * sh;
+        dq[2] = un[5] * sh;
+        dq[3] = cos(half);
+    }
+    double qn[4];
+    quat_mul(dq, qi + 3, qn);
+    double nn = sqrt(qn[0] * qn[0] + qn[1] * qn[1] + qn[2] * qn[2] + qn[3] * qn[3]);
+    for (int k = 0; k < 4; ++k) qo[3 + k] = qn[k] / nn;
+}
+
+static void integrate(const world_sys *S, const orc_params *P, const double *q, const double *lam, double hz,
                       double *q_out, double *u_out) {
     int nb = S->nb, m = S->m, n6 = 6 * nb;
     for (int i = 0; i < nb; ++i) {
@@ -950,25 +1036,26 @@ static void integrate(const world_sys *S, const orc_params *P, const double *q, 
             un[r] = S->uf[6 * i + r] + s;
         }
         int gb = S->b0 + i;
-        const double *qi = q + 7 * (size_t)gb;
-        double *qo = q_out + 7 * (size_t)gb;
         for (int k = 0; k < 6; ++k) u_out[6 * (size_t)gb + k] = un[k];
-        for (int k = 0; k < 3; ++k) qo[k] = qi[k] + P->dt * un[k];
-        double wn = sqrt(un[3] * un[3] + un[4] * un[4] + un[5] * un[5]);
-        double dq[4] = {0, 0, 0, 1};
-        if (wn > 0.0) {
-            double half = 0.5 * P->dt * wn;
-            double sh = sin(half) / wn;
-            dq[0] = un[3] * sh;
-            dq[1] = un[4] * sh;
-            dq[2] = un[5] * sh;
-            dq[3] = cos(half);
-        }
-        double qn[4];
-        quat_mul(dq, qi + 3, qn);
-        double nn = sqrt(qn[0] * qn[0] + qn[1] * qn[1] + qn[2] * qn[2] + qn[3] * qn[3]);
-        for (int k = 0; k < 4; ++k) qo[3 + k] = qn[k] / nn;
+        advance_pose(q + 7 * (size_t)gb, un, hz, q_out + 7 * (size_t)gb);
     }
+    (void)P;
+}
+
+/* The configuration the step's constraints and forces are evaluated at:
+ * the pre-step poses (semi-implicit Euler), or (Moreau-Jean midpoint) the
+ * poses advanced by dt / 2 with the pre-step twists, written to qm for the
+ * bodies of world w.  Returns the horizon hz from there to the step's end. */
+static double step_configuration(const orc_batch *B, const orc_params *P, const double *q, const double *u, int w,
+                                 double *qm) {
+    world_range R = get_range(B, w);
+    const int mj = P->integrator == 1;
+    for (int gb = R.b0; gb < R.b1; ++gb) {
+        if (mj) advance_pose(q + 7 * (size_t)gb, u + 6 * (size_t)gb, 0.5 * P->dt, qm + 7 * (size_t)gb);
+        else
+            for (int k = 0; k < 7; ++k) qm[7 * (size_t)gb + k] = q[7 * (size_t)gb + k];
+    }
+    return mj ? 0.5 * P->dt : P->dt;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -990,11 +1077,15 @@ int orc_step(const orc_batch *B, const orc_params *P, orc_io *io) {
     int nw = B->n_worlds;
     orc_row_offsets(B, io->row_offset);
     int err = 0;
+    /* configuration of the constraints (pre-step or half-step poses) */
+    double *qm = malloc(sizeof(double) * (7 * (size_t)B->n_bodies + 1));
+    if (!qm) return -1;
 #pragma omp parallel for schedule(static)
     for (int w = 0; w < nw; ++w) {
         world_sys S;
         memset(&S, 0, sizeof S);
-        if (build_world(B, P, io->q, io->u, io->joint_torque, w, &S) != 0) {
+        const double hz = step_configuration(B, P, io->q, io->u, w, qm);
+        if (build_world(B, P, qm, io->u, io->joint_torque, w, hz, &S) != 0) {
             err = -1;
             sys_free(&S);
             continue;
@@ -1012,11 +1103,12 @@ int orc_step(const orc_batch *B, const orc_params *P, orc_io *io) {
                                io->resid + 4 * (size_t)w, rlog, wlog);
         io->iters[w] = it;
         io->status[w] = st;
-        integrate(&S, P, io->q, io->lambda + r0, io->q_out, io->u_out);
+        integrate(&S, P, qm, io->lambda + r0, hz, io->q_out, io->u_out);
         free(D);
         free(vf);
         sys_free(&S);
     }
+    free(qm);
     return err;
 }
 
@@ -1031,10 +1123,15 @@ void orc_world_dims(const orc_batch *B, int w, int *nb, int *m) {
  * mu, the 6x6 blocks of M^-1 [nb x 36], u_f [6nb], D [m x m], v_f [m]. */
 int orc_world_system(const orc_batch *B, const orc_params *P, const double *q, const double *u,
                      const double *joint_torque, int w, double *J, double *f, double *vstar, int *kind,
-                     double *mu, double *Minv, double *uf, double *D, double *vf) {
+                     double *mu, double *Minv, double *uf, double *D, double *vf, double *Rreg) {
     world_sys S;
     memset(&S, 0, sizeof S);
-    if (build_world(B, P, q, u, joint_torque, w, &S) != 0) {
+    double *qm = malloc(sizeof(double) * (7 * (size_t)B->n_bodies + 1));
+    if (!qm) return -1;
+    const double hz = step_configuration(B, P, q, u, w, qm);
+    int bad = build_world(B, P, qm, u, joint_torque, w, hz, &S) != 0;
+    free(qm);
+    if (bad) {
         sys_free(&S);
         return -1;
     }
@@ -1046,9 +1143,16 @@ int orc_world_system(const orc_batch *B, const orc_params *P, const double *q, c
     memcpy(mu, S.mu, sizeof(double) * m);
     memcpy(Minv, S.Minv, sizeof(double) * 36 * S.nb);
     memcpy(uf, S.uf, sizeof(double) * n6);
+    if (Rreg) memcpy(Rreg, S.Rreg, sizeof(double) * m);
     delassus(&S, D, vf);
     sys_free(&S);
     return 0;
+}
+
+/* The poses the step's constraints are evaluated at (q itself, or the
+ * Moreau-Jean half-step poses) for every world, into qm [nb*7]. */
+void orc_step_configuration(const orc_batch *B, const orc_params *P, const double *q, const double *u, double *qm) {
+    for (int w = 0; w < B->n_worlds; ++w) (void)step_configuration(B, P, q, u, w, qm);
 }
 
 /* Joint coordinate of joint j and its two 6-vector Jacobians. */

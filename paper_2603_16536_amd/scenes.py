@@ -150,6 +150,9 @@ class Scene:
     # per-joint PD gains (kp, kd) toward the assembled coordinate; used when
     # the caller gives no global gains
     joint_pd: np.ndarray = field(default_factory=lambda: np.zeros((0, 2)))
+    # implicit joint drives (kp, kd, damping, armature, ref) solved as
+    # regularised rows; all zero: no drive row
+    joint_drive: np.ndarray = field(default_factory=lambda: np.zeros((0, 5)))
 
     # contact probe points: body-frame points tested against the plane z = 0
     probe_world: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))
@@ -228,6 +231,7 @@ class Scene:
         s.joint_limit = self.joint_limit[j0:j1].copy()
         s.joint_actuated = self.joint_actuated[j0:j1].copy()
         s.joint_pd = _pd_of(self)[j0:j1].copy()
+        s.joint_drive = _drive_of(self)[j0:j1].copy()
         p0, p1 = po[w], po[w + 1]
         s.probe_world = np.zeros(p1 - p0, np.int32)
         s.probe_body = (self.probe_body[p0:p1] - b0).astype(np.int32)
@@ -263,11 +267,15 @@ def _pd_of(s):
     return s.joint_pd if s.joint_pd.shape[0] == s.n_joints else np.zeros((s.n_joints, 2))
 
 
+def _drive_of(s):
+    return s.joint_drive if s.joint_drive.shape[0] == s.n_joints else np.zeros((s.n_joints, 5))
+
+
 def concat(scenes, gravity=None, dt=None, reset_height=None):
     """Stack single- or multi-world scenes into one batch."""
     out = Scene(n_worlds=0)
     bw, bm, bi, q, u, bx = [], [], [], [], [], []
-    jt, jw, jb, jf, jl, ja, jp = [], [], [], [], [], [], []
+    jt, jw, jb, jf, jl, ja, jp, jd = [], [], [], [], [], [], [], []
     pw, pb, pp, pm = [], [], [], []
     cw, cb, cp, cn, cg, cm, ck = [], [], [], [], [], [], []
     rb = []
@@ -287,6 +295,7 @@ def concat(scenes, gravity=None, dt=None, reset_height=None):
         jl.append(s.joint_limit)
         ja.append(s.joint_actuated)
         jp.append(_pd_of(s))
+        jd.append(_drive_of(s))
         pw.append(s.probe_world + nw)
         pb.append(s.probe_body + nb)
         pp.append(s.probe_point)
@@ -318,6 +327,7 @@ def concat(scenes, gravity=None, dt=None, reset_height=None):
     out.joint_limit = np.concatenate(jl).reshape(-1, 2)
     out.joint_actuated = np.concatenate(ja).astype(np.int32)
     out.joint_pd = np.concatenate(jp).reshape(-1, 2)
+    out.joint_drive = np.concatenate(jd).reshape(-1, 5)
     out.probe_world = np.concatenate(pw).astype(np.int32)
     out.probe_body = np.concatenate(pb).astype(np.int32)
     out.probe_point = np.concatenate(pp).reshape(-1, 3)
@@ -341,7 +351,7 @@ class _Builder:
 
     def __init__(self):
         self.mass, self.inertia, self.q, self.u = [], [], [], []
-        self.jt, self.jb, self.jf, self.jl, self.ja, self.jp = [], [], [], [], [], []
+        self.jt, self.jb, self.jf, self.jl, self.ja, self.jp, self.jd = [], [], [], [], [], [], []
         self.pb, self.pp, self.pm = [], [], []
         self.cb, self.cp, self.cn, self.cg, self.cm, self.ck = [], [], [], [], [], []
 
@@ -363,7 +373,7 @@ class _Builder:
         return np.concatenate([p_local, q_local])
 
     def joint(self, jtype, a, b, point_w, axis_w, limit=(np.nan, np.nan), actuated=0,
-              point_b_w=None, pd=(0.0, 0.0)):
+              point_b_w=None, pd=(0.0, 0.0), drive=(0.0, 0.0, 0.0, 0.0, 0.0)):
         """Joint whose frames coincide in the current (assembled) pose: both
         frames sit at ``point_w`` (``point_b_w`` for side b if given) with x
         along ``axis_w``."""
@@ -376,6 +386,7 @@ class _Builder:
         self.jl.append(np.asarray(limit, np.float64))
         self.ja.append(int(actuated))
         self.jp.append(np.asarray(pd, np.float64))
+        self.jd.append(np.asarray(drive, np.float64))
         return len(self.jt) - 1
 
     def probe(self, b, point_local, mu):
@@ -408,6 +419,7 @@ class _Builder:
         s.joint_limit = np.array(self.jl).reshape(-1, 2)
         s.joint_actuated = np.array(self.ja, np.int32)
         s.joint_pd = np.array(self.jp).reshape(-1, 2)
+        s.joint_drive = np.array(self.jd).reshape(-1, 5)
         npb = len(self.pb)
         s.probe_world = np.zeros(npb, np.int32)
         s.probe_body = np.array(self.pb, np.int32)
