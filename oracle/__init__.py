@@ -118,6 +118,9 @@ def lib():
         L.orc_world_system.restype = C.c_int
         L.orc_world_system.argtypes = [C.POINTER(_Batch), C.POINTER(_Params)] + [C.c_void_p] * 3 + [C.c_int] + [C.c_void_p] * 10
         L.orc_step_configuration.argtypes = [C.POINTER(_Batch), C.POINTER(_Params)] + [C.c_void_p] * 3
+        L.orc_fk.restype = C.c_int
+        L.orc_fk.argtypes = [C.POINTER(_Batch), C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int,
+                             C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_joint_coordinate.restype = C.c_double
         L.orc_joint_coordinate.argtypes = [C.POINTER(_Batch), C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
         L.orc_cholesky.restype = C.c_int
@@ -393,3 +396,25 @@ def floor_report(scene, params: Params, w, q=None, u=None, joint_torque=None, re
     out["floor_2"] = n2
     out["floor_inf"] = n2 * n2 / float(np.abs(n).sum()) if n2 > 0 else 0.0
     return out
+
+
+def forward_kinematics(scene, targets, base=None, q=None, tol=1e-12, max_iters=100):
+    """Sec. 6.3 forward kinematics by Gauss-Newton: poses that satisfy every
+    joint constraint and put each joint with a finite entry of ``targets``
+    [n_joints] at that coordinate, with body ``base[w]`` of each world held
+    fixed (None: the scene's reset bodies; -1: none).  Returns (q [nb, 7],
+    iterations [nw], |F|_inf [nw])."""
+    keep = _Keep()
+    b = _batch(scene, keep)
+    q = keep(scene.q if q is None else q, np.float64)
+    t = keep(targets, np.float64)
+    if base is None:
+        base = scene.reset_body if scene.reset_body.size == scene.n_worlds else np.full(scene.n_worlds, -1)
+    bs = keep(base, np.int32)
+    q_out = np.zeros((scene.n_bodies, 7))
+    iters = np.zeros(scene.n_worlds, np.int32)
+    res = np.zeros(scene.n_worlds)
+    rc = lib().orc_fk(C.byref(b), _p(q), _p(t), _p(bs), float(tol), int(max_iters), _p(q_out), _p(iters), _p(res))
+    if rc != 0:
+        raise MemoryError("oracle forward kinematics failed")
+    return q_out, iters, res

@@ -20,6 +20,8 @@
  *                     damping) as regularised rows: R on the diagonal of
  *                     D, their targets in v*
  *   Sec. 3            the Moreau-Jean midpoint variant of the time step
+ *   Sec. 6.3          forward kinematics by Gauss-Newton (consistent poses
+ *                     from target joint coordinates, for resets)
  * Where the paper is silent the readings are stated next to the code that
  * uses them.  Everything is written for clarity: dense J (m x 6 n_b), dense
  * D = J M^-1 J^T, a textbook Cholesky and two triangular solves per
@@ -1170,3 +1172,125 @@ void orc_project_block(int kind, double mu, const double *w, double *o) {
 
 /* Triangular-basis of a normal, for tests. */
 void orc_tangent_basis(const double *n, double *t1, double *t2) { tangent_basis(n, t1, t2); }
+
+/* ------------------------------------------------------------------------ */
+/* Sec. 6.3 forward kinematics: poses consistent with every joint constraint */
+/* and with target joint coordinates, by Gauss-Newton                        */
+/* ------------------------------------------------------------------------ */
+
+/* For every world w: starting from q_in, find poses with f(q) = 0 for every
+ * joint (Sec. 3 constraint functions) and c_j(q) = target[j] for every
+ * joint with a finite target (NaN = free), keeping body base[w] fixed (-1:
+ * none).  Gauss-Newton on F = (f, c_T - target) with J its Jacobian over
+ * the body twists: each iteration takes the least-change step
+ *   Delta = -W J^T (J W J^T + mu I)^-1 F,   W = M^-1 (base block 0),
+ * mu = 1e-12 times the largest diagonal entry of J W J^T (the loop rows of
+ * planar loops are redundant), and moves every body by Delta with the
+ * exponential map (r += Delta_v, R <- exp(Delta_w) R).  It stops when
+ * |F|_inf <= tol (iters = iterations taken) or after max_iters.  resid[w]
+ * = |F|_inf at the returned poses.  Limits, drives and contacts play no
+ * part.  Returns 0, or -1 on allocation failure. */
+int orc_fk(const orc_batch *B, const double *q_in, const double *target, const int32_t *base, double tol,
+           int max_iters, double *q_out, int32_t *iters, double *resid) {
+    orc_batch Bj = *B; /* joints only: no contacts, no drive rows */
+    Bj.n_contacts = 0;
+    Bj.joint_drive = NULL;
+    orc_params P;
+    memset(&P, 0, sizeof P);
+    P.dt = 1.0;
+    memcpy(q_out, q_in, sizeof(double) * 7 * (size_t)B->n_bodies);
+    int err = 0;
+#pragma omp parallel for schedule(dynamic)
+    for (int w = 0; w < B->n_worlds; ++w) {
+        world_range R = get_range(&Bj, w);
+        const int nb = R.b1 - R.b0, n6 = 6 * nb;
+        int nt = 0;
+        for (int j = R.j0; j < R.j1; ++j) nt += !isnan(target[j]);
+        const int mj = 5 * (R.j1 - R.j0), m = mj + nt;
+        double *u0 = calloc((size_t)6 * B->n_bodies + 1, sizeof(double));
+        double *Jt = calloc((size_t)m * n6 + 1, sizeof(double)), *F = calloc((size_t)m + 1, sizeof(double));
+        double *WJ = calloc((size_t)n6 * m + 1, sizeof(double)), *A = calloc((size_t)m * m + 1, sizeof(double));
+        double *L = calloc((size_t)m * m + 1, sizeof(double)), *y = calloc((size_t)m + 1, sizeof(double));
+        double *Dl = calloc((size_t)n6 + 1, sizeof(double));
+        if (!u0 || !Jt || !F || !WJ || !A || !L || !y || !Dl) {
+            err = -1;
+        } else {
+            int it = 0;
+            double fn = INFINITY;
+            for (;;) {
+                world_sys S;
+                memset(&S, 0, sizeof S);
+                if (build_world(&Bj, &P, q_out, u0, NULL, w, 1.0, &S) != 0) {
+                    err = -1;
+                    sys_free(&S);
+                    break;
+                }
+                /* F and J: the joint rows, then one row per target */
+                memset(Jt, 0, sizeof(double) * (size_t)m * n6);
+                for (int r = 0; r < mj; ++r) {
+                    F[r] = S.f[r];
+                    for (int c = 0; c < n6; ++c) Jt[(size_t)r * n6 + c] = S.J[(size_t)r * n6 + c];
+                }
+                int r = mj;
+                for (int j = R.j0; j < R.j1; ++j) {
+                    if (isnan(target[j])) continue;
+                    double Ja[6], Jb[6];
+                    F[r] = joint_coordinate(&Bj, q_out, j, Ja, Jb) - target[j];
+                    int la = local_body(B->joint_body[2 * j], R.b0), lb = local_body(B->joint_body[2 * j + 1], R.b0);
+                    for (int k = 0; k < 6; ++k) {
+                        if (la >= 0) Jt[(size_t)r * n6 + 6 * la + k] += Ja[k];
+                        if (lb >= 0) Jt[(size_t)r * n6 + 6 * lb + k] += Jb[k];
+                    }
+                    ++r;
+                }
+                fn = inf_norm(m, F);
+                if (fn <= tol || it >= max_iters) {
+                    sys_free(&S);
+                    break;
+                }
+                /* W J^T with W = M^-1, the base body's block zero */
+                const int lbase = base ? local_body(base[w], R.b0) : -1;
+                for (int i = 0; i < nb; ++i)
+                    for (int a = 0; a < 6; ++a)
+                        for (int k = 0; k < m; ++k) {
+                            double s = 0.0;
+                            if (i != lbase)
+                                for (int c = 0; c < 6; ++c)
+                                    s += S.Minv[36 * (size_t)i + 6 * a + c] * Jt[(size_t)k * n6 + 6 * i + c];
+                            WJ[(size_t)(6 * i + a) * m + k] = s;
+                        }
+                double dmax = 0.0;
+                for (int a = 0; a < m; ++a)
+                    for (int b = 0; b < m; ++b) {
+                        double s = 0.0;
+                        for (int c = 0; c < n6; ++c) s += Jt[(size_t)a * n6 + c] * WJ[(size_t)c * m + b];
+                        A[(size_t)a * m + b] = s;
+                        if (a == b && s > dmax) dmax = s;
+                    }
+                const double mu = 1e-12 * (dmax > 0.0 ? dmax : 1.0);
+                for (int a = 0; a < m; ++a) A[(size_t)a * m + a] += mu;
+                if (orc_cholesky(m, A, L) != 0) {
+                    sys_free(&S);
+                    break;
+                }
+                chol_solve(m, L, F, y);
+                for (int c = 0; c < n6; ++c) {
+                    double s = 0.0;
+                    for (int k = 0; k < m; ++k) s += WJ[(size_t)c * m + k] * y[k];
+                    Dl[c] = -s;
+                }
+                for (int i = 0; i < nb; ++i) {
+                    double qn[7];
+                    advance_pose(q_out + 7 * (size_t)(R.b0 + i), Dl + 6 * i, 1.0, qn);
+                    for (int k = 0; k < 7; ++k) q_out[7 * (size_t)(R.b0 + i) + k] = qn[k];
+                }
+                ++it;
+                sys_free(&S);
+            }
+            iters[w] = it;
+            resid[w] = fn;
+        }
+        free(u0); free(Jt); free(F); free(WJ); free(A); free(L); free(y); free(Dl);
+    }
+    return err;
+}
