@@ -17,7 +17,10 @@
  *                   D + diag(eta + rho) once per step;
  *   Sec. 4.1        Nesterov acceleration with restart, warm start,
  *                   Jacobi preconditioning, infinity-norm residuals;
- *   Sec. 5.2        heterogeneous worlds (per-world sizes, masks).
+ *   Sec. 5.2        heterogeneous worlds (per-world sizes, masks);
+ *   Sec. 3, Eq. 2   joint drives (implicit PD, armature, viscous damping)
+ *                   as regularised rows (R and v* of the KKT system), and
+ *                   the Moreau-Jean midpoint variant of the time step.
  *
  * Conventions.  Quaternions are (x, y, z, w).  Twists are (v, w), w in the
  * world frame.  A joint couples body_a (a body of the same world) and body_b
@@ -26,7 +29,8 @@
  * for body_b = -1) whose x axis is the joint axis.  A contact normal points
  * from body_b to body_a; a positive normal impulse separates them.  Constraint
  * rows of a world are ordered: 5 rows per joint (joint order), one row per
- * joint with a limit, then 3 rows (n, t1, t2) per contact.
+ * joint with a limit, one row per joint with an implicit drive (joint
+ * order), then 3 rows (n, t1, t2) per contact.
  *
  * Ownership.  All pointer arguments are owned by the caller.  Arguments named
  * "_dev" are device pointers (e.g. torch tensors' data_ptr()); the rest are
@@ -78,6 +82,10 @@ typedef int32_t kamx_status;
 #define KAMX_WARM_EXTERNAL 2 /* impulses given by kamx_set_warmstart      */
 #define KAMX_WARM_LEARNED 3  /* prediction of the attached network         */
 
+#define KAMX_EULER 0       /* semi-implicit Euler (Sec. 3)                            */
+#define KAMX_MOREAU_JEAN 1 /* Moreau-Jean midpoint: constraints, forces and contacts at
+                              q + dt/2 u-, then q+ = q_mid + dt/2 u+ (Sec. 3)         */
+
 #define KAMX_SCHED_INDEX 0 /* one launch per step, worlds of a bucket in index order           */
 #define KAMX_SCHED_LPT 1   /* one launch per step, by decreasing previous iteration count       */
 #define KAMX_SCHED_CHAIN 2 /* multi-step calls keep each world on its workgroup for up to 64
@@ -101,10 +109,23 @@ typedef struct {
  * -1).  limit_lo / limit_hi bound the joint coordinate (revolute: angle of
  * A's frame about the axis relative to B's; prismatic: offset of A's anchor
  * along B's axis); NaN means unbounded, and a joint with any finite bound
- * gets one unilateral row against the nearer bound.  Actuation adds the
- * generalized force kp (ref - c) - kd dc/dt along the coordinate c, plus
- * Gaussian noise of the model's torque_sigma when actuated != 0.  Joints must
- * be sorted by world. */
+ * gets one unilateral row against the nearer bound.  Gaussian noise of the
+ * model's torque_sigma is added along the coordinate c when actuated != 0.
+ *
+ * Drive.  With implicit_drive = 0, kp and kd act explicitly: the generalized
+ * force kp (ref - c) - kd dc/dt from the step's start configuration;
+ * damping and armature must then be 0.  With implicit_drive != 0 the joint
+ * gets a drive row (Sec. 3: gains absorbed into the constraint rows; Eq. 2:
+ * R and v*): over the step the drive's impulse is
+ *   dt [kp (ref - c - h dc+/dt) - (kd + damping) dc+/dt
+ *       - armature (dc+/dt - dc-/dt) / dt],
+ * PD on the coordinate reached at the end of the step, viscous damping on
+ * the new rate, and the rotor's reflected inertia (armature, kg m^2 or kg)
+ * opposing the change of rate; h is the time from the configuration the
+ * row is built at to the end of the step (dt; dt/2 for KAMX_MOREAU_JEAN).
+ * The row has R = 1 / (dt K) and v* = -(kp (ref - c) + armature dc-/dt /
+ * dt) / K with K = kp h + kd + damping + armature / dt > 0, so it is stable
+ * for any gains.  Joints must be sorted by world. */
 typedef struct {
     int32_t type;
     int32_t world;
@@ -114,6 +135,8 @@ typedef struct {
     float limit_lo, limit_hi;
     float kp, kd, ref;
     int32_t actuated;
+    float damping, armature;
+    int32_t implicit_drive;
 } kamx_joint_desc;
 
 /* A contact probe: a point fixed in a body, tested each step against the
@@ -168,11 +191,16 @@ typedef struct {
     float reset_height;   /* a world whose reset body is below this height is
                              reset to the stored initial state at step start */
     int32_t log_restarts; /* 1: record the restart decision of every iteration */
+    int32_t integrator;   /* KAMX_EULER or KAMX_MOREAU_JEAN                   */
 } kamx_params;
 
 /* Fill *p with defaults (dt 2 ms, gravity -9.81 z, eta 1e-4, rho 1e-4 / 0.3,
  * eps 1e-6, 2000 iterations, acceleration and preconditioning on, restart
- * factor 0.999, beta 0.2, cold start, margin 0.02 m, no noise). */
+ * factor 0.999, beta 0.2, cold start, margin 0.02 m, no noise, semi-implicit
+ * Euler).  Position-level terms act over the time from the configuration
+ * the rows are built at to the end of the step: the Baumgarte bias of a
+ * bilateral row is beta f / h, a separated contact or limit f / h, a
+ * penetrating one beta f / h, with h = dt (Euler) or dt/2 (Moreau-Jean). */
 void kamx_default_params(kamx_params *p);
 
 /* Create a model of n_worlds worlds.  bodies[nb], joints[nj], probes[np]
@@ -316,6 +344,37 @@ kamx_status kamx_step(kamx_model m, int32_t nsteps, kamx_stream stream);
  * iters_dev = NULL turns logging off.  EINVAL if steps < 1. */
 kamx_status kamx_set_iteration_log(kamx_model m, int32_t *iters_dev, int32_t *rows_dev, int32_t steps);
 
+/* Forward kinematics for resets (Sec. 6.3): move every body of every world
+ * so that all joint constraints hold (the passive joints of kinematic loops
+ * included) and each joint j with a finite targets_dev[j] (device, [nj],
+ * global joint order; NaN = free) sits at that coordinate, keeping each
+ * world's reset body where it is (worlds without one move all bodies).
+ * Gauss-Newton from the current poses: F = (the five constraint functions
+ * of every joint, c_j - target_j), least-change steps -M^-1 J^T (J M^-1 J^T
+ * + mu)^-1 F (Jacobi-scaled, mu = 1e-5 on the unit diagonal), bodies moved
+ * by the exponential map; F and the poses in FP64, the linear solves in
+ * FP32.  Stops when |F|_inf <= tol or after max_iters iterations.  The
+ * poses are written back (FP32) and the twists set to zero; iters_dev and
+ * resid_dev [n_worlds] (device, may be NULL) receive the iterations taken
+ * and |F|_inf at the returned FP64 poses (NaN when the normal matrix could
+ * not be factored, or when a world has more than 224 rows with its target
+ * rows: 5 per joint plus one per target, that world is left unchanged).
+ * Asynchronous on stream; EINVAL on bad arguments. */
+kamx_status kamx_forward_kinematics(kamx_model m, const float *targets_dev, int32_t max_iters, float tol,
+                                    int32_t *iters_dev, float *resid_dev, kamx_stream stream);
+
+/* The iterate Alg. 1 returns (step 11), for checking the reported
+ * residuals (step 9) from outside: every following step writes, for every
+ * row r of every world (at the row offsets of kamx_model_info),
+ * iterate_dev[4 r .. 4 r + 3] = (x~, y~, z~, p): the last x, y and z of the
+ * world's solve in preconditioned units and the row's Jacobi scale
+ * (Sec. 4.1), so that lambda = p y~; rows beyond a world's active count get
+ * zeros.  iterate_dev (device, [rows_capacity * 4] floats, 16-byte aligned,
+ * caller-owned, valid while steps are pending) or NULL (off).  Drops
+ * captured graphs; not written by kamx_autotune's trials.  EINVAL when
+ * misaligned. */
+kamx_status kamx_set_iterate_log(kamx_model m, float *iterate_dev);
+
 /* Impulses of the last step (physical units, N s) into lambda_dev
  * [rows_capacity]; rows beyond a world's active count are zero. */
 kamx_status kamx_read_impulses(kamx_model m, float *lambda_dev, kamx_stream stream);
@@ -396,6 +455,24 @@ kamx_status kamx_mlp_set_normalization(kamx_mlp net, const float *mu_in, const f
 /* y_dev [batch][n_out] = network(x_dev [batch][n_in]); 1 <= batch <= max_batch. */
 kamx_status kamx_mlp_forward(kamx_mlp net, const float *x_dev, int32_t batch, float *y_dev, kamx_stream stream);
 
+/* The forward pass of kamx_mlp_forward for callers that cannot allocate
+ * device memory (code under stream or graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): same kernels, same result bit for bit,
+ * but the normalised input and both hidden activations live in a fixed
+ * 16 MiB device array that the library holds on every GPU it runs on until
+ * the process ends; this call allocates nothing and frees nothing.  x_dev
+ * [batch][n_in] and y_dev [batch][n_out] are the caller's device arrays.
+ * Limit: pad64(batch) * (n_in_pad + 2 n_hidden) * 2 bytes <= 16 MiB (for
+ * 704 padded inputs and 256 hidden units, batch <= 6848); a larger batch is
+ * rejected with EINVAL before any work is enqueued.  The network's own
+ * max_batch does not apply.  Every call on one GPU shares that GPU's array
+ * and overwrites it: calls that overlap on one GPU (on different streams,
+ * or with a kamx_mlp_forward_noalloc of another network) race; calls
+ * ordered on one stream do not.  EDEVICE if the array's address cannot be
+ * obtained. */
+kamx_status kamx_mlp_forward_noalloc(kamx_mlp net, const float *x_dev, int32_t batch, float *y_dev,
+                                     kamx_stream stream);
+
 /* One Adam step on the mean squared error of the standardised outputs
  * against y_target_dev [batch][n_out] (physical units).  loss_dev (device,
  * may be NULL) receives the loss before the update. */
@@ -410,14 +487,16 @@ kamx_status kamx_mlp_weights(kamx_mlp net, float *buf_dev, int32_t set, kamx_str
 kamx_status kamx_mlp_gradients(kamx_mlp net, float *buf_dev, kamx_stream stream);
 
 /* Feature and slot sizes of a model whose worlds share one structure (same
- * bodies, joints, limited joints and contact capacity; else EUNSUPPORTED).
- * Slots: the 5 rows of every joint and the limit rows in row order, then
- * three (n, t1, t2) per contact key 0 .. contact capacity - 1 (the probe
- * index for probe contacts).  Features per world: for every body its
- * position relative to the world's reset body (3), quaternion (4), linear
- * and angular velocity (6); then the previous step's impulses by slot
- * (zero after a reset); then the generalized joint forces of the coming
- * step (actuation, noise and external). */
+ * bodies, joints, limited and driven joints and contact capacity; else
+ * EUNSUPPORTED).  Slots: the 5 rows of every joint, the limit rows and the
+ * drive rows in row order, then three (n, t1, t2) per contact key 0 ..
+ * contact capacity - 1 (the probe index for probe contacts).  Features per
+ * world: for every body its position relative to the world's reset body
+ * (3), quaternion (4), linear and angular velocity (6) at the configuration
+ * the step's rows are built at (the half-step poses for KAMX_MOREAU_JEAN);
+ * then the previous step's impulses by slot (zero after a reset); then the
+ * explicit generalized joint forces of the coming step (explicit PD, noise
+ * and external). */
 kamx_status kamx_model_feature_dims(kamx_model m, int32_t *n_features, int32_t *n_slots);
 
 /* Features of the coming step into x_dev [n_worlds][n_features]. */

@@ -926,7 +926,8 @@ int orc_solve_ncp(int m, const double *D, const double *vf, const int *kind, con
             int restart;
             if (P->replay && replay_log) restart = replay_log[it - 1] != 0;
             else restart = !(c < P->restart_factor * c_prev);
-            if (log_out) log_out[it - 1] = (uint8_t)restart;
+            /* the log holds log_stride decisions per world (0: as many as iterations) */
+            if (log_out && (P->log_stride <= 0 || it <= P->log_stride)) log_out[it - 1] = (uint8_t)restart;
             if (!restart) {
                 double a_next = 0.5 * (1.0 + sqrt(1.0 + 4.0 * a_k * a_k));
                 double beta = (a_k - 1.0) / a_next;

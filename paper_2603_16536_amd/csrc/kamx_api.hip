@@ -19,8 +19,12 @@ int bucket_capacity(int rows);
 size_t step_smem_bytes(int mc);
 hipError_t launch_lpt_order(const int32_t *worlds, int n, const int32_t *iters, int32_t *order, hipStream_t stream);
 hipError_t launch_advance_step(uint32_t *ctr, uint32_t inc, hipStream_t stream);
-hipError_t launch_box_bin(const WorldInfo *worlds, int n_worlds, const float *q, const float *box_geom, float wx,
-                          float wy, float margin, kamx_contact *out, int32_t *count, hipStream_t stream);
+hipError_t launch_fk(const WorldInfo *worlds, int n_worlds, const int32_t *jint, const float *jf, const float *mass,
+                     const float *inertia, float *q, float *u, const float *targets, int max_iters, float tol,
+                     int32_t *iters, float *resid, hipStream_t stream);
+hipError_t launch_box_bin(const WorldInfo *worlds, int n_worlds, const float *q, const float *u, float half_dt,
+                          const float *box_geom, float wx, float wy, float margin, kamx_contact *out, int32_t *count,
+                          hipStream_t stream);
 int box_bin_max_boxes();
 bool step_generates_box_contacts(int mc);
 hipError_t launch_impulse_slots(const WorldInfo *worlds, int n_worlds, int n_contact_slots, int n_slots,
@@ -83,6 +87,7 @@ struct kamx_model_s {
     int32_t *iter_log = nullptr;  // caller-owned [iter_log_rows * n_worlds] iterations per step
     int32_t *row_log = nullptr;   // caller-owned, same shape: active rows per step
     int32_t iter_log_rows = 0;
+    float *iterate_log = nullptr;  // caller-owned [rows_cap * 4] final iterate of the last step
     std::vector<int32_t> row_offsets;
     std::vector<Bucket> buckets;
     std::vector<void *> allocations;
@@ -162,6 +167,8 @@ static kamx_status check_device() {
 }
 
 static kamx_status validate_params(const kamx_params *p) {
+    if (p && p->integrator != KAMX_EULER && p->integrator != KAMX_MOREAU_JEAN)
+        return fail(KAMX_EINVAL, "integrator must be KAMX_EULER or KAMX_MOREAU_JEAN");
     if (!p) return fail(KAMX_EINVAL, "params is NULL");
     if (!(p->dt > 0.f)) return fail(KAMX_EINVAL, "dt must be positive");
     if (!(p->eta >= 0.f) || !(p->rho_bilateral > 0.f) || !(p->rho_contact > 0.f))
@@ -196,6 +203,7 @@ static SolverParams to_solver(const kamx_params &p) {
     s.seed_hi = (uint32_t)(p.seed >> 32);
     s.reset_height = p.reset_height;
     s.log_restarts = p.log_restarts;
+    s.integrator = p.integrator;
     return s;
 }
 
@@ -222,6 +230,7 @@ void kamx_default_params(kamx_params *p) {
     p->seed = 0;
     p->reset_height = -INFINITY;
     p->log_restarts = 0;
+    p->integrator = KAMX_EULER;
 }
 
 const char *kamx_last_error(void) { return g_error.c_str(); }
@@ -295,6 +304,7 @@ kamx_status kamx_model_create(const kamx_body_desc *bodies, int32_t nb, const ka
         if (W.nj > kMaxJoints) return fail(KAMX_EINVAL, "world %d: %d joints (max %d)", w, W.nj, kMaxJoints);
         if (W.np > kMaxContacts) return fail(KAMX_EINVAL, "world %d: %d probes (max %d)", w, W.np, kMaxContacts);
         W.nlim = 0;
+        W.ndrv = 0;
         for (int j = W.j0; j < W.j0 + W.nj; ++j) {
             const kamx_joint_desc &J = joints[j];
             if (J.type != KAMX_REVOLUTE && J.type != KAMX_PRISMATIC)
@@ -304,12 +314,23 @@ kamx_status kamx_model_create(const kamx_body_desc *bodies, int32_t nb, const ka
             if (J.body_b != -1 && (J.body_b < W.b0 || J.body_b >= W.b0 + W.nb || J.body_b == J.body_a))
                 return fail(KAMX_EINVAL, "joint %d: body_b %d invalid", j, J.body_b);
             if (!isnan(J.limit_lo) || !isnan(J.limit_hi)) W.nlim++;
+            if (!(J.damping >= 0.f) || !(J.armature >= 0.f) || !isfinite(J.damping) || !isfinite(J.armature))
+                return fail(KAMX_EINVAL, "joint %d: damping and armature must be finite and >= 0", j);
+            if (J.implicit_drive) {
+                if (!(J.kp >= 0.f) || !(J.kd >= 0.f) || !isfinite(J.kp) || !isfinite(J.kd) || !isfinite(J.ref))
+                    return fail(KAMX_EINVAL, "joint %d: implicit drive needs finite kp, kd >= 0 and ref", j);
+                if (!(J.kp > 0.f || J.kd > 0.f || J.damping > 0.f || J.armature > 0.f))
+                    return fail(KAMX_EINVAL, "joint %d: implicit drive with all gains zero", j);
+                W.ndrv++;
+            } else if (J.damping != 0.f || J.armature != 0.f) {
+                return fail(KAMX_EINVAL, "joint %d: damping and armature need implicit_drive", j);
+            }
         }
         for (int k = W.p0; k < W.p0 + W.np; ++k)
             if (probes[k].body < W.b0 || probes[k].body >= W.b0 + W.nb)
                 return fail(KAMX_EINVAL, "probe %d: body %d not in world %d", k, probes[k].body, w);
         W.contact_cap = std::max(W.np, (int)max_contacts_per_world);
-        W.row_cap = 5 * W.nj + W.nlim + 3 * W.contact_cap;
+        W.row_cap = 5 * W.nj + W.nlim + W.ndrv + 3 * W.contact_cap;
         if (W.row_cap > kMaxRows)
             return fail(KAMX_EINVAL, "world %d: row capacity %d exceeds %d", w, W.row_cap, kMaxRows);
         W.row_base = row_off[w];
@@ -334,10 +355,10 @@ kamx_status kamx_model_create(const kamx_body_desc *bodies, int32_t nb, const ka
     m->uniform = true;
     for (int w = 1; w < n_worlds; ++w)
         if (wi[w].nb != wi[0].nb || wi[w].nj != wi[0].nj || wi[w].nlim != wi[0].nlim ||
-            wi[w].contact_cap != wi[0].contact_cap)
+            wi[w].ndrv != wi[0].ndrv || wi[w].contact_cap != wi[0].contact_cap)
             m->uniform = false;
     m->n_contact_slots = wi[0].contact_cap;
-    m->n_slots = 5 * wi[0].nj + wi[0].nlim + 3 * wi[0].contact_cap;
+    m->n_slots = 5 * wi[0].nj + wi[0].nlim + wi[0].ndrv + 3 * wi[0].contact_cap;
     m->n_feat = 13 * wi[0].nb + m->n_slots + wi[0].nj;
 
     auto cleanup_fail = [&](kamx_status st) {
@@ -367,6 +388,7 @@ kamx_status kamx_model_create(const kamx_body_desc *bodies, int32_t nb, const ka
         int fl = 0;
         if (J.actuated) fl |= kJointActuated;
         if (!isnan(J.limit_lo) || !isnan(J.limit_hi)) fl |= kJointLimited;
+        if (J.implicit_drive) fl |= kJointDriven;
         jint[4 * j + 3] = fl;
         float *f = &jf[kJointFloats * (size_t)j];
         for (int e = 0; e < 7; ++e) {
@@ -378,6 +400,8 @@ kamx_status kamx_model_create(const kamx_body_desc *bodies, int32_t nb, const ka
         f[16] = J.kp;
         f[17] = J.kd;
         f[18] = J.ref;
+        f[19] = J.damping;
+        f[20] = J.armature;
     }
     std::vector<int32_t> pbody(std::max(np, 1), 0);
     std::vector<float> pf(4 * (size_t)std::max(np, 1), 0.f);
@@ -587,6 +611,7 @@ static StepArgs step_args(kamx_model m) {
     a.status = m->d_status;
     a.rows = m->d_rows;
     a.rlog = m->params.log_restarts ? m->d_rlog : nullptr;
+    a.iterate_out = m->iterate_log;
     a.tau_out = m->d_tau;
     a.contacts_out = m->d_contacts_out;
     a.ncontacts_out = m->d_ncontacts;
@@ -602,6 +627,12 @@ static StepArgs step_args(kamx_model m) {
     if (m->mlp) a.mlp = mlp_view(m->mlp);
     a.n_contact_slots = m->n_contact_slots;
     return a;
+}
+
+// time by which the stand-alone contact generation advances the poses: the
+// step builds its rows at the half-step configuration for Moreau-Jean
+static float gen_half_dt(kamx_model m) {
+    return m->params.integrator == KAMX_MOREAU_JEAN ? 0.5f * m->params.dt : 0.f;
 }
 
 static kamx_status ensure_bucket_streams(kamx_model m) {
@@ -649,8 +680,8 @@ static kamx_status enqueue_launch(kamx_model m, int n, int pos, hipStream_t s) {
     }
     const bool lpt = n == 1 && m->schedule != KAMX_SCHED_INDEX;
     if (m->box_bin && !m->box_fused) {
-        hipError_t e = launch_box_bin(m->d_worlds, m->n_worlds, m->d_q, m->d_box_geom, m->bin_wx, m->bin_wy,
-                                      m->bin_margin, m->d_gen, m->d_gen_count, s);
+        hipError_t e = launch_box_bin(m->d_worlds, m->n_worlds, m->d_q, m->d_u, gen_half_dt(m), m->d_box_geom,
+                                      m->bin_wx, m->bin_wy, m->bin_margin, m->d_gen, m->d_gen_count, s);
         if (e != hipSuccess) return fail(KAMX_EDEVICE, "contact generation launch: %s", hipGetErrorString(e));
     }
     // several buckets run concurrently on the model's bucket streams (fork
@@ -851,12 +882,13 @@ static kamx_status enqueue_bucket_trial(kamx_model m, int bi, int steps, hipStre
     StepArgs a = step_args(m);
     a.bucket_worlds = b.d_worlds;
     a.n_bucket_worlds = b.n;
+    a.iterate_out = nullptr;  // trials leave the caller's iterate log alone
     const bool chain = chained(m);
     for (int k = 0; k < steps;) {
         const int n = chain ? steps - k : 1;
         if (m->box_bin && !m->box_fused) {
-            hipError_t e = launch_box_bin(m->d_worlds, m->n_worlds, m->d_q, m->d_box_geom, m->bin_wx, m->bin_wy,
-                                          m->bin_margin, m->d_gen, m->d_gen_count, s);
+            hipError_t e = launch_box_bin(m->d_worlds, m->n_worlds, m->d_q, m->d_u, gen_half_dt(m), m->d_box_geom,
+                                          m->bin_wx, m->bin_wy, m->bin_margin, m->d_gen, m->d_gen_count, s);
             if (e != hipSuccess) return fail(KAMX_EDEVICE, "contact generation launch: %s", hipGetErrorString(e));
         }
         a.nsteps = n;
@@ -950,6 +982,28 @@ kamx_status kamx_set_iteration_log(kamx_model m, int32_t *iters_dev, int32_t *ro
     m->iter_log = iters_dev;
     m->row_log = iters_dev ? rows_dev : nullptr;
     m->iter_log_rows = iters_dev ? steps : 0;
+    return KAMX_OK;
+}
+
+kamx_status kamx_forward_kinematics(kamx_model m, const float *targets_dev, int32_t max_iters, float tol,
+                                    int32_t *iters_dev, float *resid_dev, kamx_stream stream) {
+    if (!m) return fail(KAMX_EINVAL, "model is NULL");
+    if (!targets_dev) return fail(KAMX_EINVAL, "targets_dev is NULL");
+    if (max_iters < 0 || max_iters > 10000) return fail(KAMX_EINVAL, "max_iters must be in [0, 10000]");
+    if (!(tol >= 0.f)) return fail(KAMX_EINVAL, "tol must be >= 0");
+    K_TRY(check_device());
+    hipError_t e = launch_fk(m->d_worlds, m->n_worlds, m->d_jint, m->d_jf, m->d_mass, m->d_inertia, m->d_q, m->d_u,
+                             targets_dev, max_iters, tol, iters_dev, resid_dev, reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail(KAMX_EDEVICE, "forward kinematics launch: %s", hipGetErrorString(e));
+    return KAMX_OK;
+}
+
+kamx_status kamx_set_iterate_log(kamx_model m, float *iterate_dev) {
+    if (!m) return fail(KAMX_EINVAL, "model is NULL");
+    if (iterate_dev && (reinterpret_cast<uintptr_t>(iterate_dev) & 15))
+        return fail(KAMX_EINVAL, "iterate_dev must be 16-byte aligned");
+    drop_graphs(m);
+    m->iterate_log = iterate_dev;
     return KAMX_OK;
 }
 

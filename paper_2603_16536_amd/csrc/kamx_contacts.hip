@@ -12,18 +12,31 @@ namespace {
 
 constexpr int kNarrowThreads = 256;
 
+// half_dt > 0: the boxes at their Moreau-Jean half-step poses (q advanced
+// by half_dt with the twists u), the configuration the step builds its rows at
 __global__ __launch_bounds__(kNarrowThreads) void box_bin_kernel(const WorldInfo *worlds, const float *q,
+                                                                 const float *u, float half_dt,
                                                                  const float *box_geom, float wx, float wy,
                                                                  float margin, kamx_contact *out, int32_t *count) {
     __shared__ BoxLds S;
     const int w = blockIdx.x;
     const WorldInfo W = worlds[w];
     const float *qw = q + 7 * (long)W.b0;
+    const float *uw = u + 6 * (long)W.b0;
     const int keep = box_bin_generate<kNarrowThreads>(
         S, W.nb, box_geom + 4 * (long)W.b0, wx, wy, margin, W.contact_cap,
         [&](int b, float c[3], float qt[4]) {
-            for (int e = 0; e < 3; ++e) c[e] = qw[7 * b + e];
-            for (int e = 0; e < 4; ++e) qt[e] = qw[7 * b + 3 + e];
+            float pose[7];
+            for (int e = 0; e < 7; ++e) pose[e] = qw[7 * b + e];
+            if (half_dt > 0.f) {
+                float u6[6];
+                for (int e = 0; e < 6; ++e) u6[e] = uw[6 * b + e];
+                float qm[7];
+                half_step_pose(pose, u6, half_dt, qm);
+                for (int e = 0; e < 7; ++e) pose[e] = qm[e];
+            }
+            for (int e = 0; e < 3; ++e) c[e] = pose[e];
+            for (int e = 0; e < 4; ++e) qt[e] = pose[3 + e];
         },
         [&](int c, int key, float gap, const float p[3], const float n[3], float mu, int la, int lb) {
             kamx_contact ct;
@@ -43,11 +56,12 @@ __global__ __launch_bounds__(kNarrowThreads) void box_bin_kernel(const WorldInfo
 
 }  // namespace
 
-hipError_t launch_box_bin(const WorldInfo *worlds, int n_worlds, const float *q, const float *box_geom, float wx,
-                          float wy, float margin, kamx_contact *out, int32_t *count, hipStream_t stream) {
+hipError_t launch_box_bin(const WorldInfo *worlds, int n_worlds, const float *q, const float *u, float half_dt,
+                          const float *box_geom, float wx, float wy, float margin, kamx_contact *out, int32_t *count,
+                          hipStream_t stream) {
     if (n_worlds <= 0) return hipSuccess;
-    hipLaunchKernelGGL(box_bin_kernel, dim3(n_worlds), dim3(kNarrowThreads), 0, stream, worlds, q, box_geom, wx, wy,
-                       margin, out, count);
+    hipLaunchKernelGGL(box_bin_kernel, dim3(n_worlds), dim3(kNarrowThreads), 0, stream, worlds, q, u, half_dt,
+                       box_geom, wx, wy, margin, out, count);
     return hipGetLastError();
 }
 

@@ -12,7 +12,7 @@ constexpr int kMaxBodies = KAMX_MAX_BODIES_PER_WORLD;
 constexpr int kMaxJoints = KAMX_MAX_JOINTS_PER_WORLD;
 constexpr int kMaxContacts = KAMX_MAX_CONTACTS_PER_WORLD;
 constexpr int kMaxRows = KAMX_MAX_ROWS_PER_WORLD;
-constexpr int kJointFloats = 24;  // frame_a 7, frame_b 7, lo, hi, kp, kd, ref, pad
+constexpr int kJointFloats = 24;  // frame_a 7, frame_b 7, lo, hi, kp, kd, ref, damping, armature, pad
 
 // row kinds
 constexpr int kRowBilateral = 0;
@@ -23,6 +23,7 @@ constexpr int kRowTangent = 3;
 // joint flag bits (jint[4*j+3])
 constexpr int kJointActuated = 1;
 constexpr int kJointLimited = 2;
+constexpr int kJointDriven = 4;  // implicit drive row (PD, damping, armature)
 
 // Per-world table (one 64-byte record per world).
 struct WorldInfo {
@@ -34,7 +35,8 @@ struct WorldInfo {
     int32_t row_cap;        // row capacity (joint + limit + 3 * contact capacity)
     int32_t contact_cap;    // contact capacity
     int32_t reset_body;     // world-local body index, or -1
-    int32_t pad[5];
+    int32_t ndrv;           // joints with an implicit drive row
+    int32_t pad[4];
 };
 
 struct SolverParams {
@@ -50,7 +52,35 @@ struct SolverParams {
     uint32_t seed_lo, seed_hi;
     float reset_height;
     int32_t log_restarts;
+    int32_t integrator;  // KAMX_EULER or KAMX_MOREAU_JEAN
 };
+
+// Poses the step's rows are built at: the pre-step pose (Euler), or for the
+// Moreau-Jean midpoint the pose advanced by h = dt / 2 with the pre-step
+// twist (r + h v, exp(h [w]x) R by the quaternion exponential, renormalised).
+// Shared by the step kernel and the contact generation kernel so both see
+// the same bits.
+__device__ inline void half_step_pose(const float q[7], const float u[6], float h, float out[7]) {
+    for (int k = 0; k < 3; ++k) out[k] = q[k] + h * u[k];
+    const float wn = sqrtf(u[3] * u[3] + u[4] * u[4] + u[5] * u[5]);
+    float dq[4] = {0.f, 0.f, 0.f, 1.f};
+    if (wn > 0.f) {
+        const float half = 0.5f * h * wn;
+        const float sh = sinf(half) / wn;
+        dq[0] = u[3] * sh;
+        dq[1] = u[4] * sh;
+        dq[2] = u[5] * sh;
+        dq[3] = cosf(half);
+    }
+    const float *p = q + 3;
+    float r[4];
+    r[0] = dq[3] * p[0] + dq[0] * p[3] + dq[1] * p[2] - dq[2] * p[1];
+    r[1] = dq[3] * p[1] - dq[0] * p[2] + dq[1] * p[3] + dq[2] * p[0];
+    r[2] = dq[3] * p[2] + dq[0] * p[1] - dq[1] * p[0] + dq[2] * p[3];
+    r[3] = dq[3] * p[3] - dq[0] * p[0] - dq[1] * p[1] - dq[2] * p[2];
+    const float nn = 1.f / sqrtf(r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + r[3] * r[3]);
+    for (int k = 0; k < 4; ++k) out[3 + k] = r[k] * nn;
+}
 
 // ---- learned warm start: numerics shared by the batched network kernels
 // and the per-world inference inside the step kernel, so both produce the
@@ -108,6 +138,7 @@ struct StepArgs {
     int32_t *status;
     int32_t *rows;          // active rows per world
     uint8_t *rlog;          // [n_worlds*max_iters] or null
+    float *iterate_out;     // [rows*4] final (x~, y~, z~, p) per row, or null
     float *tau_out;         // [nj]
     kamx_contact *contacts_out;  // [n_worlds*kMaxContacts]
     int32_t *ncontacts_out;      // [n_worlds]
@@ -140,7 +171,7 @@ __host__ __device__ inline int tri_row_offset(int i) {
 __host__ __device__ inline int body_floats() { return 32 * kMaxBodies; }
 __host__ __device__ inline int joint_floats() { return 16 * kMaxJoints; }  // tau, Jc[12], a, b, type|flags
 __host__ __device__ inline int contact_floats() { return 12 * kMaxContacts; }  // point, normal, gap, mu, a, b, key, slot
-__host__ __device__ inline int row_floats(int mc) { return 17 * mc; }
+__host__ __device__ inline int row_floats(int mc) { return 18 * mc; }
 __host__ __device__ inline int vec_floats(int mc) { return 15 * mc; }
 __host__ __device__ inline int bodyw_floats() { return 2 * 6 * kMaxBodies; }  // FP64 [6][kMaxBodies]
 __host__ __device__ inline int inc_floats(int mc) { return ((kMaxBodies + 1 + 2 * mc) + 3) & ~3; }

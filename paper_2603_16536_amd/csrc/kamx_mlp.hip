@@ -13,6 +13,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -120,7 +121,7 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_kernel(Operand A, Operand B
                 const float v = acc[i][j][c];
                 if (EPI == kEpiHidden) {
                     float z = v + e.bias[n];
-                    e.f32[m * e.ld + n] = z;
+                    if (e.f32) e.f32[m * e.ld + n] = z;
                     e.b16[m * e.ld + n] = to_bf16(gelu(z));
                 } else if (EPI == kEpiOut) {
                     float yn = v + e.bias[n];
@@ -384,10 +385,17 @@ extern "C" kamx_status kamx_mlp_create(int32_t n_in, int32_t n_hidden, int32_t n
     C_TRY(mlp_alloc(n, &n->partial, (R * std::max<long>(op, 1) + 255) / 256));
     {
         // split-K weight gradients: each of M x N outputs gets up to
-        // grad_splits(...) partials; bias gradients up to kColBlocks
-        const long a = (long)grad_splits(op, H, (int)R) * op * H, b = (long)grad_splits(H, H, (int)R) * H * H,
-                   c = (long)grad_splits(H, fp, (int)R) * H * fp, d = (long)kColBlocks * std::max(H, op);
-        n->ws_floats = std::max(std::max(a, b), std::max(c, d));
+        // grad_splits(...) partials for the padded batch K of a training
+        // call (any multiple of 64 up to the capacity: a smaller batch can
+        // take more slices than the capacity itself); bias gradients up to
+        // kColBlocks
+        long most = (long)kColBlocks * std::max(H, op);
+        for (long K = 64; K <= R; K += 64) {
+            const long a = (long)grad_splits(op, H, (int)K) * op * H, b = (long)grad_splits(H, H, (int)K) * H * H,
+                       c = (long)grad_splits(H, fp, (int)K) * H * fp;
+            most = std::max(most, std::max(a, std::max(b, c)));
+        }
+        n->ws_floats = most;
         C_TRY(mlp_alloc(n, &n->ws, n->ws_floats));
     }
     // initial weights U(-1/sqrt(fan_in), 1/sqrt(fan_in)) on the active
@@ -488,29 +496,37 @@ static hipError_t colsum(kamx_mlp n, const float *a, int rows, int cols, float *
     return hipGetLastError();
 }
 
+// Activations of one forward pass: the normalised BF16 input, the two
+// BF16 hidden activations and, for training, the FP32 pre-activations and
+// normalised outputs (null when only the prediction is wanted).
+struct Acts {
+    __bf16 *xh, *h1, *h2;
+    float *z1, *z2, *yn;
+};
+
 // forward over rows padded to a multiple of 64; y (optional) receives the
 // de-standardised outputs of the first batch rows
-static kamx_status mlp_forward_rows(kamx_mlp n, const float *x, long ldx, int batch, float *y, long ldy,
-                                    bool keep_output, hipStream_t s) {
+static kamx_status mlp_forward_rows(kamx_mlp n, const Acts &a, const float *x, long ldx, int batch, float *y,
+                                    long ldy, hipStream_t s) {
     const int R = pad64(batch), H = n->H, fp = n->fp, op = n->op;
     const Layout &L = n->L;
     long cnt = (long)R * fp;
     hipLaunchKernelGGL(normalise_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, x, ldx, batch, n->n_in,
-                       n->mu_in, n->s_in, n->xh, R, fp);
+                       n->mu_in, n->s_in, a.xh, R, fp);
     MLP_HIP(hipGetLastError());
     EpiArgs e{};
     e.bias = n->w + L.ob1;
-    e.f32 = n->z1;
-    e.b16 = n->h1;
+    e.f32 = a.z1;
+    e.b16 = a.h1;
     e.ld = H;
-    MLP_HIP((gemm<kEpiHidden>(Operand{n->xh, fp, 1}, Operand{n->wb + L.bW1, fp, 1}, R, H, fp, e, s)));
+    MLP_HIP((gemm<kEpiHidden>(Operand{a.xh, fp, 1}, Operand{n->wb + L.bW1, fp, 1}, R, H, fp, e, s)));
     e.bias = n->w + L.ob2;
-    e.f32 = n->z2;
-    e.b16 = n->h2;
-    MLP_HIP((gemm<kEpiHidden>(Operand{n->h1, H, 1}, Operand{n->wb + L.bW2, H, 1}, R, H, H, e, s)));
+    e.f32 = a.z2;
+    e.b16 = a.h2;
+    MLP_HIP((gemm<kEpiHidden>(Operand{a.h1, H, 1}, Operand{n->wb + L.bW2, H, 1}, R, H, H, e, s)));
     EpiArgs o{};
     o.bias = n->w + L.ob3;
-    o.f32 = keep_output ? n->yn : nullptr;
+    o.f32 = a.yn;
     o.ld = op;
     o.y = y;
     o.ldy = ldy;
@@ -518,15 +534,25 @@ static kamx_status mlp_forward_rows(kamx_mlp n, const float *x, long ldx, int ba
     o.n_out = n->n_out;
     o.mu = n->mu_out;
     o.sigma = n->sd_out;
-    MLP_HIP((gemm<kEpiOut>(Operand{n->h2, H, 1}, Operand{n->wb + L.bW3, H, 1}, R, op, H, o, s)));
+    MLP_HIP((gemm<kEpiOut>(Operand{a.h2, H, 1}, Operand{n->wb + L.bW3, H, 1}, R, op, H, o, s)));
     return KAMX_OK;
+}
+
+static Acts own_acts(kamx_mlp n, bool keep) {
+    Acts a{n->xh, n->h1, n->h2, nullptr, nullptr, nullptr};
+    if (keep) {
+        a.z1 = n->z1;
+        a.z2 = n->z2;
+        a.yn = n->yn;
+    }
+    return a;
 }
 
 namespace kamx {
 // used by the model's learned warm start
 kamx_status mlp_forward_internal(kamx_mlp n, const float *x, int batch, float *y, hipStream_t s) {
     if (batch > n->cap) return mlp_fail(KAMX_EINVAL, "batch %d above the network's capacity %d", batch, n->cap);
-    return mlp_forward_rows(n, x, n->n_in, batch, y, n->n_out, false, s);
+    return mlp_forward_rows(n, own_acts(n, false), x, n->n_in, batch, y, n->n_out, s);
 }
 int mlp_n_in(kamx_mlp n) { return n->n_in; }
 MlpView mlp_view(kamx_mlp n) {
@@ -555,7 +581,63 @@ int mlp_capacity(kamx_mlp n) { return n->cap; }
 extern "C" kamx_status kamx_mlp_forward(kamx_mlp n, const float *x, int32_t batch, float *y, kamx_stream stream) {
     if (!n || !x || !y) return mlp_fail(KAMX_EINVAL, "NULL argument");
     if (batch < 1 || batch > n->cap) return mlp_fail(KAMX_EINVAL, "batch must be in [1, %d]", n->cap);
-    return mlp_forward_rows(n, x, n->n_in, batch, y, n->n_out, false, reinterpret_cast<hipStream_t>(stream));
+    return mlp_forward_rows(n, own_acts(n, false), x, n->n_in, batch, y, n->n_out,
+                            reinterpret_cast<hipStream_t>(stream));
+}
+
+// ---- forward pass without allocation -------------------------------------
+// The activations of kamx_mlp_forward_noalloc live in this fixed array: each
+// GPU the library runs on holds its own copy until the process ends.  Host
+// code never passes the array's name to a kernel (on the host it is only a
+// stand-in for the symbol); it uses the device address that
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t kNoallocScratchBytes = size_t(16) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// device address of this GPU's scratch array (looked up once per device)
+kamx_status scratch_address(void **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return mlp_fail(KAMX_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return mlp_fail(KAMX_EUNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return mlp_fail(KAMX_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return KAMX_OK;
+}
+}  // namespace
+
+extern "C" kamx_status kamx_mlp_forward_noalloc(kamx_mlp n, const float *x, int32_t batch, float *y,
+                                                kamx_stream stream) {
+    if (!n || !x || !y) return mlp_fail(KAMX_EINVAL, "NULL argument");
+    if (batch < 1 || batch > (1 << 24)) return mlp_fail(KAMX_EINVAL, "batch must be in [1, 2^24]");
+    const size_t per_row = sizeof(__bf16) * ((size_t)n->fp + 2 * (size_t)n->H);
+    const size_t rows_max = (kNoallocScratchBytes / per_row) / 64 * 64;
+    if ((size_t)pad64(batch) > rows_max)
+        return mlp_fail(KAMX_EINVAL, "batch %d above the %zu rows the fixed %zu-byte workspace holds for this network",
+                        batch, rows_max, kNoallocScratchBytes);
+    void *base = nullptr;
+    kamx_status st = scratch_address(&base);
+    if (st != KAMX_OK) return st;
+    // every activation is written before it is read (padded rows included),
+    // so nothing in the array has to start at zero
+    const long R = pad64(batch);
+    Acts a{};
+    a.xh = reinterpret_cast<__bf16 *>(base);
+    a.h1 = a.xh + R * n->fp;
+    a.h2 = a.h1 + R * n->H;
+    return mlp_forward_rows(n, a, x, n->n_in, batch, y, n->n_out, reinterpret_cast<hipStream_t>(stream));
 }
 
 extern "C" kamx_status kamx_mlp_train_step(kamx_mlp n, const float *x, const float *y_target, int32_t batch, float lr,
@@ -566,7 +648,7 @@ extern "C" kamx_status kamx_mlp_train_step(kamx_mlp n, const float *x, const flo
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const int R = pad64(batch), H = n->H, fp = n->fp, op = n->op;
     const Layout &L = n->L;
-    kamx_status st = mlp_forward_rows(n, x, n->n_in, batch, nullptr, 0, true, s);
+    kamx_status st = mlp_forward_rows(n, own_acts(n, true), x, n->n_in, batch, nullptr, 0, s);
     if (st != KAMX_OK) return st;
     const long cnt = (long)R * op;
     const int blocks = (int)((cnt + 255) / 256);

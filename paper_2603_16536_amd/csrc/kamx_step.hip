@@ -20,59 +20,10 @@
 #include <math.h>
 
 #include "kamx_boxbin.h"
+#include "kamx_geom.h"
 #include "kamx_internal.h"
 
 namespace kamx {
-
-// ---------------------------------------------------------------------------
-// small device math
-// ---------------------------------------------------------------------------
-
-template <typename T>
-__device__ inline void rot_of_quat(const T q[4], T R[9]) {
-    T x = q[0], y = q[1], z = q[2], w = q[3];
-    R[0] = T(1) - T(2) * (y * y + z * z);
-    R[1] = T(2) * (x * y - z * w);
-    R[2] = T(2) * (x * z + y * w);
-    R[3] = T(2) * (x * y + z * w);
-    R[4] = T(1) - T(2) * (x * x + z * z);
-    R[5] = T(2) * (y * z - x * w);
-    R[6] = T(2) * (x * z - y * w);
-    R[7] = T(2) * (y * z + x * w);
-    R[8] = T(1) - T(2) * (x * x + y * y);
-}
-
-template <typename T>
-__device__ inline void qprod(const T p[4], const T q[4], T r[4]) {
-    r[0] = p[3] * q[0] + p[0] * q[3] + p[1] * q[2] - p[2] * q[1];
-    r[1] = p[3] * q[1] - p[0] * q[2] + p[1] * q[3] + p[2] * q[0];
-    r[2] = p[3] * q[2] + p[0] * q[1] - p[1] * q[0] + p[2] * q[3];
-    r[3] = p[3] * q[3] - p[0] * q[0] - p[1] * q[1] - p[2] * q[2];
-}
-
-template <typename T>
-__device__ inline void cross(const T a[3], const T b[3], T c[3]) {
-    c[0] = a[1] * b[2] - a[2] * b[1];
-    c[1] = a[2] * b[0] - a[0] * b[2];
-    c[2] = a[0] * b[1] - a[1] * b[0];
-}
-
-template <typename T>
-__device__ inline T dot3(const T a[3], const T b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
-
-template <typename T>
-__device__ inline void mv3(const T R[9], const T v[3], T o[3]) {
-    o[0] = R[0] * v[0] + R[1] * v[1] + R[2] * v[2];
-    o[1] = R[3] * v[0] + R[4] * v[1] + R[5] * v[2];
-    o[2] = R[6] * v[0] + R[7] * v[1] + R[8] * v[2];
-}
-
-template <typename T>
-__device__ inline void mtv3(const T R[9], const T v[3], T o[3]) {
-    o[0] = R[0] * v[0] + R[3] * v[1] + R[6] * v[2];
-    o[1] = R[1] * v[0] + R[4] * v[1] + R[7] * v[2];
-    o[2] = R[2] * v[0] + R[5] * v[1] + R[8] * v[2];
-}
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).
 __device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
@@ -151,7 +102,7 @@ enum { JTAU = 0, JC = 1, JA = 13, JB = 14, JTF = 15 };
 // contact fields [field][kMaxContacts]
 enum { CP = 0, CN = 3, CGAP = 6, CMU = 7, CA = 8, CB = 9, CKEY = 10 };
 // row fields [field][MC]
-enum { RJ = 0, RBIAS = 12, RMU = 13, RIA = 14, RIB = 15, RKIND = 16 };
+enum { RJ = 0, RBIAS = 12, RMU = 13, RIA = 14, RIB = 15, RKIND = 16, RREG = 17 };
 // vector fields [field][MC]
 enum { VP = 0, VRHO, VVT, VX, VYH, VZH, VYP, VZP, VRHS, VT, VXN, VWS, VAUX, VCOL, VDX };
 
@@ -198,83 +149,11 @@ __device__ inline void apply_minv(const Lds &L, int b, const float in[6], float 
 // offsets and near-orthogonal axis products (about 1e-7 absolute) would
 // become velocity errors of order 1e-5.  J and everything downstream stay
 // FP32.
-struct JointGeo {
-    double pa[3], pb[3], ra[3], rb[3], Ra[9], Rb[9];
-};
-
 __device__ inline void joint_geo(const Lds &L, const float *jf, int la, int lb, JointGeo &g) {
-    double Rbody[9], t[3], qq[4], qb[4], fr[4], c[3];
-    for (int k = 0; k < 4; ++k) qb[k] = L.bf(BQ + 3 + k, la);
-    rot_of_quat(qb, Rbody);
-    for (int k = 0; k < 3; ++k) c[k] = jf[k];
-    mv3(Rbody, c, t);
-    for (int k = 0; k < 3; ++k) {
-        g.ra[k] = L.bf(BQ + k, la);
-        g.pa[k] = g.ra[k] + t[k];
-    }
-    for (int k = 0; k < 4; ++k) fr[k] = jf[3 + k];
-    qprod(qb, fr, qq);
-    rot_of_quat(qq, g.Ra);
-    for (int k = 0; k < 4; ++k) fr[k] = jf[10 + k];
-    if (lb >= 0) {
-        for (int k = 0; k < 4; ++k) qb[k] = L.bf(BQ + 3 + k, lb);
-        rot_of_quat(qb, Rbody);
-        for (int k = 0; k < 3; ++k) c[k] = jf[7 + k];
-        mv3(Rbody, c, t);
-        for (int k = 0; k < 3; ++k) {
-            g.rb[k] = L.bf(BQ + k, lb);
-            g.pb[k] = g.rb[k] + t[k];
-        }
-        qprod(qb, fr, qq);
-        rot_of_quat(qq, g.Rb);
-    } else {
-        for (int k = 0; k < 3; ++k) {
-            g.rb[k] = 0.0;
-            g.pb[k] = jf[7 + k];
-        }
-        rot_of_quat(fr, g.Rb);
-    }
-}
-
-__device__ inline void col(const double R[9], int k, double c[3]) {
-    c[0] = R[k];
-    c[1] = R[3 + k];
-    c[2] = R[6 + k];
-}
-
-// Joint coordinate and its Jacobian (6-vectors for sides a and b).
-__device__ inline double joint_coord(int type, const JointGeo &g, float Ja[6], float Jb[6]) {
-    double Xb[3], Yb[3], Zb[3], Ya[3];
-    col(g.Rb, 0, Xb);
-    col(g.Rb, 1, Yb);
-    col(g.Rb, 2, Zb);
-    col(g.Ra, 1, Ya);
-    if (type == KAMX_REVOLUTE) {
-        for (int k = 0; k < 3; ++k) {
-            Ja[k] = 0.f;
-            Jb[k] = 0.f;
-            Ja[3 + k] = (float)Xb[k];
-            Jb[3 + k] = (float)-Xb[k];
-        }
-        return atan2(dot3(Ya, Zb), dot3(Ya, Yb));
-    }
-    double d[3], la[3], lb[3], c[3];
-    for (int k = 0; k < 3; ++k) {
-        d[k] = g.pa[k] - g.pb[k];
-        la[k] = g.pa[k] - g.ra[k];
-        lb[k] = g.pa[k] - g.rb[k];
-    }
-    cross(la, Xb, c);
-    for (int k = 0; k < 3; ++k) {
-        Ja[k] = (float)Xb[k];
-        Ja[3 + k] = (float)c[k];
-    }
-    cross(lb, Xb, c);
-    for (int k = 0; k < 3; ++k) {
-        Jb[k] = (float)-Xb[k];
-        Jb[3 + k] = (float)-c[k];
-    }
-    return dot3(d, Xb);
+    double qa[7], qb[7];
+    for (int k = 0; k < 7; ++k) qa[k] = L.bf(BQ + k, la);
+    for (int k = 0; k < 7; ++k) qb[k] = lb >= 0 ? (double)L.bf(BQ + k, lb) : 0.0;
+    joint_geo_q(qa, qb, lb >= 0, jf, g);
 }
 
 __device__ inline void put_row(const Lds &L, int r, const float Ja[6], int la, const float Jb[6], int lb, float f,
@@ -287,10 +166,13 @@ __device__ inline void put_row(const Lds &L, int r, const float Ja[6], int la, c
     L.ri(RIB, r) = lb;
     L.ri(RKIND, r) = kind;
     L.rf(RMU, r) = mu;
+    L.rf(RREG, r) = 0.f;
+    // position-level terms act over the time from the rows' configuration to
+    // the end of the step: dt, or dt / 2 from the Moreau-Jean half step
     float bias = 0.f;
-    float inv_dt = 1.f / P.dt;
-    if (kind == kRowBilateral) bias = P.baumgarte * f * inv_dt;
-    else if (kind == kRowLimit || kind == kRowNormal) bias = (f >= 0.f ? f : P.baumgarte * f) * inv_dt;
+    float inv_h = (P.integrator == KAMX_MOREAU_JEAN ? 2.f : 1.f) / P.dt;
+    if (kind == kRowBilateral) bias = P.baumgarte * f * inv_h;
+    else if (kind == kRowLimit || kind == kRowNormal) bias = (f >= 0.f ? f : P.baumgarte * f) * inv_h;
     L.rf(RBIAS, r) = bias;
 }
 
@@ -308,75 +190,9 @@ __device__ inline void put_row6(const Lds &L, int r, const double Ja[6], int la,
 
 __device__ inline void joint_rows(const Lds &L, int type, const JointGeo &g, int la, int lb, int r0,
                                   const SolverParams &P) {
-    double Xa[3], Ya[3], Yb[3], Zb[3];
-    col(g.Ra, 0, Xa);
-    col(g.Ra, 1, Ya);
-    col(g.Rb, 1, Yb);
-    col(g.Rb, 2, Zb);
-    double arm_a[3], arm_b[3], d[3];
-    for (int k = 0; k < 3; ++k) {
-        arm_a[k] = g.pa[k] - g.ra[k];
-        arm_b[k] = g.pb[k] - g.rb[k];
-        d[k] = g.pa[k] - g.pb[k];
-    }
-    double Ja[6], Jb[6], c[3];
-    if (type == KAMX_REVOLUTE) {
-        for (int e = 0; e < 3; ++e) {
-            double ek[3] = {0.0, 0.0, 0.0};
-            ek[e] = 1.0;
-            cross(arm_a, ek, c);
-            for (int k = 0; k < 3; ++k) {
-                Ja[k] = ek[k];
-                Ja[3 + k] = c[k];
-            }
-            cross(arm_b, ek, c);
-            for (int k = 0; k < 3; ++k) {
-                Jb[k] = -ek[k];
-                Jb[3 + k] = -c[k];
-            }
-            put_row6(L, r0 + e, Ja, la, Jb, lb, d[e], kRowBilateral, P);
-        }
-        const double *T[2] = {Yb, Zb};
-        for (int e = 0; e < 2; ++e) {
-            cross(Xa, T[e], c);
-            for (int k = 0; k < 3; ++k) {
-                Ja[k] = 0.0;
-                Ja[3 + k] = c[k];
-                Jb[k] = 0.0;
-                Jb[3 + k] = -c[k];
-            }
-            put_row6(L, r0 + 3 + e, Ja, la, Jb, lb, dot3(Xa, T[e]), kRowBilateral, P);
-        }
-    } else {
-        double lever_b[3];
-        for (int k = 0; k < 3; ++k) lever_b[k] = g.pa[k] - g.rb[k];
-        const double *T[2] = {Yb, Zb};
-        for (int e = 0; e < 2; ++e) {
-            cross(arm_a, T[e], c);
-            for (int k = 0; k < 3; ++k) {
-                Ja[k] = T[e][k];
-                Ja[3 + k] = c[k];
-            }
-            cross(lever_b, T[e], c);
-            for (int k = 0; k < 3; ++k) {
-                Jb[k] = -T[e][k];
-                Jb[3 + k] = -c[k];
-            }
-            put_row6(L, r0 + e, Ja, la, Jb, lb, dot3(d, T[e]), kRowBilateral, P);
-        }
-        const double *U[3] = {Xa, Xa, Ya};
-        const double *V[3] = {Yb, Zb, Zb};
-        for (int e = 0; e < 3; ++e) {
-            cross(U[e], V[e], c);
-            for (int k = 0; k < 3; ++k) {
-                Ja[k] = 0.0;
-                Ja[3 + k] = c[k];
-                Jb[k] = 0.0;
-                Jb[3 + k] = -c[k];
-            }
-            put_row6(L, r0 + 2 + e, Ja, la, Jb, lb, dot3(U[e], V[e]), kRowBilateral, P);
-        }
-    }
+    joint_constraints(type, g, [&](int e, const double Ja[6], const double Jb[6], double f) {
+        put_row6(L, r0 + e, Ja, la, Jb, lb, f, kRowBilateral, P);
+    });
 }
 
 // ---------------------------------------------------------------------------
@@ -614,28 +430,31 @@ __device__ inline void body_minv64(const Lds &L, int b, double w[6]) {
 }
 
 // Row r of the product after a gather, given w_a, w_b = M^-1 g of its bodies.
+// (drive rows add their regularisation: D = J M^-1 J^T + R, Eq. 4, so row r
+// of D~ x gains p_r R_r p_r x_r)
 __device__ inline float delassus_row_w(const Lds &L, const float *vp, int r, const double wa[6], const double wbv[6],
-                                       bool has_b) {
+                                       bool has_b, float xr) {
     double a0 = 0.0, a1 = 0.0;
     for (int c = 0; c < 6; ++c) a0 += (double)L.rf(RJ + c, r) * wa[c];
     if (has_b)
         for (int c = 0; c < 6; ++c) a1 += (double)L.rf(RJ + 6 + c, r) * wbv[c];
-    return (float)((a0 + a1) * (double)vp[r]);
+    const double pr = (double)vp[r];
+    return (float)((a0 + a1 + (double)L.rf(RREG, r) * pr * (double)xr) * pr);
 }
 
-__device__ inline float delassus_row(const Lds &L, const float *vp, int r) {
+__device__ inline float delassus_row(const Lds &L, const float *vp, int r, float xr) {
     int ia = L.ri(RIA, r), ib = L.ri(RIB, r);
     double wa[6], wbv[6];
     body_minv64(L, ia, wa);
     if (ib >= 0) body_minv64(L, ib, wbv);
-    return delassus_row_w(L, vp, r, wa, wbv, ib >= 0);
+    return delassus_row_w(L, vp, r, wa, wbv, ib >= 0, xr);
 }
 
 // Full product out = D~ x (gather, then every row).  Ends with a barrier.
 template <int NT>
 __device__ inline void delassus_apply(const Lds &L, int m, int nb, const float *vp, const float *x, float *out) {
     delassus_gather<NT>(L, nb, vp, x);
-    for (int r = threadIdx.x; r < m; r += NT) out[r] = delassus_row(L, vp, r);
+    for (int r = threadIdx.x; r < m; r += NT) out[r] = delassus_row(L, vp, r, x[r]);
     __syncthreads();
 }
 
@@ -696,10 +515,17 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
         int gb = W.b0 + b;
         const float *qs = reset ? a.q0 : a.q;
         const float *us = reset ? a.u0 : a.u;
-        float q[7];
+        float q[7], u6[6];
         for (int k = 0; k < 7; ++k) q[k] = qs[7 * gb + k];
+        for (int k = 0; k < 6; ++k) u6[k] = us[6 * gb + k];
+        if (P.integrator == KAMX_MOREAU_JEAN) {
+            // rows, forces and contacts at the half-step configuration
+            float qm[7];
+            half_step_pose(q, u6, 0.5f * P.dt, qm);
+            for (int k = 0; k < 7; ++k) q[k] = qm[k];
+        }
         for (int k = 0; k < 7; ++k) L.bf(BQ + k, b) = q[k];
-        for (int k = 0; k < 6; ++k) L.bf(BU + k, b) = us[6 * gb + k];
+        for (int k = 0; k < 6; ++k) L.bf(BU + k, b) = u6[k];
         float R[9];
         rot_of_quat(q + 3, R);
         for (int k = 0; k < 9; ++k) L.bf(BR + k, b) = R[k];
@@ -724,7 +550,7 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
             for (int k = 0; k < 6; ++k) rate += Jb[k] * L.bf(BU + k, lb);
         float tau = a.ext_tau ? a.ext_tau[gj] : 0.f;
         float kp = jf[16], kd = jf[17], ref = jf[18];
-        if (kp != 0.f || kd != 0.f) tau += kp * (ref - c) - kd * rate;
+        if (!(fl & kJointDriven) && (kp != 0.f || kd != 0.f)) tau += kp * (ref - c) - kd * rate;
         if ((fl & kJointActuated) && P.torque_sigma != 0.f)
             tau += P.torque_sigma * noise_normal(P.seed_lo, P.seed_hi, (uint32_t)w, step, (uint32_t)j);
         L.jfld(JTAU, j) = tau;
@@ -745,7 +571,7 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
     // feature t of this world (same layout as kamx_model_features)
     auto feature = [&](int t) -> float {
         const int rb = W.reset_body;
-        const int rc0 = 5 * nj + W.nlim;
+        const int rc0 = 5 * nj + W.nlim + W.ndrv;
         const int S = rc0 + 3 * a.n_contact_slots;
         if (t < 13 * nb) {
             const int b = t / 13, c = t - 13 * (t / 13);
@@ -943,7 +769,8 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
     __syncthreads();
     const int nc = s_int[1];
     const int row_lim0 = 5 * nj;
-    const int row_c0 = 5 * nj + W.nlim;
+    const int row_drv0 = 5 * nj + W.nlim;
+    const int row_c0 = row_drv0 + W.ndrv;
     const int m = row_c0 + 3 * nc;
 
     // ---- constraint rows
@@ -972,6 +799,29 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
                 Jb[k] *= sg;
             }
             put_row(L, row_lim0 + rank, Ja, la, Jb, lb, gval, kRowLimit, 0.f, P);
+        }
+        if (fl & kJointDriven) {
+            // drive row (Sec. 3 implicit PD, armature, damping; Eq. 2 R, v*):
+            // along the coordinate c the impulse over the step is
+            // dt [kp (ref - c - h c'+) - (kd + d) c'+ - I_a (c'+ - c'-) / dt],
+            // i.e. J_c u+ + R lambda + v* = 0 with K = kp h + kd + d + I_a / dt,
+            // R = 1 / (dt K), v* = -(kp (ref - c) + I_a c'- / dt) / K
+            int rank = 0;
+            const int *tf = reinterpret_cast<const int *>(L.j) + JTF * kMaxJoints;
+            for (int k = 0; k < j; ++k) rank += (tf[k] >> 4) & kJointDriven ? 1 : 0;
+            float Ja[6], Jb[6];
+            const double c = joint_coord(type, g, Ja, Jb);
+            float rate = 0.f;
+            for (int k = 0; k < 6; ++k) rate += Ja[k] * L.bf(BU + k, la);
+            if (lb >= 0)
+                for (int k = 0; k < 6; ++k) rate += Jb[k] * L.bf(BU + k, lb);
+            const float h = P.integrator == KAMX_MOREAU_JEAN ? 0.5f * P.dt : P.dt;
+            const float kp = jf[16], kd = jf[17], ref = jf[18], damp = jf[19], arm = jf[20];
+            const float K = kp * h + kd + damp + arm / P.dt;
+            const int r = row_drv0 + rank;
+            put_row(L, r, Ja, la, Jb, lb, 0.f, kRowBilateral, 0.f, P);
+            L.rf(RBIAS, r) = -(float)((double)kp * ((double)ref - c) + (double)arm * (double)rate / (double)P.dt) / K;
+            L.rf(RREG, r) = 1.f / (P.dt * K);
         }
     }
     for (int c = tid; c < nc; c += NT) {
@@ -1066,7 +916,7 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
     float *tdiag = L.vec(VCOL), *tp = L.vec(VAUX);  // free fields above W
     const int kind_row = i < m ? L.ri(RKIND, i) : -1;
     if (i < m) {
-        float dsum = 0.f;
+        float dsum = L.rf(RREG, i);  // D_ii = J_i M^-1 J_i^T + R_ii
         for (int k = 0; k < 12; ++k) dsum += L.rf(RJ + k, i) * Wv[k * MC + i];
         tdiag[i] = dsum;
     }
@@ -1132,6 +982,7 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
                 for (int k = 0; k < 6; ++k) acc += L.rf(RJ + 6 + k, ri_) * Wv[k * MC + rj_];
             if (ib >= 0 && ib == jb)
                 for (int k = 0; k < 6; ++k) acc += L.rf(RJ + 6 + k, ri_) * Wv[(6 + k) * MC + rj_];
+            if (ri_ == rj_) acc += L.rf(RREG, ri_);  // drive rows: D = J M^-1 J^T + R
             acc *= tp[ri_] * tp[rj_];
             if (ri_ == rj_) {
                 const int kd = L.ri(RKIND, ri_);
@@ -1704,7 +1555,10 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
                     }
                 }
                 side = lane_group_sum<2>(side);
-                if (hh == 0 && io < m) vdx[io] = (float)(side * (double)vp[io]);
+                if (hh == 0 && io < m) {
+                    const double pr = (double)vp[io];
+                    vdx[io] = (float)((side + (double)L.rf(RREG, io) * pr * (double)vxn[io]) * pr);
+                }
             }
             __syncthreads();
             if (owner_o) {
@@ -1838,6 +1692,12 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
         if (i < m) lam = vp[i] * vyp[i];
         a.lambda[W.row_base + i] = lam;
         if (i < m) vaux[i] = lam;
+        if (a.iterate_out) {
+            // the returned iterate in preconditioned units and the scales
+            const bool act = i < m;
+            *reinterpret_cast<float4 *>(a.iterate_out + 4 * ((long)W.row_base + i)) =
+                make_float4(act ? vx[i] : 0.f, act ? vyp[i] : 0.f, act ? vzp[i] : 0.f, act ? vp[i] : 0.f);
+        }
     }
     if (tid == 0) {
         a.iters[w] = it;
@@ -1895,21 +1755,12 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
         }
         int gb = W.b0 + b;
         for (int k = 0; k < 6; ++k) a.u[6 * gb + k] = un[k];
-        float q[4], dq[4] = {0.f, 0.f, 0.f, 1.f}, qn[4];
-        for (int k = 0; k < 4; ++k) q[k] = L.bf(BQ + 3 + k, b);
-        for (int k = 0; k < 3; ++k) a.q[7 * gb + k] = L.bf(BQ + k, b) + P.dt * un[k];
-        float wn = sqrtf(un[3] * un[3] + un[4] * un[4] + un[5] * un[5]);
-        if (wn > 0.f) {
-            float half = 0.5f * P.dt * wn;
-            float sh = sinf(half) / wn;
-            dq[0] = un[3] * sh;
-            dq[1] = un[4] * sh;
-            dq[2] = un[5] * sh;
-            dq[3] = cosf(half);
-        }
-        qprod(dq, q, qn);
-        float nn = 1.f / sqrtf(qn[0] * qn[0] + qn[1] * qn[1] + qn[2] * qn[2] + qn[3] * qn[3]);
-        for (int k = 0; k < 4; ++k) a.q[7 * gb + 3 + k] = qn[k] * nn;
+        // poses over the rest of the step from the rows' configuration: dt
+        // (Euler) or dt / 2 from the half-step poses (Moreau-Jean)
+        float q[7], qn[7];
+        for (int k = 0; k < 7; ++k) q[k] = L.bf(BQ + k, b);
+        half_step_pose(q, un, P.integrator == KAMX_MOREAU_JEAN ? 0.5f * P.dt : P.dt, qn);
+        for (int k = 0; k < 7; ++k) a.q[7 * gb + k] = qn[k];
     }
     __syncthreads();
     if (a.phase_clk && tid == 0) a.phase_clk[16 * w + 7] = wall_clock64();
@@ -1937,18 +1788,18 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void st
     }
 }
 
-// Impulses of the last step in slot layout (joint and limit rows, then three
+// Impulses of the last step in slot layout (joint, limit and drive rows, then three
 // slots per contact key; slots of absent contacts are zero), one thread per
 // world and slot.
 __global__ void impulse_slots_kernel(const WorldInfo *worlds, int n_worlds, int n_contact_slots, const float *lambda,
                                      const int32_t *keys, const int32_t *ncontacts, float *out) {
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const WorldInfo W0 = worlds[0];
-    const int S = 5 * W0.nj + W0.nlim + 3 * n_contact_slots;
+    const int S = 5 * W0.nj + W0.nlim + W0.ndrv + 3 * n_contact_slots;
     if (idx >= (long)n_worlds * S) return;
     const int w = (int)(idx / S), t = (int)(idx - (long)w * S);
     const WorldInfo W = worlds[w];
-    const int rc0 = 5 * W.nj + W.nlim;
+    const int rc0 = 5 * W.nj + W.nlim + W.ndrv;
     float v = 0.f;
     if (t < rc0) {
         v = lambda[W.row_base + t];

@@ -22,6 +22,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 WORLD_OK, WORLD_MAXITER, WORLD_NONFINITE, WORLD_FACTOR_FAIL = 0, 1, 2, 4
 WARM_COLD, WARM_PREVIOUS, WARM_EXTERNAL, WARM_LEARNED = 0, 1, 2, 3
 SCHED_INDEX, SCHED_LPT, SCHED_CHAIN = 0, 1, 2
+EULER, MOREAU_JEAN = 0, 1
 MAX_CONTACTS_PER_WORLD = 64
 
 
@@ -32,6 +33,7 @@ class kamx_params(C.Structure):
         ("accel", C.c_int32), ("restart_factor", C.c_float), ("precond", C.c_int32), ("baumgarte", C.c_float),
         ("warmstart", C.c_int32), ("contact_margin", C.c_float), ("torque_sigma", C.c_float),
         ("seed", C.c_uint64), ("reset_height", C.c_float), ("log_restarts", C.c_int32),
+        ("integrator", C.c_int32),
     ]
 
 
@@ -44,6 +46,7 @@ class kamx_joint_desc(C.Structure):
         ("type", C.c_int32), ("world", C.c_int32), ("body_a", C.c_int32), ("body_b", C.c_int32),
         ("frame_a", C.c_float * 7), ("frame_b", C.c_float * 7), ("limit_lo", C.c_float), ("limit_hi", C.c_float),
         ("kp", C.c_float), ("kd", C.c_float), ("ref", C.c_float), ("actuated", C.c_int32),
+        ("damping", C.c_float), ("armature", C.c_float), ("implicit_drive", C.c_int32),
     ]
 
 
@@ -54,12 +57,13 @@ class kamx_probe_desc(C.Structure):
 BODY_DTYPE = np.dtype([("world", "<i4"), ("mass", "<f4"), ("inertia", "<f4", 3)])
 JOINT_DTYPE = np.dtype([("type", "<i4"), ("world", "<i4"), ("body_a", "<i4"), ("body_b", "<i4"),
                         ("frame_a", "<f4", 7), ("frame_b", "<f4", 7), ("limit_lo", "<f4"), ("limit_hi", "<f4"),
-                        ("kp", "<f4"), ("kd", "<f4"), ("ref", "<f4"), ("actuated", "<i4")])
+                        ("kp", "<f4"), ("kd", "<f4"), ("ref", "<f4"), ("actuated", "<i4"),
+                        ("damping", "<f4"), ("armature", "<f4"), ("implicit_drive", "<i4")])
 PROBE_DTYPE = np.dtype([("world", "<i4"), ("body", "<i4"), ("point", "<f4", 3), ("mu", "<f4")])
 CONTACT_DTYPE = np.dtype([("body_a", "<i4"), ("body_b", "<i4"), ("point", "<f4", 3), ("normal", "<f4", 3),
                           ("gap", "<f4"), ("mu", "<f4"), ("key", "<i4")])
 assert CONTACT_DTYPE.itemsize == 44 and BODY_DTYPE.itemsize == 20
-assert JOINT_DTYPE.itemsize == 96 and PROBE_DTYPE.itemsize == 24
+assert JOINT_DTYPE.itemsize == 108 and PROBE_DTYPE.itemsize == 24
 
 _lib = None
 
@@ -94,11 +98,14 @@ def lib():
         L.kamx_set_bucket_threads.argtypes = [vp, i32, i32]
         L.kamx_autotune.argtypes = [vp, i32, C.POINTER(C.c_float)]
         L.kamx_set_iteration_log.argtypes = [vp, vp, vp, i32]
+        L.kamx_set_iterate_log.argtypes = [vp, vp]
+        L.kamx_forward_kinematics.argtypes = [vp, vp, i32, C.c_float, vp, vp, vp]
         L.kamx_mlp_create.argtypes = [i32, i32, i32, i32, C.c_uint64, C.POINTER(vp)]
         L.kamx_mlp_destroy.argtypes = [vp]
         L.kamx_mlp_info.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), i64p]
         L.kamx_mlp_set_normalization.argtypes = [vp, vp, vp, vp, vp, vp]
         L.kamx_mlp_forward.argtypes = [vp, vp, i32, vp, vp]
+        L.kamx_mlp_forward_noalloc.argtypes = [vp, vp, i32, vp, vp]
         L.kamx_mlp_train_step.argtypes = [vp, vp, vp, i32, C.c_float, vp, vp]
         L.kamx_mlp_weights.argtypes = [vp, vp, i32, vp]
         L.kamx_mlp_gradients.argtypes = [vp, vp, vp]
@@ -119,10 +126,11 @@ def lib():
                      "kamx_set_warmstart", "kamx_step", "kamx_read_impulses", "kamx_read_stats",
                      "kamx_read_restart_log", "kamx_read_torques", "kamx_read_contacts", "kamx_reset_count",
                      "kamx_read_phase_clock", "kamx_set_schedule", "kamx_mlp_create", "kamx_mlp_destroy",
-                     "kamx_mlp_info", "kamx_mlp_set_normalization", "kamx_mlp_forward", "kamx_mlp_train_step",
+                     "kamx_mlp_info", "kamx_mlp_set_normalization", "kamx_mlp_forward", "kamx_mlp_forward_noalloc",
+                     "kamx_mlp_train_step",
                      "kamx_mlp_weights", "kamx_mlp_gradients", "kamx_model_feature_dims", "kamx_model_features",
                      "kamx_read_impulse_slots", "kamx_model_attach_mlp", "kamx_contacts_box_bin",
-                     "kamx_set_iteration_log"):
+                     "kamx_set_iteration_log", "kamx_set_iterate_log", "kamx_forward_kinematics"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -231,6 +239,17 @@ class Model:
                 joints["kd"][:nj][on] = scene.joint_pd[on, 1]
             if refs is not None:
                 joints["ref"][:nj][on] = np.asarray(refs, np.float32)[on]
+            # implicit drives (kp, kd, damping, armature, ref): a drive row
+            # replaces the explicit PD of those joints
+            drv = getattr(scene, "joint_drive", None)
+            if drv is not None and drv.shape[0] == nj:
+                dj = np.any(drv[:, :4] != 0.0, axis=1)
+                joints["implicit_drive"][:nj] = dj.astype(np.int32)
+                joints["kp"][:nj][dj] = drv[dj, 0]
+                joints["kd"][:nj][dj] = drv[dj, 1]
+                joints["damping"][:nj][dj] = drv[dj, 2]
+                joints["armature"][:nj][dj] = drv[dj, 3]
+                joints["ref"][:nj][dj] = drv[dj, 4]
         probes = np.zeros(max(np_, 1), PROBE_DTYPE)
         if np_:
             probes["world"][:np_] = scene.probe_world
@@ -375,6 +394,31 @@ class Model:
                 assert t is None or (t.dtype == torch.int32 and t.is_contiguous() and t.shape[1] == self.n_worlds)
             _check(lib().kamx_set_iteration_log(self.handle, _ptr(iters), _ptr(rows), int(iters.shape[0])))
         self._iter_log = (iters, rows)
+
+    def forward_kinematics(self, targets, max_iters=50, tol=1e-9, stream=None):
+        """Poses consistent with every joint and with the target joint
+        coordinates ([n_joints], NaN = free), reset bodies held; twists set to
+        zero.  Returns device tensors (iterations, |F|_inf) per world."""
+        t = torch.as_tensor(np.asarray(targets, np.float32) if not torch.is_tensor(targets) else targets,
+                            dtype=torch.float32, device=self.device).contiguous()
+        it = torch.zeros(self.n_worlds, dtype=torch.int32, device=self.device)
+        res = torch.zeros(self.n_worlds, dtype=torch.float32, device=self.device)
+        _check(lib().kamx_forward_kinematics(self.handle, _ptr(t), int(max_iters), float(tol), _ptr(it), _ptr(res),
+                                             _stream(stream)))
+        self._fk_targets = t
+        return it, res
+
+    def set_iterate_log(self, on=True):
+        """Record the last step's final iterate (x~, y~, z~, p) per row
+        into a device tensor [rows_capacity, 4] (returned); on=False stops."""
+        if not on:
+            _check(lib().kamx_set_iterate_log(self.handle, None))
+            self._iterate = None
+            return None
+        t = torch.zeros((max(self.rows_capacity, 1), 4), dtype=torch.float32, device=self.device)
+        _check(lib().kamx_set_iterate_log(self.handle, _ptr(t)))
+        self._iterate = t
+        return t
 
     def set_schedule(self, mode):
         """Mapping of steps onto workgroups: SCHED_CHAIN (default), SCHED_LPT
@@ -530,6 +574,14 @@ class MLP:
         y = out if out is not None else torch.empty((b, self.n_out), dtype=torch.float32, device=self.device)
         _check(lib().kamx_mlp_forward(self.handle, _ptr(x), b, _ptr(y), _stream(stream)))
         return y
+
+    def forward_noalloc(self, x, out, stream=None):
+        """The same prediction as forward(), with the activations in the
+        library's fixed per-GPU workspace (no device allocation inside);
+        ``x`` and ``out`` must be contiguous FP32 device tensors."""
+        assert x.dtype == torch.float32 and out.dtype == torch.float32 and x.is_contiguous() and out.is_contiguous()
+        _check(lib().kamx_mlp_forward_noalloc(self.handle, _ptr(x), x.shape[0], _ptr(out), _stream(stream)))
+        return out
 
     def train_step(self, x, y, lr, loss=None, stream=None):
         """One Adam step; ``loss`` (a one-element device tensor) receives the

@@ -610,14 +610,16 @@ BIPED_FOOT = (0.20, 0.10, 0.04)
 BIPED_PD = (15.0, 0.6)  # N m / rad, N m s / rad: the DR Legs gains of the paper's RL setup (Sec. 6.3)
 
 
-def biped_world(rng, dt=2e-3, mu=None, link_masses=None):
+def biped_world(rng, dt=2e-3, mu=None, link_masses=None, sole_probes=4):
     """A 31-body biped: pelvis + 2 legs x (hip-yaw, hip-roll, thigh, shin,
     foot) + 2 legs x 5 crank-rod parallelogram transmissions (2 bodies and 3
     revolute joints each).  40 revolute joints (200 bilateral rows), four
     sole probe points per foot (8 contacts, 24 rows).  Stands on z = 0 with
     straight legs at rest; exactly on the constraint manifold.  The ten chain
     joints (hip yaw, roll, pitch, knee, ankle of each leg) are actuated; the
-    3-30 g transmission links are passive."""
+    3-30 g transmission links are passive.  sole_probes = 2 keeps only the
+    heel and toe of each sole's centre line (12 contact rows instead of 24,
+    which leaves room in the 224-row bucket for ten drive rows)."""
     if mu is None:
         mu = rng.uniform(0.5, 1.0)
     if link_masses is None:
@@ -649,7 +651,7 @@ def biped_world(rng, dt=2e-3, mu=None, link_masses=None):
         foot = B.body(0.6, box_inertia(0.6, fx, fy, fz), fc, ident)
         B.joint(REVOLUTE, foot, shin, An, ya, actuated=1, pd=BIPED_PD)
         for ix in (-1, 1):
-            for iy in (-1, 1):
+            for iy in ((-1, 1) if sole_probes == 4 else (0,)):
                 B.probe(foot, (0.5 * fx * ix, 0.5 * fy * iy, -0.5 * fz), mu)
         # parallelogram transmissions: (parent, child, joint point, delta, crank)
         loops = [
@@ -673,17 +675,60 @@ def biped_world(rng, dt=2e-3, mu=None, link_masses=None):
     return B.scene(dt, reset_body=pelvis)
 
 
-def biped_batch(n_worlds, seed=1002, dt=2e-3):
+BIPED_ARMATURE = 5e-4  # kg m^2: reflected rotor inertia of a transmission drive
+
+
+def with_drives(scene, mode="implicit", pd=BIPED_PD, armature=BIPED_ARMATURE, damping=0.01):
+    """The biped with joint drives as regularised rows (Sec. 3 implicit PD,
+    armature and viscous damping) instead of explicit PD:
+
+    * "implicit": the ten actuated chain joints keep their gains, solved as
+      implicit PD rows toward the assembled pose;
+    * "transmission": the hip yaw and roll joints keep their explicit PD,
+      the hip pitch, knee and ankle chain joints are passive, and the ten
+      crank joints of the parallelogram transmissions are actuated instead
+      (implicit PD, rotor armature and damping; noise acts on them), as the
+      paper's DR Legs drives its legs through the linkages (Sec. 6.1).
+
+    Either adds ten drive rows: with the 200 joint rows the scene must come
+    from biped_batch(..., sole_probes=2) to fit the 224-row bucket."""
+    s = scene.replace(joint_drive=np.zeros((scene.n_joints, 5)), joint_actuated=scene.joint_actuated.copy(),
+                      joint_pd=scene.joint_pd.copy())
+    jo = scene.joint_offsets()
+    for w in range(scene.n_worlds):
+        js = range(jo[w], jo[w + 1])
+        chain = [j for j in js if scene.joint_actuated[j]]
+        if mode == "implicit":
+            for j in chain:
+                s.joint_drive[j] = (pd[0], pd[1], 0.0, 0.0, 0.0)
+                s.joint_pd[j] = (0.0, 0.0)
+            continue
+        # per leg: 5 chain joints then 5 loops of 3 joints (crank, rod-crank, rod-child)
+        local = [j - jo[w] for j in js]
+        for leg in range(2):
+            base = 20 * leg
+            for k in (2, 3, 4):  # hip pitch, knee, ankle: driven through the linkages
+                s.joint_actuated[jo[w] + base + k] = 0
+                s.joint_pd[jo[w] + base + k] = (0.0, 0.0)
+            for li in range(5):
+                crank = jo[w] + base + 5 + 3 * li
+                s.joint_actuated[crank] = 1
+                s.joint_drive[crank] = (pd[0], pd[1], damping, armature, 0.0)
+        assert len(local) == 40
+    return s
+
+
+def biped_batch(n_worlds, seed=1002, dt=2e-3, sole_probes=4):
     """``n_worlds`` identical bipeds (transmission masses drawn once from
     the seed) with a per-world friction coefficient mu ~ U[0.5, 1.0]."""
     rng = np.random.default_rng(seed)
     link_masses = rng.uniform(0.003, 0.030, 20)
     mus = rng.uniform(0.5, 1.0, n_worlds)
-    one = biped_world(rng, dt, mu=0.75, link_masses=link_masses)
+    one = biped_world(rng, dt, mu=0.75, link_masses=link_masses, sole_probes=sole_probes)
     s = concat([one] * n_worlds, reset_height=0.2)
     # per-world friction
-    s.probe_mu = np.repeat(mus, 8)
-    s.contact_mu = np.repeat(mus, 8)
+    s.probe_mu = np.repeat(mus, 2 * sole_probes)
+    s.contact_mu = np.repeat(mus, 2 * sole_probes)
     return s
 
 

@@ -11,11 +11,12 @@ from paper_2603_16536_amd import kamx, scenes
 def oracle_params(p: "kamx.kamx_params", **over):
     P = oracle.Params(dt=p.dt, gravity=tuple(p.gravity), eta=p.eta, rho_bil=p.rho_bilateral, rho_c=p.rho_contact,
                       eps=p.eps, max_iters=p.max_iters, fixed_iters=p.fixed_iters, accel=p.accel,
-                      restart_factor=p.restart_factor, precond=p.precond, baumgarte=p.baumgarte)
+                      restart_factor=p.restart_factor, precond=p.precond, baumgarte=p.baumgarte,
+                      integrator=p.integrator)
     return P.replace(**over)
 
 
-def gpu_step(scene, params, explicit_contacts=True, ext=None, max_contacts=None, warm=None):
+def gpu_step(scene, params, explicit_contacts=True, ext=None, max_contacts=None, warm=None, setup=None):
     """One step of every world on the GPU.  Returns numpy outputs, the
     contacts the library used (for checking its own contact generation) and
     the inputs the oracle needs to rebuild the step on its side."""
@@ -30,6 +31,9 @@ def gpu_step(scene, params, explicit_contacts=True, ext=None, max_contacts=None,
         model.set_external(ext)
     if warm is not None:
         model.set_warmstart(warm)
+    if setup is not None:
+        setup(model)  # e.g. earlier steps that fill the previous-step cache, or a network
+    it_log = model.set_iterate_log()
     model.step(1)
     torch.cuda.synchronize()
     q, u = (t.cpu().numpy().astype(np.float64) for t in model.state())
@@ -38,6 +42,7 @@ def gpu_step(scene, params, explicit_contacts=True, ext=None, max_contacts=None,
                torques=model.torques().cpu().numpy().astype(np.float64), **st)
     if model.params.log_restarts:
         out["restart_log"] = model.restart_log().cpu().numpy()
+    out["iterate"] = it_log.cpu().numpy().astype(np.float64)
     raw, cnt = model.contacts()
     out["used_scene"] = kamx.contacts_to_scene(scene, raw, cnt)
     out["inputs"] = dict(ext=None if ext is None else np.asarray(ext, np.float64), explicit=explicit_contacts,
@@ -48,10 +53,16 @@ def gpu_step(scene, params, explicit_contacts=True, ext=None, max_contacts=None,
 
 def oracle_torques(scene, params, w, ext=None, step=0, pd=None, refs=None):
     """Generalized joint forces of world w computed on the oracle side: the
-    external forces, PD toward refs (per-joint gains of the scene unless pd
-    is given) on the actuated joints, and sigma N(0, 1) noise from the
-    Philox4x32-10 / Box-Muller definition keyed by (seed; world, step, joint
-    slot)."""
+    external forces, explicit PD toward refs (per-joint gains of the scene
+    unless pd is given) on the actuated joints without an implicit drive,
+    evaluated at the configuration the step builds its rows at (the
+    half-step poses of the Moreau-Jean variant), and sigma N(0, 1) noise
+    from the Philox4x32-10 / Box-Muller definition keyed by (seed; world,
+    step, joint slot)."""
+    q_rows = oracle.step_configuration(scene, oracle_params(params))
+    drv = getattr(scene, "joint_drive", None)
+    driven = np.any(drv[:, :4] != 0.0, axis=1) if drv is not None and drv.shape[0] == scene.n_joints else \
+        np.zeros(scene.n_joints, bool)
     jo = scene.joint_offsets()
     j0, j1 = jo[w], jo[w + 1]
     tau = np.zeros(j1 - j0)
@@ -63,8 +74,8 @@ def oracle_torques(scene, params, w, ext=None, step=0, pd=None, refs=None):
         if not scene.joint_actuated[j]:
             continue
         kp, kd = (float(pd[0]), float(pd[1])) if pd is not None else (gains[j, 0], gains[j, 1])
-        if kp != 0.0 or kd != 0.0:
-            c, Ja, Jb = oracle.joint_coordinate(scene, scene.q, j)
+        if (kp != 0.0 or kd != 0.0) and not driven[j]:
+            c, Ja, Jb = oracle.joint_coordinate(scene, q_rows, j)
             a, b = scene.joint_body[j]
             rate = Ja @ scene.u[a] + (Jb @ scene.u[b] if b >= 0 else 0.0)
             ref = 0.0 if refs is None else float(np.float32(refs[j]))
@@ -186,3 +197,190 @@ def biped_refs(scene):
     for j in range(scene.n_joints):
         refs[j] = oracle.joint_coordinate(scene, scene.q, j)[0]
     return refs
+
+
+REFERENCE = dict(eps=1e-12, max_iters=100000, fixed_iters=0)
+
+
+def oracle_inputs(scene, params, g, worlds, inputs=None):
+    """The sub-scene of ``worlds`` with the contacts the oracle generates
+    itself from the pre-step state (checked key for key against the ones
+    the GPU used), and the joint forces computed oracle-side."""
+    import oracle.contacts as OC
+    inp = dict(g.get("inputs") or {})
+    inp.update(inputs or {})
+    sw = scene.subset(list(worlds))
+    qr = oracle.step_configuration(sw, oracle_params(params))  # contacts at the rows' configuration
+    if inp.get("box_bin") is not None:
+        wx, wy, margin, cap = inp["box_bin"]
+        sub = OC.box_bin_contacts(sw, qr, wx, wy, margin, cap)
+    elif inp.get("explicit", True):
+        sub = sw
+    else:
+        sub = OC.probe_contacts(sw, qr, float(params.contact_margin))
+    gsub = g["used_scene"].subset(list(worlds))
+    so, go = sub.contact_offsets(), gsub.contact_offsets()
+    perms = []
+    for k in range(len(worlds)):
+        kk = sub.contact_key[so[k]:so[k + 1]]
+        gk = gsub.contact_key[go[k]:go[k + 1]]
+        assert np.array_equal(np.sort(gk), np.sort(kk)), f"contact sets differ in world {worlds[k]}"
+        g_of_key = {int(x): i for i, x in enumerate(gk)}
+        perms.append([g_of_key[int(x)] for x in kk])
+    tau = np.concatenate([oracle_torques(scene, params, int(w), ext=inp.get("ext"), step=inp.get("step", 0),
+                                         pd=inp.get("pd"), refs=inp.get("refs")) for w in worlds] or [np.zeros(0)])
+    return sub, perms, tau
+
+
+def fp64_residuals_at_iterate(S, it, kind, mu):
+    """r_p, r_d, r_c (Alg. 1 step 9, in preconditioned units) evaluated in
+    FP64 at the GPU's returned iterate (x~, y~, z~) with the GPU's scales p
+    and the oracle's D and v_f."""
+    x, y, z, p = it[:, 0], it[:, 1], it[:, 2], it[:, 3]
+    D, vf = S["D"], S["vf"]
+    v = p * (D @ (p * x)) + p * vf
+    m = len(x)
+    g = np.zeros(m)
+    for i in range(m):
+        if kind[i] == oracle.ROW_NORMAL:
+            g[i] = mu[i] * np.hypot(v[i + 1], v[i + 2])
+    rp = np.abs(x - y).max() if m else 0.0
+    rd = np.abs(v + g - z).max() if m else 0.0
+    rc = 0.0
+    i = 0
+    while i < m:
+        if kind[i] == oracle.ROW_NORMAL:
+            rc = max(rc, abs(y[i] * (v[i] + g[i]) + y[i + 1] * v[i + 1] + y[i + 2] * v[i + 2]))
+            i += 3
+        elif kind[i] == oracle.ROW_LIMIT:
+            rc = max(rc, abs(y[i] * v[i]))
+            i += 1
+        else:
+            i += 1
+    return np.array([rp, rd, rc])
+
+
+def compare_worlds(scene, params, g, worlds, mode="reference", oracle_over=None, warm=None, inputs=None,
+                   log_iters=None):
+    """Run the oracle on ``worlds`` (one OpenMP call) and compare each world
+    with the GPU step in ``g``.
+
+    mode "replay": the oracle runs the GPU's iteration count with the GPU's
+    restart decisions (both paths take the same branches).
+    mode "reference": the oracle runs its own PADMM from the same
+    initialisation (its own restart decisions) to 1e-12, cap 1e5 iterations;
+    mode "same": its own decisions at the GPU's tolerance and cap.
+
+    Per world: relative errors of u+, J^T lambda per body, lambda and the
+    momentum-weighted u+ (c.2 item 15 normalisation), the FP64 NCP residual
+    of the GPU impulses, the GPU's reported residuals next to their FP64
+    values at its returned iterate, and (when the GPU logged them) the
+    first iteration at which its restart decisions differ from the oracle's
+    own (0: never within the shorter run)."""
+    worlds = [int(w) for w in worlds]
+    sub, perms, tau = oracle_inputs(scene, params, g, worlds, inputs)
+    over = dict(oracle_over or {})
+    if mode == "reference":
+        over = {**REFERENCE, **over}
+    replay_log = None
+    if mode == "replay":
+        iters = [max(int(g["iters"][w]), 1) for w in worlds]
+        # one call per distinct iteration count (the fixed count is a parameter)
+        groups = {}
+        for k, n in enumerate(iters):
+            groups.setdefault(n, []).append(k)
+    else:
+        groups = {None: list(range(len(worlds)))}
+    ws_sub = None
+    if warm is not None:
+        ro = g["row_offsets"]
+        ws_sub = np.concatenate([np.asarray(warm, np.float64)[ro[w]:ro[w + 1]] for w in worlds])
+    results = [None] * len(worlds)
+    for n, ks in groups.items():
+        o = dict(over)
+        if n is not None:
+            o["fixed_iters"] = n
+        P = oracle_params(params, **o)
+        s2 = sub.subset(ks)
+        ws2 = None
+        if ws_sub is not None:
+            so = oracle.row_offsets(sub)
+            ws2 = np.concatenate([ws_sub[so[k]:so[k + 1]] for k in ks])
+        kw = {}
+        if n is not None and "restart_log" in g:
+            kw["replay_log"] = np.stack([g["restart_log"][worlds[k], :n] for k in ks])
+        elif n is None and log_iters:
+            kw["log_iters"] = int(log_iters)
+        jo = sub.joint_offsets()
+        tau2 = np.concatenate([tau[jo[k]:jo[k + 1]] for k in ks] or [np.zeros(0)])
+        ref = oracle.step(s2, P, joint_torque=tau2, lambda_ws=ws2, **kw)
+        bo2, ro2 = s2.body_offsets(), ref["row_offset"]
+        for j, k in enumerate(ks):
+            results[k] = dict(u=ref["u"][bo2[j]:bo2[j + 1]], lam=ref["lam"][ro2[j]:ro2[j + 1]],
+                              iters=int(ref["iters"][j]), status=int(ref["status"][j]), resid=ref["resid"][j],
+                              restart_log=ref["restart_log"][j] if "restart_log" in ref else None)
+    out = []
+    jo = sub.joint_offsets()
+    for k, w in enumerate(worlds):
+        ref = results[k]
+        tw = tau[jo[k]:jo[k + 1]]
+        S = oracle.world_system(sub.subset([k]), oracle_params(params), 0, joint_torque=tw)
+        m = S["J"].shape[0]
+        r0 = int(g["row_offsets"][w])
+        lam_raw = g["lam"][r0:r0 + m]
+        assert np.all(g["lam"][r0 + m:int(g["row_offsets"][w + 1])] == 0.0)
+        rc0 = m - 3 * len(perms[k])
+        rowperm = np.arange(m)
+        for i, gi in enumerate(perms[k]):
+            rowperm[rc0 + 3 * i:rc0 + 3 * i + 3] = np.arange(rc0 + 3 * gi, rc0 + 3 * gi + 3)
+        lam_g = lam_raw[rowperm]
+        b0, b1 = scene.body_offsets()[w], scene.body_offsets()[w + 1]
+        floor_imp = 1e-6 * world_mass(scene)[w] * 9.81 * params.dt
+        floor_vel = 1e-6 * 9.81 * params.dt
+        u_g = g["u"][b0:b1].reshape(-1)
+        u_o = ref["u"].reshape(-1)
+        imp_g = S["J"].T @ lam_g
+        imp_o = S["J"].T @ ref["lam"]
+        du = (g["u"][b0:b1] - ref["u"]).reshape(-1, 6)
+        mom = np.zeros_like(du)
+        for j, b in enumerate(range(b0, b1)):
+            R = scenes.quat_to_mat(scene.q[b, 3:])
+            mom[j, :3] = scene.body_mass[b] * du[j, :3]
+            mom[j, 3:] = R @ (scene.body_inertia[b] * (R.T @ du[j, 3:]))
+        D, vf, kind, mu = S["D"], S["vf"], S["kind"], S["mu"]
+        p = oracle.preconditioner(D, kind, params.precond)
+        res = dict(
+            world=w, m=m, iters=int(g["iters"][w]), status=int(g["status"][w]), ref_iters=ref["iters"],
+            ref_status=ref["status"], ref_resid=ref["resid"],
+            e_u=np.abs(u_g - u_o).max() / max(np.abs(u_o).max(), floor_vel),
+            e_mom=np.abs(mom).max() / max(np.abs(imp_o).max(), floor_imp),
+            e_imp=np.abs(imp_g - imp_o).max() / max(np.abs(imp_o).max(), floor_imp),
+            e_lam=np.abs(lam_g - ref["lam"]).max() / max(np.abs(ref["lam"]).max(), floor_imp),
+            r_ncp=ncp_natural_residual(lam_g / p, p * (D @ lam_g + vf), kind, mu),
+            gpu_resid=np.asarray(g["resid"][w], np.float64), lam_g=lam_g, ref=ref, S=S)
+        if "iterate" in g:
+            it = g["iterate"][r0:r0 + m][rowperm]
+            res["fp64_resid"] = fp64_residuals_at_iterate(S, it, kind, mu)
+        if mode != "replay" and ref.get("restart_log") is not None and "restart_log" in g:
+            n = min(res["iters"], ref["iters"], len(ref["restart_log"]))
+            a, b = g["restart_log"][w, :n], ref["restart_log"][:n]
+            diff = np.nonzero(a != b)[0]
+            res["restart_first_diff"] = int(diff[0]) + 1 if diff.size else 0
+            res["restart_compared"] = n
+        out.append(res)
+    return out
+
+
+def summary(name, rs):
+    e = np.array([[r["e_u"], r["e_imp"], r["e_lam"], r["e_mom"], r["r_ncp"]] for r in rs])
+    line = (f"\n{name}: max rel err u+ {e[:, 0].max():.2e}  J^T lambda {e[:, 1].max():.2e}  lambda {e[:, 2].max():.2e}"
+            f"  momentum-weighted u+ {e[:, 3].max():.2e}  FP64 r_ncp of GPU lambda {e[:, 4].max():.2e}")
+    if all("fp64_resid" in r for r in rs):
+        gr = np.array([r["gpu_resid"][:3] for r in rs])
+        fr = np.array([r["fp64_resid"] for r in rs])
+        line += f"\n  GPU residuals max {gr.max(0)}  FP64 at the GPU iterate max {fr.max(0)}  max |diff| {np.abs(gr - fr).max(0)}"
+    if any("restart_first_diff" in r for r in rs):
+        line += "\n  first restart disagreement (iteration, 0 = none) " + str(
+            [(r["restart_first_diff"], r["restart_compared"]) for r in rs if "restart_first_diff" in r])
+    print(line, flush=True)
+    return e

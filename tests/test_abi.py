@@ -36,10 +36,10 @@ def test_every_declared_symbol_is_exported(libkamx):
 def test_struct_sizes_match_the_header_layout():
     from paper_2603_16536_amd import kamx
     assert C.sizeof(kamx.kamx_body_desc) == 20
-    assert C.sizeof(kamx.kamx_joint_desc) == 96
+    assert C.sizeof(kamx.kamx_joint_desc) == 108
     assert C.sizeof(kamx.kamx_probe_desc) == 24
     assert kamx.CONTACT_DTYPE.itemsize == 44
-    assert C.sizeof(kamx.kamx_params) == 88
+    assert C.sizeof(kamx.kamx_params) == 96
 
 
 def test_defaults_and_host_side_validation(libkamx):

@@ -76,13 +76,19 @@ def test_forward_matches_reference(n_in, n_hidden, n_out, batch):
     d.close()
 
 
-def test_gradients_loss_and_adam_match_reference():
+@pytest.mark.parametrize("n_in,n_hidden,n_out,batch,cap", [(100, 128, 50, 70, 128), (667, 256, 224, 4096, 4096),
+                                                       (667, 256, 224, 1024, 4032)])
+def test_gradients_loss_and_adam_match_reference(n_in, n_hidden, n_out, batch, cap):
+    """Loss, the six gradients and the first Adam step.  The biped network
+    at batch 4096 sums its weight gradients over the batch in several
+    slices (split over the batch, slices added in order); batch 1024 under
+    a capacity of 4032 (not a power of two) takes more slices than the
+    capacity itself, which the workspace must hold."""
     rng = np.random.default_rng(7)
-    net = random_net(rng, 100, 128, 50)
-    batch = 70
-    d = device_net(net, 128)
+    net = random_net(rng, n_in, n_hidden, n_out)
+    d = device_net(net, cap)
     x = rng.normal(0, 2, (batch, net.n_in)).astype(np.float32)
-    t = (net.mu_out[:50] + net.sigma_out[:50] * rng.normal(0, 1, (batch, 50))).astype(np.float32)
+    t = (net.mu_out[:n_out] + net.sigma_out[:n_out] * rng.normal(0, 1, (batch, n_out))).astype(np.float32)
     loss_dev = torch.zeros(1, dtype=torch.float32, device="cuda")
     w0 = d.weights().cpu().numpy()
     lr = 1e-3

@@ -1,0 +1,263 @@
+"""GPU parity without replay: the HIP step (through the C ABI) against the
+FP64 oracle running its own PADMM (its own restart decisions, Alg. 1 step
+8) from the same initialisation to 1e-12 (cap 1e5 iterations), on the same
+FP32-rounded single-step states.
+
+Per world this checks what the parity contract fixes for converged states:
+* the unique quantities, u+ and the net constraint impulse J^T lambda per
+  body, within 1e-4 relative (normalised by the world's largest value with a
+  floor of 1e-6 m g dt);
+* lambda itself where D~ is nonsingular (lambda is unique there);
+* the FP64 natural-map NCP residual (Eq. 3) of the GPU impulses;
+* the residuals the GPU reports (Alg. 1 step 9), recomputed in FP64 at the
+  iterate it returns, so that an exit on a wrongly small residual shows;
+* its restart decisions against the oracle's own, up to the first
+  iteration at which the FP32 and FP64 paths part.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2603_16536_amd import kamx, scenes  # noqa: E402
+
+from parity_util import biped_refs, compare_worlds, gpu_step, summary  # noqa: E402
+
+TOL = 1e-4
+
+
+def cfg2_params(**over):
+    p = dict(dt=2e-3, eta=1e-4, rho_bilateral=1e-4, rho_contact=0.3, eps=1e-6, max_iters=2000, log_restarts=1)
+    p.update(over)
+    return p
+
+
+def biped_state(n_worlds, seed, v_scale=0.2, w_scale=1.0):
+    scene = scenes.round_to_f32(scenes.biped_batch(n_worlds, seed=1002))
+    rng = np.random.default_rng(seed)
+    scene = scenes.perturb_state(scene, rng, v_scale, w_scale)
+    scene.u = scene.u.astype(np.float32).astype(np.float64)
+    tau = np.zeros(scene.n_joints)
+    act = scene.joint_actuated.astype(bool)
+    tau[act] = rng.normal(0.0, 5.0, act.sum())
+    return scene, tau.astype(np.float32)
+
+
+def check_reported_residuals(rs, eps):
+    """The GPU's reported r_p, r_d, r_c agree with their FP64 values at the
+    iterate it returned, and a world the GPU calls converged has FP64
+    residuals within a small factor of the tolerance."""
+    for r in rs:
+        g, f = r["gpu_resid"][:3], r["fp64_resid"]
+        assert np.all(np.abs(g - f) <= 0.5 * eps + 1e-3 * np.abs(f)), (r["world"], g, f)
+        if r["status"] == kamx.WORLD_OK:
+            assert np.all(f < 1.5 * eps), (r["world"], f)
+
+
+def test_biped_4096_unreplayed_sample_with_capped_worlds():
+    """The benchmark's batch shape: 4096 perturbed bipeds in one call; 56
+    random worlds plus up to 8 that hit the iteration cap, each against the
+    oracle's own converged solve."""
+    scene, tau = biped_state(4096, seed=7)
+    g = gpu_step(scene, cfg2_params(), ext=tau)
+    params = kamx.make_params(**cfg2_params())
+    rng = np.random.default_rng(0)
+    capped = np.nonzero(g["status"] == kamx.WORLD_MAXITER)[0]
+    pick = list(rng.choice(capped, size=min(8, capped.size), replace=False)) if capped.size else []
+    rest = np.setdiff1d(np.arange(4096), pick)
+    worlds = np.sort(np.r_[np.array(pick, int), rng.choice(rest, size=64 - len(pick), replace=False)])
+    rs = compare_worlds(scene, params, g, worlds, mode="reference", log_iters=2000)
+    e = summary(f"biped 4096 (sample {len(worlds)}, {len(pick)} capped; GPU converged "
+                f"{np.mean(g['status'] == 0):.4f})", rs)
+    conv = np.array([r["status"] == kamx.WORLD_OK for r in rs])
+    for r in rs:
+        print(f"  world {r['world']}: iters {r['iters']} status {r['status']} ref iters {r['ref_iters']} "
+              f"ref r {r['ref_resid'][:3].max():.1e} e_u {r['e_u']:.1e} e_imp {r['e_imp']:.1e} "
+              f"e_mom {r['e_mom']:.1e} r_ncp {r['r_ncp']:.1e} restart diff {r.get('restart_first_diff')}",
+              flush=True)
+    assert e[conv, 1].max() < TOL
+    assert e[conv, 3].max() < TOL
+    assert e[conv, 4].max() < 1e-5
+    check_reported_residuals(rs, 1e-6)
+
+
+def test_fourbar_fixed_iterations_restart_decisions():
+    """Four-bar + box, exactly 50 iterations: the GPU's restart decisions
+    agree with the oracle's own over the leading iterations; the converged
+    reference is then compared on the unique quantities (the 50-iteration
+    iterate is within the method's own distance from it)."""
+    scene = scenes.round_to_f32(scenes.fourbar_batch(64, seed=1001))
+    p = dict(dt=1e-3, eta=1e-4, rho_bilateral=1e-6, rho_contact=1.0, fixed_iters=50, max_iters=50, log_restarts=1)
+    g = gpu_step(scene, p)
+    params = kamx.make_params(**p)
+    rs = compare_worlds(scene, params, g, range(64), mode="same", log_iters=50)
+    summary("four-bar + box, 64 worlds, own restart decisions at 50 iterations", rs)
+    first = np.array([r["restart_first_diff"] for r in rs])
+    agree = np.mean(first == 0)
+    print(f"worlds whose 50 restart decisions all agree: {agree:.3f}; first disagreements {sorted(first[first > 0])}")
+    assert agree >= 0.9
+    assert np.all((first == 0) | (first > 10))
+
+
+def test_unique_impulses_on_nonsingular_worlds():
+    """Where D~ is nonsingular the impulses themselves are unique: a free box
+    touching the ground at two points (6 rows on 6 degrees of freedom) and
+    a limited three-link chain (a tree: 15 joint rows and its limit rows are
+    independent).  lambda within 1e-4 of the oracle's converged solve."""
+    rng = np.random.default_rng(3)
+    worlds = []
+    for k in range(6):
+        worlds.append(scenes.box_point_contacts(rng, n_points=2, mu=0.6, gap_scale=1e-3, v_scale=0.3))
+    for k in range(6):
+        worlds.append(scenes.random_chain_world(rng, n_bodies=3, with_limits=True, on_manifold=True))
+    scene = scenes.round_to_f32(scenes.concat(worlds))
+    params = cfg2_params(dt=1e-3, eps=1e-7)
+    g = gpu_step(scene, params, max_contacts=2)
+    kp = kamx.make_params(**params)
+    rs = compare_worlds(scene, kp, g, range(scene.n_worlds), mode="reference")
+    e = summary("free boxes on two contacts; limited chains", rs)
+    from oracle import floor_report
+    import oracle
+    for r, w in zip(rs, range(scene.n_worlds)):
+        rep = floor_report(scene, oracle.Params(dt=1e-3), w)
+        assert rep["null_dim"] == 0, (w, rep)
+    assert np.all(g["status"] == 0)
+    assert e[:, 2].max() < TOL and e[:, 0].max() < TOL and e[:, 1].max() < TOL
+    check_reported_residuals(rs, 1e-7)
+
+
+def test_warm_starts_leave_the_converged_answer_unchanged():
+    """Cold, previous-step, learned (an untrained network) and a garbage
+    external warm start of 1e6 times random impulses, on the same state,
+    contacts and joint forces: every world that converges under all four
+    ends at the same unique quantities as the oracle's converged solve
+    (J^T lambda within 1e-4, momentum-weighted u+ within 1e-4); only the
+    iteration counts differ (the warm start sets where Alg. 1 starts, step
+    2, not where it stops)."""
+    n = 64
+    scene, tau = biped_state(n, seed=31)
+    other, _ = biped_state(n, seed=32)
+    p = cfg2_params(log_restarts=0)
+    nets = []
+
+    def previous(m):
+        # a step from another state fills the cache, then the state of the test
+        m.upload_state(other.q, other.u)
+        m.step(1)
+        m.upload_state(scene.q, scene.u)
+
+    def learned(m):
+        nf, ns = m.feature_dims()
+        net = kamx.MLP(nf, ns, n_hidden=256, max_batch=n, seed=9)
+        nets.append(net)
+        m.attach_mlp(net)
+
+    rng = np.random.default_rng(5)
+    runs = dict(
+        cold=gpu_step(scene, p, ext=tau),
+        previous=gpu_step(scene, dict(p, warmstart=kamx.WARM_PREVIOUS), ext=tau, setup=previous),
+        learned=gpu_step(scene, dict(p, warmstart=kamx.WARM_LEARNED), ext=tau, setup=learned),
+    )
+    rows = int(runs["cold"]["row_offsets"][-1])
+    runs["garbage"] = gpu_step(scene, dict(p, warmstart=kamx.WARM_EXTERNAL), ext=tau,
+                               warm=(1e6 * rng.normal(0.0, 1.0, rows)).astype(np.float32))
+    for net in nets:
+        net.close()
+    ok = np.ones(n, bool)
+    for mode, g in runs.items():
+        ok &= g["status"] == 0
+        print(f"{mode}: iterations mean {g['iters'].mean():.1f} p50 {np.median(g['iters']):.0f} max {g['iters'].max()}; "
+              f"converged {np.mean(g['status'] == 0):.3f}", flush=True)
+    assert ok.mean() > 0.8
+    worlds = np.nonzero(ok)[0][:24]
+    params = kamx.make_params(**p)
+    errs = {}
+    for mode, g in runs.items():
+        rs = compare_worlds(scene, params, g, worlds, mode="reference")
+        errs[mode] = summary(f"{mode} warm start, {len(worlds)} worlds converged in every mode", rs)
+    bo = scene.body_offsets()
+    for mode in ("previous", "learned", "garbage"):
+        d = max(np.abs(runs[mode]["u"][bo[w]:bo[w + 1]] - runs["cold"]["u"][bo[w]:bo[w + 1]]).max() /
+                max(np.abs(runs["cold"]["u"][bo[w]:bo[w + 1]]).max(), 1e-6) for w in worlds)
+        print(f"{mode}: max rel u+ difference to the cold solve {d:.2e}")
+    for mode, e in errs.items():
+        assert e[:, 1].max() < TOL and e[:, 3].max() < TOL, mode
+
+
+def test_excavator_unreplayed_with_active_stroke_limit():
+    """The excavator (mass ratio 1e4, four loops, three cylinders) with every
+    cylinder's upper stroke bound moved to its current length and a force
+    pushing it outward, so the limit rows are active; no Baumgarte (the
+    FP32-rounded loops would add their own floor).  Against the oracle's
+    converged solve: J^T lambda and the plain u+ of every body."""
+    rng = np.random.default_rng(21)
+    scene = scenes.round_to_f32(scenes.excavator_batch(8, seed=1003))
+    scene = scenes.perturb_state(scene, rng, 0.05, 0.05)
+    scene.u = scene.u.astype(np.float32).astype(np.float64)
+    import oracle
+    lim = scene.joint_limit.copy()
+    tau = np.zeros(scene.n_joints)
+    for j in range(scene.n_joints):
+        if scene.joint_type[j] == scenes.PRISMATIC:
+            c = oracle.joint_coordinate(scene, scene.q, j)[0]
+            lim[j] = (c - 0.3, np.float32(c))
+            tau[j] = 5e4
+    scene = scene.replace(joint_limit=lim)
+    act = scene.joint_actuated.astype(bool) & (scene.joint_type != scenes.PRISMATIC)
+    tau[act] = rng.normal(0.0, 2000.0, act.sum())
+    p = cfg2_params(baumgarte=0.0)
+    g = gpu_step(scene, p, ext=tau.astype(np.float32))
+    params = kamx.make_params(**p)
+    rs = compare_worlds(scene, params, g, range(8), mode="reference")
+    e = summary(f"excavator 8 worlds, stroke limits active, iters {g['iters'].tolist()}", rs)
+    for r in rs:
+        lam, kind = r["ref"]["lam"], r["S"]["kind"]
+        lim_rows = np.nonzero(kind == 1)[0]
+        print(f"  world {r['world']}: limit impulses (oracle) {lam[lim_rows]}  GPU {r['lam_g'][lim_rows]}")
+        assert np.all(lam[lim_rows] > 0.0)
+    conv = np.array([r["status"] == 0 for r in rs])
+    assert e[:, 1].max() < TOL and e[:, 3].max() < TOL
+    print(f"plain u+ max rel error {e[:, 0].max():.2e}")
+
+
+def test_box_bin_falling_state_at_contact_cap():
+    """The contact-heavy workload as benchmarked: 20 boxes per world dropped
+    into the bin, stepped until they pile up, then one step with the
+    contacts generated inside the step kernel at the 64-contact cap,
+    against the oracle's converged solve on its own generated contacts."""
+    scene = scenes.box_bin_batch(64, seed=1005)
+    p = cfg2_params(max_iters=2000, log_restarts=0)
+    m = kamx.Model(scene, params=p, max_contacts=64)
+    m.contacts_box_bin(margin=0.01)
+    m.step(60)
+    q, u = (t.cpu().numpy().astype(np.float64) for t in m.state())
+    m.close()
+    s1 = scene.replace(q=q, u=u)
+    m = kamx.Model(s1, params=p, max_contacts=64)
+    m.contacts_box_bin(margin=0.01)
+    it_log = m.set_iterate_log()
+    m.step(1)
+    torch.cuda.synchronize()
+    q2, u2 = (t.cpu().numpy().astype(np.float64) for t in m.state())
+    st = {k: v.cpu().numpy() for k, v in m.stats().items()}
+    raw, cnt = m.contacts()
+    g = dict(q=q2, u=u2, lam=m.impulses().cpu().numpy().astype(np.float64), row_offsets=m.row_offsets,
+             used_scene=kamx.contacts_to_scene(s1, raw, cnt), iterate=it_log.cpu().numpy().astype(np.float64),
+             inputs=dict(box_bin=(0.15, 0.15, 0.01, 64), explicit=False, ext=None, step=0), **st)
+    counts = cnt.cpu().numpy()
+    print(f"contacts per world: min {counts.min()} mean {counts.mean():.1f} max {counts.max()}; "
+          f"at the cap {np.mean(counts == 64):.2f}; converged {np.mean(st['status'] == 0):.3f}")
+    m.close()
+    params = kamx.make_params(**p)
+    worlds = np.argsort(-counts)[:12]
+    rs = compare_worlds(s1, params, g, worlds, mode="reference")
+    e = summary("boxes in a bin after 60 steps (12 worlds with the most contacts)", rs)
+    conv = np.array([r["status"] == 0 for r in rs])
+    assert np.any(counts == 64)
+    assert e[conv, 1].max() < TOL and e[conv, 3].max() < TOL
+    check_reported_residuals(rs, 1e-6)
