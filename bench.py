@@ -122,7 +122,35 @@ def make_model(workload, n_worlds, warmstart, schedule, seed=None):
     return scene, model
 
 
-def run_gpu(n_worlds, steps, warmup, warmstart, schedule, net=None, seed=None, workload="biped", autotune=True):
+def last_step_sample(model, scene, n_sample=64, seed=0):
+    """One more (untimed) step after the timed rollout, with what an FP64
+    check of its solves needs: the pre-step state, the joint forces and
+    contacts the step used, the impulses, the returned iterate and the
+    reported residuals of a sample of worlds (every capped one first)."""
+    import torch
+    from paper_2603_16536_amd import kamx
+    q0, u0 = (t.cpu().numpy().astype(np.float64) for t in model.state())
+    it_log = model.set_iterate_log()
+    model.step(1)
+    torch.cuda.synchronize()
+    st = {k: v.cpu().numpy() for k, v in model.stats().items()}
+    raw, cnt = model.contacts()
+    used = kamx.contacts_to_scene(scene.replace(q=q0, u=u0), raw, cnt)
+    out = dict(scene=used, torques=model.torques().cpu().numpy().astype(np.float64),
+               lam=model.impulses().cpu().numpy().astype(np.float64), row_offsets=model.row_offsets,
+               iterate=it_log.cpu().numpy().astype(np.float64), **st)
+    model.set_iterate_log(False)
+    rng = np.random.default_rng(seed)
+    capped = np.nonzero(st["status"] != 0)[0]
+    rest = np.setdiff1d(np.arange(scene.n_worlds), capped)
+    k = min(len(capped), n_sample // 4)
+    out["sample"] = np.sort(np.r_[rng.choice(capped, k, replace=False) if k else np.zeros(0, int),
+                                  rng.choice(rest, n_sample - k, replace=False)]).astype(int)
+    return out
+
+
+def run_gpu(n_worlds, steps, warmup, warmstart, schedule, net=None, seed=None, workload="biped", autotune=True,
+            capture=False):
     """Warm-up steps, then one timed call of `steps` steps (chained launches
     where the mode allows, single-step launches otherwise), bracketed by HIP
     events on the launch stream; per-step iteration and row counts come
@@ -143,7 +171,8 @@ def run_gpu(n_worlds, steps, warmup, warmstart, schedule, net=None, seed=None, w
     nw = scene.n_worlds
     iters = torch.zeros((steps, nw), dtype=torch.int32, device="cuda")
     rows = torch.zeros((steps, nw), dtype=torch.int32, device="cuda")
-    model.set_iteration_log(iters, rows)
+    status_log = torch.zeros((steps, nw), dtype=torch.int32, device="cuda")
+    model.set_iteration_log(iters, rows, status_log)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     resets0 = model.reset_count()
     torch.cuda.synchronize()
@@ -155,13 +184,15 @@ def run_gpu(n_worlds, steps, warmup, warmstart, schedule, net=None, seed=None, w
     t1 = time.perf_counter()
     model.set_iteration_log(None)
     status = model.stats()["status"].cpu().numpy()
+    check = last_step_sample(model, scene) if capture else None
     # box-bin worlds (192-row bucket) generate their contacts inside the step
     # kernel, so every workload chains under the default schedule
     chained = schedule == kamx_sched_chain()
     launches = -(-steps // 64) if chained else steps
     out = dict(
         wall_s=t1 - t0, event_ms=e0.elapsed_time(e1), launches=launches, steps_per_launch=steps / launches,
-        iters=iters.cpu().numpy(), rows=rows.cpu().numpy(), status_last=status,
+        iters=iters.cpu().numpy(), rows=rows.cpu().numpy(), status=status_log.cpu().numpy(), status_last=status,
+        check=check,
         resets=model.reset_count() - resets0, buckets=model.n_buckets, bucket_table=bucket_table,
         sum_kb2=incidence_sq(scene) if workload == "biped" else 0.0,
     )
@@ -206,6 +237,21 @@ def mlp_throughput(net, batch=4096, reps=50):
     return res
 
 
+def solver_stats(run, world_steps):
+    """Iterations and outcomes of every timed world-step (from the per-step
+    iteration and status logs): a world-step converged when all three
+    residuals went below 1e-6 (status OK); the rest stopped at the iteration
+    cap, on a non-finite residual or a failed factorization."""
+    it, st = run["iters"], run["status"]
+    conv = float((st == 0).mean())
+    return {"iters_mean": round(float(it.mean()), 1), "iters_p50": float(np.percentile(it, 50)),
+            "iters_p99": float(np.percentile(it, 99)), "converged_fraction": round(conv, 5),
+            "status_counts": {"ok": int((st == 0).sum()), "maxiter": int(((st & 1) != 0).sum()),
+                              "nonfinite": int(((st & 2) != 0).sum()), "factor_fail": int(((st & 4) != 0).sum())},
+            "converged_world_steps_per_s": round(world_steps * conv / run["wall_s"], 1),
+            "value_counts": "every world-step, converged or stopped at the cap"}
+
+
 def kamx_sched_chain():
     from paper_2603_16536_amd import kamx
     return kamx.SCHED_CHAIN
@@ -214,7 +260,25 @@ def kamx_sched_chain():
 def cpu_baseline(min_seconds=12.0, n_worlds=512, max_steps=60):
     """The FP64 oracle on the host cores: the same biped workload (PD +
     noise torques, probe contacts refreshed every step, cold start to 1e-6),
-    a bounded sample of worlds and steps."""
+    a bounded sample of worlds and steps, on every core the process may use
+    and on one core."""
+    import oracle
+
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    threads = min(threads, int(os.environ.get("OMP_NUM_THREADS", threads)))
+    oracle.set_threads(threads)
+    allc = oracle_rollout(min_seconds, n_worlds, max_steps)
+    oracle.set_threads(1)
+    one = oracle_rollout(min_seconds / 3.0, 32, max_steps)
+    oracle.set_threads(threads)
+    return dict(value=allc["rate"], unit="world-steps/s", cores=threads, kind="oracle",
+                sample=f"{allc['worlds']} biped worlds x {allc['steps']} steps from the standing pose, FP64, "
+                       f"mean {allc['iters']:.0f} iterations, {allc['seconds']:.1f} s",
+                one_core={"value": one["rate"], "unit": "world-steps/s", "cores": 1,
+                          "sample": f"{one['worlds']} worlds x {one['steps']} steps, {one['seconds']:.1f} s"})
+
+
+def oracle_rollout(min_seconds, n_worlds, max_steps):
     import oracle
     from paper_2603_16536_amd import scenes
 
@@ -244,10 +308,63 @@ def cpu_baseline(min_seconds=12.0, n_worlds=512, max_steps=60):
         done += scene.n_worlds
         q, u = out["q"], out["u"]
         step += 1
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return dict(value=done / spent, unit="world-steps/s", cores=threads, kind="oracle",
-                sample=f"{n_worlds} biped worlds x {step} steps from the standing pose, FP64, "
-                       f"mean {it_sum / max(done, 1):.0f} iterations, {spent:.1f} s")
+    return dict(rate=done / spent, worlds=n_worlds, steps=step, iters=it_sum / max(done, 1), seconds=spent)
+
+
+def fp64_check(chk):
+    """The oracle's FP64 view of sampled GPU solves of one benchmark step:
+    the natural-map NCP residual (Eq. 3) of the GPU impulses, and the three
+    residuals Alg. 1 step 9 reports, recomputed at the GPU's returned
+    iterate.  The system (D, v_f) is built by the oracle from the pre-step
+    state, the step's joint forces and the contacts the step used."""
+    import oracle
+
+    sc = chk["scene"]
+    P = oracle.Params(dt=CFG2["dt"], eta=CFG2["eta"], rho_bil=CFG2["rho_bilateral"], rho_c=CFG2["rho_contact"],
+                      baumgarte=CFG2["baumgarte"])
+    jo = sc.joint_offsets()
+    ncp_conv, ncp_all, diff = 0.0, 0.0, 0.0
+    for w in chk["sample"]:
+        S = oracle.world_system(sc, P, int(w), joint_torque=chk["torques"])
+        m = S["J"].shape[0]
+        r0 = int(chk["row_offsets"][w])
+        lam = chk["lam"][r0:r0 + m]
+        it = chk["iterate"][r0:r0 + m]
+        D, vf, kind, mu = S["D"], S["vf"], S["kind"], S["mu"]
+        p = oracle.preconditioner(D, kind)
+        v = p * (D @ lam + vf)
+        lt = lam / p
+        r = 0.0
+        i = 0
+        while i < m:  # || lam~ - Pi_K(lam~ - (v + Gamma(v))) ||_inf
+            if kind[i] == oracle.ROW_NORMAL:
+                wv = v[i:i + 3].copy()
+                wv[0] += mu[i] * np.hypot(v[i + 1], v[i + 2])
+                o = oracle.project_block(2, mu[i], lt[i:i + 3] - wv)
+                r = max(r, np.abs(lt[i:i + 3] - o).max())
+                i += 3
+            elif kind[i] == oracle.ROW_LIMIT:
+                r = max(r, abs(lt[i] - max(lt[i] - v[i], 0.0)))
+                i += 1
+            else:
+                r = max(r, abs(v[i]))
+                i += 1
+        ncp_all = max(ncp_all, r)
+        if chk["status"][w] == 0:
+            ncp_conv = max(ncp_conv, r)
+            # r_p, r_d, r_c at the returned iterate with the GPU's scales
+            x, y, z, pg = it[:, 0], it[:, 1], it[:, 2], it[:, 3]
+            vv = pg * (D @ (pg * x)) + pg * vf
+            g = np.zeros(m)
+            nrm = np.nonzero(kind == oracle.ROW_NORMAL)[0]
+            g[nrm] = mu[nrm] * np.hypot(vv[nrm + 1], vv[nrm + 2])
+            rd = np.abs(vv + g - z).max()
+            diff = max(diff, abs(rd - chk["resid"][w, 1]), abs(np.abs(x - y).max() - chk["resid"][w, 0]))
+    n_conv = int(np.sum(chk["status"][chk["sample"]] == 0))
+    return {"ncp_residual_fp64_max_converged": float(ncp_conv), "ncp_residual_fp64_max_all": float(ncp_all),
+            "reported_vs_fp64_residual_max_diff": float(diff), "gpu_reported_residual_max_converged":
+            float(chk["resid"][chk["status"] == 0, :3].max()), "sample_worlds": len(chk["sample"]),
+            "sample_converged": n_conv, "units": "preconditioned (Jacobi-scaled) impulses and velocities"}
 
 
 def contacts_from_probes(scene, q, margin):
@@ -311,11 +428,10 @@ def main():
         args.no_learned = True
         args.no_cpu = True
     cold = run_gpu(args.worlds, args.steps, args.warmup, kamx.WARM_COLD, sched, workload=args.workload,
-                   autotune=not args.no_autotune)
-    cap = {"biped": CFG2["max_iters"], "fourbar": 51}.get(args.workload, 200)
+                   autotune=not args.no_autotune, capture=args.workload == "biped" and not args.no_cpu)
     value = args.worlds * args.steps / cold["wall_s"]
     it = cold["iters"]
-    conv = float((it < cap).mean())
+    conv = float((cold["status"] == 0).mean())
     flops_total = float(algorithmic_flops(cold["rows"], it, cold["sum_kb2"]).sum())
     avg_launch_s = cold["event_ms"] / 1e3 / cold["launches"]
     achieved = flops_total / cold["launches"] / avg_launch_s / 1e12
@@ -344,21 +460,17 @@ def main():
                      "traffic": measured_traffic(cold["steps_per_launch"]) if args.workload == "biped" and args.worlds == 4096 else None,
                      "kernel": "step_kernel<224,512>" if args.workload == "biped" else "all step kernels",
                      "avg_launch_ms": round(1e3 * avg_launch_s, 4), "steps_per_launch": cold["steps_per_launch"]},
-        "solver": {"iters_mean": round(float(it.mean()), 1), "iters_p50": float(np.percentile(it, 50)),
-                   "iters_p99": float(np.percentile(it, 99)), "converged_fraction": round(conv, 5),
-                   "resets": int(cold["resets"])},
+        "solver": solver_stats(cold, args.worlds * args.steps),
     }
+    result["solver"]["resets"] = int(cold["resets"])
     if not args.no_previous:
         print("[bench] previous-step warm-start rollout", file=sys.stderr, flush=True)
         prev = run_gpu(args.worlds, args.steps, args.warmup, kamx.WARM_PREVIOUS, sched, workload=args.workload,
                        autotune=not args.no_autotune)
-        pit = prev["iters"]
         result["warm_previous"] = {
             "value": round(args.worlds * args.steps / prev["wall_s"], 1),
             "ms_per_step": round(1e3 * prev["wall_s"] / args.steps, 4),
-            "iters_mean": round(float(pit.mean()), 1), "iters_p50": float(np.percentile(pit, 50)),
-            "iters_p99": float(np.percentile(pit, 99)),
-            "converged_fraction": round(float((pit < cap).mean()), 5)}
+            **solver_stats(prev, args.worlds * args.steps)}
     if not args.no_learned:
         from paper_2603_16536_amd import learn
         print(f"[bench] learned warm start: {args.train_steps}-step cold rollout for data (noise seed "
@@ -376,14 +488,11 @@ def main():
         t_train = time.perf_counter() - t0
         print("[bench] learned warm-start rollout", file=sys.stderr, flush=True)
         lrn = run_gpu(args.worlds, args.steps, args.warmup, kamx.WARM_LEARNED, sched, net=net)
-        lit = lrn["iters"]
         result["learned"] = {
             "value": round(args.worlds * args.steps / lrn["wall_s"], 1),
             "ms_per_step": round(1e3 * lrn["wall_s"] / args.steps, 4),
             "speedup_vs_plain": round((args.worlds * args.steps / lrn["wall_s"]) / value, 4),
-            "iters_mean": round(float(lit.mean()), 1), "iters_p50": float(np.percentile(lit, 50)),
-            "iters_p99": float(np.percentile(lit, 99)),
-            "converged_fraction": round(float((lit < CFG2["max_iters"]).mean()), 5),
+            **solver_stats(lrn, args.worlds * args.steps),
             "network": "667 -> 256 -> 256 -> 224 (GELU), BF16 matrix-core kernels, FP32 accumulation",
             "training": {"samples": info["samples"], "held_out": info["held_out"], "epochs": args.epochs,
                          "final_train_loss": round(info["train_loss"][-1], 5), "val_loss": round(info["val_loss"], 5),
@@ -400,6 +509,9 @@ def main():
     if not args.no_cpu:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline()
+        if cold["check"] is not None:
+            print("[bench] FP64 check of sampled GPU solves", file=sys.stderr, flush=True)
+            result["solver"]["fp64_check"] = fp64_check(cold["check"])
     print(json.dumps(result), flush=True)
 
 

@@ -337,12 +337,14 @@ kamx_status kamx_autotune(kamx_model m, int32_t trial_steps, float *ms_out);
  * captured (use nsteps = 1 there). */
 kamx_status kamx_step(kamx_model m, int32_t nsteps, kamx_stream stream);
 
-/* Iteration count and active row count of every step of every following
- * kamx_step call: iters_dev and rows_dev [steps][n_worlds] (device,
- * caller-owned, valid while steps are pending; rows_dev may be NULL); row k
- * holds the k-th step of the call, steps beyond `steps` are not logged.
- * iters_dev = NULL turns logging off.  EINVAL if steps < 1. */
-kamx_status kamx_set_iteration_log(kamx_model m, int32_t *iters_dev, int32_t *rows_dev, int32_t steps);
+/* Iteration count (Alg. 1 iterations run), active row count and status
+ * bits (KAMX_WORLD_*) of every step of every following kamx_step call:
+ * iters_dev, rows_dev and status_dev [steps][n_worlds] (device,
+ * caller-owned, valid while steps are pending; rows_dev and status_dev may
+ * be NULL); row k holds the k-th step of the call, steps beyond `steps` are
+ * not logged.  iters_dev = NULL turns logging off.  EINVAL if steps < 1. */
+kamx_status kamx_set_iteration_log(kamx_model m, int32_t *iters_dev, int32_t *rows_dev, int32_t *status_dev,
+                                   int32_t steps);
 
 /* Forward kinematics for resets (Sec. 6.3): move every body of every world
  * so that all joint constraints hold (the passive joints of kinematic loops

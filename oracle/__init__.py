@@ -118,6 +118,8 @@ def lib():
         L.orc_world_system.restype = C.c_int
         L.orc_world_system.argtypes = [C.POINTER(_Batch), C.POINTER(_Params)] + [C.c_void_p] * 3 + [C.c_int] + [C.c_void_p] * 10
         L.orc_step_configuration.argtypes = [C.POINTER(_Batch), C.POINTER(_Params)] + [C.c_void_p] * 3
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_set_threads.restype = None
         L.orc_fk.restype = C.c_int
         L.orc_fk.argtypes = [C.POINTER(_Batch), C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int,
                              C.c_void_p, C.c_void_p, C.c_void_p]
@@ -418,3 +420,8 @@ def forward_kinematics(scene, targets, base=None, q=None, tol=1e-12, max_iters=1
     if rc != 0:
         raise MemoryError("oracle forward kinematics failed")
     return q_out, iters, res
+
+
+def set_threads(n):
+    """Threads of the oracle's loops over worlds."""
+    lib().orc_set_threads(int(n))

@@ -34,6 +34,9 @@
  */
 #include <math.h>
 #include <stdint.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdlib.h>
 #include <string.h>
 
@@ -1113,6 +1116,16 @@ int orc_step(const orc_batch *B, const orc_params *P, orc_io *io) {
     }
     free(qm);
     return err;
+}
+
+/* Threads of the OpenMP loops over worlds (for timing the oracle on one
+ * core and on all of them). */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
 }
 
 /* Dimensions of world w: bodies and rows. */

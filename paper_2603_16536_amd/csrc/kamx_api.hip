@@ -86,6 +86,7 @@ struct kamx_model_s {
     int32_t schedule = KAMX_SCHED_CHAIN;
     int32_t *iter_log = nullptr;  // caller-owned [iter_log_rows * n_worlds] iterations per step
     int32_t *row_log = nullptr;   // caller-owned, same shape: active rows per step
+    int32_t *status_log = nullptr;  // caller-owned, same shape: status bits per step
     int32_t iter_log_rows = 0;
     float *iterate_log = nullptr;  // caller-owned [rows_cap * 4] final iterate of the last step
     std::vector<int32_t> row_offsets;
@@ -676,6 +677,7 @@ static kamx_status enqueue_launch(kamx_model m, int n, int pos, hipStream_t s) {
     if (m->iter_log && pos < m->iter_log_rows) {
         base.iter_log = m->iter_log + (long)pos * m->n_worlds;
         base.row_log = m->row_log ? m->row_log + (long)pos * m->n_worlds : nullptr;
+        base.status_log = m->status_log ? m->status_log + (long)pos * m->n_worlds : nullptr;
         base.iter_log_rows = m->iter_log_rows - pos;
     }
     const bool lpt = n == 1 && m->schedule != KAMX_SCHED_INDEX;
@@ -975,12 +977,14 @@ kamx_status kamx_autotune(kamx_model m, int32_t trial_steps, float *ms_out) {
     return KAMX_OK;
 }
 
-kamx_status kamx_set_iteration_log(kamx_model m, int32_t *iters_dev, int32_t *rows_dev, int32_t steps) {
+kamx_status kamx_set_iteration_log(kamx_model m, int32_t *iters_dev, int32_t *rows_dev, int32_t *status_dev,
+                                   int32_t steps) {
     if (!m) return fail(KAMX_EINVAL, "model is NULL");
     if (iters_dev && steps < 1) return fail(KAMX_EINVAL, "steps must be positive");
     drop_graphs(m);
     m->iter_log = iters_dev;
     m->row_log = iters_dev ? rows_dev : nullptr;
+    m->status_log = iters_dev ? status_dev : nullptr;
     m->iter_log_rows = iters_dev ? steps : 0;
     return KAMX_OK;
 }

@@ -29,11 +29,11 @@ __global__ __launch_bounds__(kNarrowThreads) void box_bin_kernel(const WorldInfo
             float pose[7];
             for (int e = 0; e < 7; ++e) pose[e] = qw[7 * b + e];
             if (half_dt > 0.f) {
-                float u6[6];
+                double q7[7], u6[6], qm[7];
+                for (int e = 0; e < 7; ++e) q7[e] = pose[e];
                 for (int e = 0; e < 6; ++e) u6[e] = uw[6 * b + e];
-                float qm[7];
-                half_step_pose(pose, u6, half_dt, qm);
-                for (int e = 0; e < 7; ++e) pose[e] = qm[e];
+                advance_pose(q7, u6, (double)half_dt, qm);
+                for (int e = 0; e < 7; ++e) pose[e] = (float)qm[e];
             }
             for (int e = 0; e < 3; ++e) c[e] = pose[e];
             for (int e = 0; e < 4; ++e) qt[e] = pose[3 + e];

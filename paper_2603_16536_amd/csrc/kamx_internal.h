@@ -55,30 +55,32 @@ struct SolverParams {
     int32_t integrator;  // KAMX_EULER or KAMX_MOREAU_JEAN
 };
 
-// Poses the step's rows are built at: the pre-step pose (Euler), or for the
-// Moreau-Jean midpoint the pose advanced by h = dt / 2 with the pre-step
-// twist (r + h v, exp(h [w]x) R by the quaternion exponential, renormalised).
-// Shared by the step kernel and the contact generation kernel so both see
+// A pose advanced by time h with a twist: r + h v, and exp(h [w]x) R by
+// the quaternion exponential (left multiplication, world-frame w),
+// renormalised.  The end-of-step pose update, and (Moreau-Jean) the
+// half-step configuration the rows are built at; evaluated in FP64 there,
+// by the step kernel and the contact generation kernel alike, so both see
 // the same bits.
-__device__ inline void half_step_pose(const float q[7], const float u[6], float h, float out[7]) {
+template <typename T>
+__device__ inline void advance_pose(const T q[7], const T u[6], T h, T out[7]) {
     for (int k = 0; k < 3; ++k) out[k] = q[k] + h * u[k];
-    const float wn = sqrtf(u[3] * u[3] + u[4] * u[4] + u[5] * u[5]);
-    float dq[4] = {0.f, 0.f, 0.f, 1.f};
-    if (wn > 0.f) {
-        const float half = 0.5f * h * wn;
-        const float sh = sinf(half) / wn;
+    const T wn = sqrt(u[3] * u[3] + u[4] * u[4] + u[5] * u[5]);
+    T dq[4] = {T(0), T(0), T(0), T(1)};
+    if (wn > T(0)) {
+        const T half = T(0.5) * h * wn;
+        const T sh = sin(half) / wn;
         dq[0] = u[3] * sh;
         dq[1] = u[4] * sh;
         dq[2] = u[5] * sh;
-        dq[3] = cosf(half);
+        dq[3] = cos(half);
     }
-    const float *p = q + 3;
-    float r[4];
+    const T *p = q + 3;
+    T r[4];
     r[0] = dq[3] * p[0] + dq[0] * p[3] + dq[1] * p[2] - dq[2] * p[1];
     r[1] = dq[3] * p[1] - dq[0] * p[2] + dq[1] * p[3] + dq[2] * p[0];
     r[2] = dq[3] * p[2] + dq[0] * p[1] - dq[1] * p[0] + dq[2] * p[3];
     r[3] = dq[3] * p[3] - dq[0] * p[0] - dq[1] * p[1] - dq[2] * p[2];
-    const float nn = 1.f / sqrtf(r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + r[3] * r[3]);
+    const T nn = T(1) / sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + r[3] * r[3]);
     for (int k = 0; k < 4; ++k) out[3 + k] = r[k] * nn;
 }
 
@@ -150,6 +152,7 @@ struct StepArgs {
     int32_t n_worlds;            // worlds of the model (stride of iter_log)
     int32_t *iter_log;           // [iter_log_rows * n_worlds] iterations of every step, or null
     int32_t *row_log;            // [iter_log_rows * n_worlds] active rows of every step, or null
+    int32_t *status_log;         // [iter_log_rows * n_worlds] status bits of every step, or null
     int32_t iter_log_rows;       // steps of this launch that have a log row
     // learned warm start
     int32_t stage;               // 0: full step; 1: write the features of the coming step and stop
@@ -174,10 +177,11 @@ __host__ __device__ inline int contact_floats() { return 12 * kMaxContacts; }  /
 __host__ __device__ inline int row_floats(int mc) { return 18 * mc; }
 __host__ __device__ inline int vec_floats(int mc) { return 15 * mc; }
 __host__ __device__ inline int bodyw_floats() { return 2 * 6 * kMaxBodies; }  // FP64 [6][kMaxBodies]
+__host__ __device__ inline int posed_floats() { return 2 * 7 * kMaxBodies; }  // FP64 poses [7][kMaxBodies]
 __host__ __device__ inline int inc_floats(int mc) { return ((kMaxBodies + 1 + 2 * mc) + 3) & ~3; }
 __host__ __device__ inline int smem_floats(int mc) {
     return body_floats() + joint_floats() + contact_floats() + row_floats(mc) + vec_floats(mc) +
-           tri_row_offset(mc) + 64 + bodyw_floats() + inc_floats(mc);
+           tri_row_offset(mc) + 64 + bodyw_floats() + posed_floats() + inc_floats(mc);
 }
 
 }  // namespace kamx

@@ -109,6 +109,7 @@ enum { VP = 0, VRHO, VVT, VX, VYH, VZH, VYP, VZP, VRHS, VT, VXN, VWS, VAUX, VCOL
 struct Lds {
     float *b, *j, *c, *r, *v, *A, *red;
     double *wb;          // [6][kMaxBodies] FP64 body work vector
+    double *qd;          // [7][kMaxBodies] FP64 poses the rows are built at
     int *inc_off;        // [kMaxBodies + 1] body -> row incidence offsets
     int *inc_list;       // [2 * MC] (row << 1) | side
     int mc;
@@ -151,8 +152,8 @@ __device__ inline void apply_minv(const Lds &L, int b, const float in[6], float 
 // FP32.
 __device__ inline void joint_geo(const Lds &L, const float *jf, int la, int lb, JointGeo &g) {
     double qa[7], qb[7];
-    for (int k = 0; k < 7; ++k) qa[k] = L.bf(BQ + k, la);
-    for (int k = 0; k < 7; ++k) qb[k] = lb >= 0 ? (double)L.bf(BQ + k, lb) : 0.0;
+    for (int k = 0; k < 7; ++k) qa[k] = L.qd[k * kMaxBodies + la];
+    for (int k = 0; k < 7; ++k) qb[k] = lb >= 0 ? L.qd[k * kMaxBodies + lb] : 0.0;
     joint_geo_q(qa, qb, lb >= 0, jf, g);
 }
 
@@ -486,7 +487,8 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
     L.A = L.v + vec_floats(MC);
     L.red = L.A + tri_row_offset(MC);
     L.wb = reinterpret_cast<double *>(L.red + 64);
-    L.inc_off = reinterpret_cast<int *>(L.red + 64 + bodyw_floats());
+    L.qd = L.wb + 6 * kMaxBodies;
+    L.inc_off = reinterpret_cast<int *>(L.red + 64 + bodyw_floats() + posed_floats());
     L.inc_list = L.inc_off + kMaxBodies + 1;
     float *A = L.A;
 
@@ -518,12 +520,19 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
         float q[7], u6[6];
         for (int k = 0; k < 7; ++k) q[k] = qs[7 * gb + k];
         for (int k = 0; k < 6; ++k) u6[k] = us[6 * gb + k];
+        // the configuration the rows are built at, in FP64: the pre-step pose,
+        // or (Moreau-Jean) the half-step pose, whose joint geometry must not
+        // carry FP32 rounding into the Baumgarte bias
+        double qd[7];
+        for (int k = 0; k < 7; ++k) qd[k] = q[k];
         if (P.integrator == KAMX_MOREAU_JEAN) {
-            // rows, forces and contacts at the half-step configuration
-            float qm[7];
-            half_step_pose(q, u6, 0.5f * P.dt, qm);
-            for (int k = 0; k < 7; ++k) q[k] = qm[k];
+            double u6d[6], qm[7];
+            for (int k = 0; k < 6; ++k) u6d[k] = u6[k];
+            advance_pose(qd, u6d, 0.5 * (double)P.dt, qm);
+            for (int k = 0; k < 7; ++k) qd[k] = qm[k];
+            for (int k = 0; k < 7; ++k) q[k] = (float)qm[k];
         }
+        for (int k = 0; k < 7; ++k) L.qd[k * kMaxBodies + b] = qd[k];
         for (int k = 0; k < 7; ++k) L.bf(BQ + k, b) = q[k];
         for (int k = 0; k < 6; ++k) L.bf(BU + k, b) = u6[k];
         float R[9];
@@ -742,10 +751,10 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
             // world point in FP64 (its height is the gap, which enters the
             // bias divided by dt), then rounded to FP32
             double qd[4], Rd[9], pld[3] = {pl[0], pl[1], pl[2]}, td[3];
-            for (int e = 0; e < 4; ++e) qd[e] = L.bf(BQ + 3 + e, lbod);
+            for (int e = 0; e < 4; ++e) qd[e] = L.qd[(3 + e) * kMaxBodies + lbod];
             rot_of_quat(qd, Rd);
             mv3(Rd, pld, td);
-            for (int e = 0; e < 3; ++e) pw[e] = (float)((double)L.bf(BQ + e, lbod) + td[e]);
+            for (int e = 0; e < 3; ++e) pw[e] = (float)(L.qd[e * kMaxBodies + lbod] + td[e]);
             act = pw[2] < P.contact_margin;
         }
         unsigned long long mask = __ballot(act);
@@ -1705,6 +1714,7 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
         if (a.iter_log && k < a.iter_log_rows) {
             a.iter_log[(long)k * a.n_worlds + w] = it;
             if (a.row_log) a.row_log[(long)k * a.n_worlds + w] = m;
+            if (a.status_log) a.status_log[(long)k * a.n_worlds + w] = status;
         }
         a.rows[w] = m;
         a.resid[4 * w + 0] = rp;
@@ -1757,10 +1767,11 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
         for (int k = 0; k < 6; ++k) a.u[6 * gb + k] = un[k];
         // poses over the rest of the step from the rows' configuration: dt
         // (Euler) or dt / 2 from the half-step poses (Moreau-Jean)
-        float q[7], qn[7];
-        for (int k = 0; k < 7; ++k) q[k] = L.bf(BQ + k, b);
-        half_step_pose(q, un, P.integrator == KAMX_MOREAU_JEAN ? 0.5f * P.dt : P.dt, qn);
-        for (int k = 0; k < 7; ++k) a.q[7 * gb + k] = qn[k];
+        double q[7], ud[6], qn[7];
+        for (int k = 0; k < 7; ++k) q[k] = L.qd[k * kMaxBodies + b];
+        for (int k = 0; k < 6; ++k) ud[k] = un[k];
+        advance_pose(q, ud, (P.integrator == KAMX_MOREAU_JEAN ? 0.5 : 1.0) * (double)P.dt, qn);
+        for (int k = 0; k < 7; ++k) a.q[7 * gb + k] = (float)qn[k];
     }
     __syncthreads();
     if (a.phase_clk && tid == 0) a.phase_clk[16 * w + 7] = wall_clock64();

@@ -97,7 +97,7 @@ def lib():
         L.kamx_bucket_info.argtypes = [vp, i32] + [C.POINTER(C.c_int32)] * 5
         L.kamx_set_bucket_threads.argtypes = [vp, i32, i32]
         L.kamx_autotune.argtypes = [vp, i32, C.POINTER(C.c_float)]
-        L.kamx_set_iteration_log.argtypes = [vp, vp, vp, i32]
+        L.kamx_set_iteration_log.argtypes = [vp, vp, vp, vp, i32]
         L.kamx_set_iterate_log.argtypes = [vp, vp]
         L.kamx_forward_kinematics.argtypes = [vp, vp, i32, C.c_float, vp, vp, vp]
         L.kamx_mlp_create.argtypes = [i32, i32, i32, i32, C.c_uint64, C.POINTER(vp)]
@@ -383,19 +383,20 @@ class Model:
         _check(lib().kamx_model_attach_mlp(self.handle, net.handle if net is not None else None))
         self._mlp = net
 
-    def set_iteration_log(self, iters, rows=None):
+    def set_iteration_log(self, iters, rows=None, status=None):
         """Device int32 tensors [steps, n_worlds] that receive the iteration
-        count (and active rows) of every step of the following step() calls
-        (None: off)."""
+        count (and active rows and status bits) of every step of the
+        following step() calls (None: off)."""
         if iters is None:
-            _check(lib().kamx_set_iteration_log(self.handle, None, None, 0))
+            _check(lib().kamx_set_iteration_log(self.handle, None, None, None, 0))
         else:
-            for t in (iters, rows):
+            for t in (iters, rows, status):
                 assert t is None or (t.dtype == torch.int32 and t.is_contiguous() and t.shape[1] == self.n_worlds)
-            _check(lib().kamx_set_iteration_log(self.handle, _ptr(iters), _ptr(rows), int(iters.shape[0])))
-        self._iter_log = (iters, rows)
+            _check(lib().kamx_set_iteration_log(self.handle, _ptr(iters), _ptr(rows), _ptr(status),
+                                                int(iters.shape[0])))
+        self._iter_log = (iters, rows, status)
 
-    def forward_kinematics(self, targets, max_iters=50, tol=1e-9, stream=None):
+    def forward_kinematics(self, targets, max_iters=50, tol=3e-7, stream=None):
         """Poses consistent with every joint and with the target joint
         coordinates ([n_joints], NaN = free), reset bodies held; twists set to
         zero.  Returns device tensors (iterations, |F|_inf) per world."""

@@ -205,7 +205,9 @@ REFERENCE = dict(eps=1e-12, max_iters=100000, fixed_iters=0)
 def oracle_inputs(scene, params, g, worlds, inputs=None):
     """The sub-scene of ``worlds`` with the contacts the oracle generates
     itself from the pre-step state (checked key for key against the ones
-    the GPU used), and the joint forces computed oracle-side."""
+    the GPU used), the GPU's contact order per world, the joint forces
+    computed oracle-side, and per world whether the GPU's contacts have the
+    oracle's geometry up to FP32 rounding."""
     import oracle.contacts as OC
     inp = dict(g.get("inputs") or {})
     inp.update(inputs or {})
@@ -221,15 +223,27 @@ def oracle_inputs(scene, params, g, worlds, inputs=None):
     gsub = g["used_scene"].subset(list(worlds))
     so, go = sub.contact_offsets(), gsub.contact_offsets()
     perms = []
+    match = []
     for k in range(len(worlds)):
         kk = sub.contact_key[so[k]:so[k + 1]]
         gk = gsub.contact_key[go[k]:go[k + 1]]
         assert np.array_equal(np.sort(gk), np.sort(kk)), f"contact sets differ in world {worlds[k]}"
         g_of_key = {int(x): i for i, x in enumerate(gk)}
-        perms.append([g_of_key[int(x)] for x in kk])
+        perm = [g_of_key[int(x)] for x in kk]
+        perms.append(perm)
+        # the same geometry up to FP32 rounding (normal, gap, point, bodies)
+        a = np.arange(so[k], so[k + 1])
+        b = go[k] + np.array(perm, int)
+        ok = True
+        if len(a):
+            ok = (np.abs(sub.contact_normal[a] - gsub.contact_normal[b]).max() < 1e-5 and
+                  np.abs(sub.contact_gap[a] - gsub.contact_gap[b]).max() < 1e-6 and
+                  np.abs(sub.contact_point[a] - gsub.contact_point[b]).max() < 1e-5 and
+                  np.array_equal(sub.contact_body[a] - sub.body_offsets()[k], gsub.contact_body[b] - gsub.body_offsets()[k]))
+        match.append(bool(ok))
     tau = np.concatenate([oracle_torques(scene, params, int(w), ext=inp.get("ext"), step=inp.get("step", 0),
                                          pd=inp.get("pd"), refs=inp.get("refs")) for w in worlds] or [np.zeros(0)])
-    return sub, perms, tau
+    return sub, perms, tau, match
 
 
 def fp64_residuals_at_iterate(S, it, kind, mu):
@@ -278,7 +292,7 @@ def compare_worlds(scene, params, g, worlds, mode="reference", oracle_over=None,
     first iteration at which its restart decisions differ from the oracle's
     own (0: never within the shorter run)."""
     worlds = [int(w) for w in worlds]
-    sub, perms, tau = oracle_inputs(scene, params, g, worlds, inputs)
+    sub, perms, tau, match = oracle_inputs(scene, params, g, worlds, inputs)
     over = dict(oracle_over or {})
     if mode == "reference":
         over = {**REFERENCE, **over}
@@ -357,7 +371,8 @@ def compare_worlds(scene, params, g, worlds, mode="reference", oracle_over=None,
             e_imp=np.abs(imp_g - imp_o).max() / max(np.abs(imp_o).max(), floor_imp),
             e_lam=np.abs(lam_g - ref["lam"]).max() / max(np.abs(ref["lam"]).max(), floor_imp),
             r_ncp=ncp_natural_residual(lam_g / p, p * (D @ lam_g + vf), kind, mu),
-            gpu_resid=np.asarray(g["resid"][w], np.float64), lam_g=lam_g, ref=ref, S=S)
+            gpu_resid=np.asarray(g["resid"][w], np.float64), lam_g=lam_g, ref=ref, S=S,
+            contacts_match=match[k])
         if "iterate" in g:
             it = g["iterate"][r0:r0 + m][rowperm]
             res["fp64_resid"] = fp64_residuals_at_iterate(S, it, kind, mu)
