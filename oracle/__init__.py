@@ -42,7 +42,7 @@ class _Params(C.Structure):
         ("max_iters", C.c_int32), ("fixed_iters", C.c_int32), ("accel", C.c_int32),
         ("restart_factor", C.c_double), ("precond", C.c_int32), ("baumgarte", C.c_double),
         ("warmstart", C.c_int32), ("replay", C.c_int32), ("log_stride", C.c_int32),
-        ("integrator", C.c_int32),
+        ("integrator", C.c_int32), ("cr_iters", C.c_int32),
     ]
 
 
@@ -85,6 +85,7 @@ class Params:
     baumgarte: float = 0.2
     warmstart: int = 0
     integrator: int = 0  # 0 semi-implicit Euler, 1 Moreau-Jean midpoint (Sec. 3)
+    cr_iters: int = 0    # 0 Cholesky; > 0 Conjugate Residual iterations per x-update (Sec. 5.1)
 
     def replace(self, **kw):
         return dataclasses.replace(self, **kw)
@@ -99,6 +100,7 @@ class Params:
         p.restart_factor, p.precond, p.baumgarte = self.restart_factor, self.precond, self.baumgarte
         p.warmstart, p.replay, p.log_stride = self.warmstart, replay, log_stride
         p.integrator = self.integrator
+        p.cr_iters = self.cr_iters
         return p
 
 
@@ -118,6 +120,8 @@ def lib():
         L.orc_world_system.restype = C.c_int
         L.orc_world_system.argtypes = [C.POINTER(_Batch), C.POINTER(_Params)] + [C.c_void_p] * 3 + [C.c_int] + [C.c_void_p] * 10
         L.orc_step_configuration.argtypes = [C.POINTER(_Batch), C.POINTER(_Params)] + [C.c_void_p] * 3
+        L.orc_cr_solve.restype = C.c_int
+        L.orc_cr_solve.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]
         L.orc_set_threads.argtypes = [C.c_int]
         L.orc_set_threads.restype = None
         L.orc_fk.restype = C.c_int
@@ -425,3 +429,13 @@ def forward_kinematics(scene, targets, base=None, q=None, tol=1e-12, max_iters=1
 def set_threads(n):
     """Threads of the oracle's loops over worlds."""
     lib().orc_set_threads(int(n))
+
+
+def cr_solve(A, b, n_iters, x0=None):
+    """Conjugate Residual on the SPD system A x = b (Sec. 5.1's inner
+    solver), n_iters iterations from x0 (default 0)."""
+    A = np.ascontiguousarray(A, np.float64)
+    b = np.ascontiguousarray(b, np.float64)
+    x = np.zeros(len(b)) if x0 is None else np.array(x0, np.float64)
+    lib().orc_cr_solve(len(b), _p(A), _p(b), int(n_iters), _p(x))
+    return x

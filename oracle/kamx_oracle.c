@@ -22,6 +22,9 @@
  *   Sec. 3            the Moreau-Jean midpoint variant of the time step
  *   Sec. 6.3          forward kinematics by Gauss-Newton (consistent poses
  *                     from target joint coordinates, for resets)
+ *   Sec. 5.1          the iterative linear solve of Alg. 1 step 5: Conjugate
+ *                     Residual with a fixed budget, warm-started at the
+ *                     previous iterate, on the Delassus operator
  * Where the paper is silent the readings are stated next to the code that
  * uses them.  Everything is written for clarity: dense J (m x 6 n_b), dense
  * D = J M^-1 J^T, a textbook Cholesky and two triangular solves per
@@ -72,6 +75,8 @@ typedef struct {
     int32_t replay;        /* 1: restart decisions read from restart_log   */
     int32_t log_stride;    /* bytes per world in restart_log               */
     int32_t integrator;    /* 0 semi-implicit Euler, 1 Moreau-Jean midpoint */
+    int32_t cr_iters;      /* 0: Cholesky; > 0: that many Conjugate Residual
+                              iterations per x-update (Sec. 5.1)          */
 } orc_params;
 
 typedef struct {
@@ -759,6 +764,51 @@ static void chol_solve(int n, const double *L, const double *b, double *x) {
     }
 }
 
+/* Sec. 5.1 iterative solve of A x = b for the SPD A = D~ + diag(eta + rho):
+ * Conjugate Residual (Saad, Iterative Methods for Sparse Linear Systems,
+ * Alg. 6.20) from the initial guess in x, exactly n_it iterations (fewer if
+ * the residual vanishes).  A is applied as a plain product. */
+static void cr_solve(int n, const double *A, const double *b, int n_it, double *x, double *work) {
+    double *r = work, *p = work + n, *Ar = work + 2 * (size_t)n, *Ap = work + 3 * (size_t)n;
+    for (int i = 0; i < n; ++i) {
+        double s = b[i];
+        for (int j = 0; j < n; ++j) s -= A[(size_t)i * n + j] * x[j];
+        r[i] = s;
+        p[i] = s;
+    }
+    for (int i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < n; ++j) s += A[(size_t)i * n + j] * r[j];
+        Ar[i] = s;
+        Ap[i] = s;
+    }
+    double rAr = 0.0;
+    for (int i = 0; i < n; ++i) rAr += r[i] * Ar[i];
+    for (int k = 0; k < n_it; ++k) {
+        double ApAp = 0.0;
+        for (int i = 0; i < n; ++i) ApAp += Ap[i] * Ap[i];
+        if (!(ApAp > 0.0) || !(rAr > 0.0)) break;
+        const double alpha = rAr / ApAp;
+        for (int i = 0; i < n; ++i) {
+            x[i] += alpha * p[i];
+            r[i] -= alpha * Ap[i];
+        }
+        for (int i = 0; i < n; ++i) {
+            double s = 0.0;
+            for (int j = 0; j < n; ++j) s += A[(size_t)i * n + j] * r[j];
+            Ar[i] = s;
+        }
+        double rAr_new = 0.0;
+        for (int i = 0; i < n; ++i) rAr_new += r[i] * Ar[i];
+        const double beta = rAr_new / rAr;
+        rAr = rAr_new;
+        for (int i = 0; i < n; ++i) {
+            p[i] = r[i] + beta * p[i];
+            Ap[i] = Ar[i] + beta * Ap[i];
+        }
+    }
+}
+
 static double inf_norm(int n, const double *v) {
     double r = 0.0;
     for (int i = 0; i < n; ++i) {
@@ -833,7 +883,8 @@ int orc_solve_ncp(int m, const double *D, const double *vf, const int *kind, con
     /* Alg. 1, step 1: D_{eta,rho} = D~ + diag(eta + rho), factored once */
     for (size_t k = 0; k < mm; ++k) A[k] = Dt[k];
     for (int i = 0; i < m; ++i) A[(size_t)i * m + i] += P->eta + rho[i];
-    if (orc_cholesky(m, A, L) != 0) {
+    double *crw = P->cr_iters > 0 ? malloc(sizeof(double) * 4 * (size_t)m) : NULL;
+    if (P->cr_iters <= 0 && orc_cholesky(m, A, L) != 0) {
         status |= ORC_FACTOR_FAIL;
         for (int i = 0; i < m; ++i) {
             lambda[i] = 0.0;
@@ -877,7 +928,13 @@ int orc_solve_ncp(int m, const double *D, const double *vf, const int *kind, con
         desaxce(m, kind, mu, zh, s);
         /* step 5: x = D_{eta,rho}^-1 (-v_f - s + eta x + rho y + z) */
         for (int i = 0; i < m; ++i) rhs[i] = -vt[i] - s[i] + P->eta * x[i] + rho[i] * yh[i] + zh[i];
-        chol_solve(m, L, rhs, xn);
+        if (P->cr_iters > 0) {
+            /* warm start at the previous iterate (Sec. 5.1) */
+            for (int i = 0; i < m; ++i) xn[i] = x[i];
+            cr_solve(m, A, rhs, P->cr_iters, xn, crw);
+        } else {
+            chol_solve(m, L, rhs, xn);
+        }
         /* step 6: y = Pi_K(x - z / rho) */
         for (int i = 0; i < m; ++i) tmp[i] = xn[i] - zh[i] / rho[i];
         project_K(m, kind, mu, tmp, yn);
@@ -995,6 +1052,7 @@ int orc_solve_ncp(int m, const double *D, const double *vf, const int *kind, con
     }
 
 done:
+    free(crw);
     free(p); free(Dt); free(A); free(L); free(vt); free(rho);
     free(x); free(y); free(z); free(yh); free(zh); free(yp); free(zp);
     free(s); free(rhs); free(xn); free(yn); free(zn); free(v); free(g); free(tmp);
@@ -1116,6 +1174,16 @@ int orc_step(const orc_batch *B, const orc_params *P, orc_io *io) {
     }
     free(qm);
     return err;
+}
+
+/* Conjugate Residual on an explicit SPD system (for tests): n_it
+ * iterations from the initial guess in x. */
+int orc_cr_solve(int n, const double *A, const double *b, int n_it, double *x) {
+    double *w = malloc(sizeof(double) * 4 * (size_t)(n > 0 ? n : 1));
+    if (!w) return -1;
+    cr_solve(n, A, b, n_it, x, w);
+    free(w);
+    return 0;
 }
 
 /* Threads of the OpenMP loops over worlds (for timing the oracle on one
