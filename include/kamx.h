@@ -203,7 +203,10 @@ typedef struct {
  * penetrating one beta f / h, with h = dt (Euler) or dt/2 (Moreau-Jean). */
 void kamx_default_params(kamx_params *p);
 
-/* Create a model of n_worlds worlds.  bodies[nb], joints[nj], probes[np]
+/* Create a model of n_worlds worlds (Sec. 3: the bodies, Eq. 1, and the
+ * joints between body pairs or a body and the world that a world's
+ * multi-body system is made of; Sec. 5.2: many such worlds, of different
+ * structure, in one batch).  bodies[nb], joints[nj], probes[np]
  * (np may be 0) are host arrays.  reset_body[n_worlds] (host, may be NULL)
  * names the global body whose height triggers a reset, or -1.  Explicit
  * contacts may later be supplied with up to max_contacts_per_world per world
@@ -229,12 +232,15 @@ kamx_status kamx_model_info(kamx_model m, int32_t *n_bodies, int32_t *n_joints, 
                             int32_t *n_buckets, int32_t *row_offsets);
 
 /* Copy poses q_dev [nb*7] and twists u_dev [nb*6] (FP32, device) into the
- * model.  as_reset_state != 0 also stores them as the reset state.
+ * model: the configuration and generalized velocity of every body (Sec. 3;
+ * position + unit quaternion (x, y, z, w), then linear and world-frame
+ * angular velocity).  as_reset_state != 0 also stores them as the reset state.
  * Stream-ordered. */
 kamx_status kamx_state_upload(kamx_model m, const float *q_dev, const float *u_dev, int32_t as_reset_state,
                               kamx_stream stream);
 
-/* Copy the current poses and twists out to q_dev [nb*7], u_dev [nb*6]. */
+/* Copy the current poses and twists out to q_dev [nb*7], u_dev [nb*6]: the
+ * state the last step advanced to (Sec. 3, the time-stepping scheme). */
 kamx_status kamx_state_download(kamx_model m, float *q_dev, float *u_dev, kamx_stream stream);
 
 /* Use explicit contacts for the following steps instead of probes:
@@ -267,10 +273,12 @@ kamx_status kamx_contacts_box_bin(kamx_model m, const kamx_box_desc *boxes, floa
                                   float margin);
 
 /* External generalized joint forces joint_torque_dev [nj] added to the
- * actuation of every following step; NULL clears them. */
+ * actuation of every following step (Sec. 3, Eq. 1: part of the generalized
+ * forces h of the free velocity); NULL clears them. */
 kamx_status kamx_set_external(kamx_model m, const float *joint_torque_dev, kamx_stream stream);
 
-/* Impulses used as the warm start in KAMX_WARM_EXTERNAL mode:
+/* Impulses that initialize the solver's iterates (Alg. 1 step 2; Sec. 4.1,
+ * warm starting) in KAMX_WARM_EXTERNAL mode:
  * lambda_dev [rows_capacity] in physical units at the row offsets of
  * kamx_model_info.  Copied at the call. */
 kamx_status kamx_set_warmstart(kamx_model m, const float *lambda_dev, kamx_stream stream);
@@ -377,11 +385,14 @@ kamx_status kamx_forward_kinematics(kamx_model m, const float *targets_dev, int3
  * misaligned. */
 kamx_status kamx_set_iterate_log(kamx_model m, float *iterate_dev);
 
-/* Impulses of the last step (physical units, N s) into lambda_dev
+/* The constraint impulses the solve returned (Alg. 1 step 11, lambda =
+ * P y after un-scaling) for the last step (physical units, N s) into lambda_dev
  * [rows_capacity]; rows beyond a world's active count are zero. */
 kamx_status kamx_read_impulses(kamx_model m, float *lambda_dev, kamx_stream stream);
 
-/* Per-world results of the last step: iterations iters_dev [n_worlds],
+/* Per-world results of the last step (Alg. 1 steps 9-10: the residuals of
+ * the exit test and the iteration at which it passed or the budget ran
+ * out): iterations iters_dev [n_worlds],
  * residuals resid_dev [n_worlds*4] = (r_p, r_d, r_c, r_ncp) in
  * preconditioned units, status_dev [n_worlds] (KAMX_WORLD_* bits) and the
  * active row count rows_dev [n_worlds].  Any pointer may be NULL. */
