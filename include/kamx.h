@@ -97,6 +97,25 @@ typedef int32_t kamx_status;
 #define KAMX_MAX_CONTACTS_PER_WORLD 64
 #define KAMX_MAX_ROWS_PER_WORLD 224
 
+/* Limits of a world solved matrix-free (Sec. 5.1: the Delassus operator
+ * applied through the Jacobian, Conjugate Residual inner solves).  Rows run
+ * one per thread with each contact's three rows in an aligned group of four:
+ * align4(5 joints + limits + drives) + 4 * contacts must not exceed
+ * KAMX_MAX_THREAD_ROWS_SPARSE. */
+#define KAMX_MAX_BODIES_SPARSE 160
+#define KAMX_MAX_JOINTS_SPARSE 200
+#define KAMX_MAX_THREAD_ROWS_SPARSE 1024
+
+/* Linear solver of Alg. 1 step 5 (Sec. 5.1), chosen per world at model
+ * creation.  DENSE: the Delassus matrix is assembled and factored once per
+ * step (worlds within the per-world limits above).  SPARSE: matrix-free
+ * Delassus products with cr_iters Conjugate Residual iterations per ADMM
+ * iteration, warm-started at the previous iterate (worlds within the sparse
+ * limits).  AUTO: dense where a world fits the dense limits, else sparse. */
+#define KAMX_SOLVER_AUTO 0
+#define KAMX_SOLVER_DENSE 1
+#define KAMX_SOLVER_SPARSE 2
+
 /* A rigid body (Sec. 3, Eq. 1): mass and principal moments of inertia in
  * its body frame.  Bodies must be sorted by world. */
 typedef struct {
@@ -192,12 +211,15 @@ typedef struct {
                              reset to the stored initial state at step start */
     int32_t log_restarts; /* 1: record the restart decision of every iteration */
     int32_t integrator;   /* KAMX_EULER or KAMX_MOREAU_JEAN                   */
+    int32_t linear_solver; /* KAMX_SOLVER_*; fixed at model creation          */
+    int32_t cr_iters;     /* Conjugate Residual iterations per ADMM iteration
+                             (matrix-free worlds; 1..1000)                   */
 } kamx_params;
 
 /* Fill *p with defaults (dt 2 ms, gravity -9.81 z, eta 1e-4, rho 1e-4 / 0.3,
  * eps 1e-6, 2000 iterations, acceleration and preconditioning on, restart
  * factor 0.999, beta 0.2, cold start, margin 0.02 m, no noise, semi-implicit
- * Euler).  Position-level terms act over the time from the configuration
+ * Euler, solver chosen by world size, 9 Conjugate Residual iterations).  Position-level terms act over the time from the configuration
  * the rows are built at to the end of the step: the Baumgarte bias of a
  * bilateral row is beta f / h, a separated contact or limit f / h, a
  * penetrating one beta f / h, with h = dt (Euler) or dt/2 (Moreau-Jean). */

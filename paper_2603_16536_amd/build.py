@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkamx.so")
-SOURCES = ["kamx_step.hip", "kamx_sched.hip", "kamx_mlp.hip", "kamx_contacts.hip", "kamx_fk.hip", "kamx_api.hip"]
+SOURCES = ["kamx_step.hip", "kamx_sched.hip", "kamx_mlp.hip", "kamx_contacts.hip", "kamx_fk.hip", "kamx_sparse.hip", "kamx_api.hip"]
 
 # Packed FP32 instructions are disabled for all device code.
 HIPCC_FLAGS = [

@@ -16,6 +16,7 @@ namespace kamx {
 hipError_t launch_step(const StepArgs &args, int mc, int nt, int n, hipStream_t stream);
 int step_threads_variants(int mc, int out[4]);
 int bucket_capacity(int rows);
+int sparse_row_class(int thread_rows);
 size_t step_smem_bytes(int mc);
 hipError_t launch_lpt_order(const int32_t *worlds, int n, const int32_t *iters, int32_t *order, hipStream_t stream);
 hipError_t launch_advance_step(uint32_t *ctr, uint32_t inc, hipStream_t stream);
@@ -112,6 +113,9 @@ struct kamx_model_s {
     int32_t *d_ncontacts = nullptr, *d_reset_count = nullptr;
     uint64_t *d_phase_clk = nullptr;  // debug phase stamps (enabled by KAMX_PHASE_CLOCK)
     uint32_t *d_step = nullptr;       // step counter read by the step kernels
+    // worlds solved matrix-free (Conjugate Residual), and the largest world
+    bool has_sparse = false;
+    int max_nb = 0, max_nj = 0;
     // learned warm start (worlds of identical structure only)
     bool uniform = false;
     int n_feat = 0, n_slots = 0, n_contact_slots = 0;
@@ -178,6 +182,9 @@ static kamx_status validate_params(const kamx_params *p) {
     if (p->fixed_iters < 0 || p->fixed_iters > 1000000) return fail(KAMX_EINVAL, "fixed_iters out of range");
     if (!(p->restart_factor > 0.f)) return fail(KAMX_EINVAL, "restart_factor must be positive");
     if (p->warmstart < KAMX_WARM_COLD || p->warmstart > KAMX_WARM_LEARNED) return fail(KAMX_EINVAL, "bad warmstart");
+    if (p->linear_solver < KAMX_SOLVER_AUTO || p->linear_solver > KAMX_SOLVER_SPARSE)
+        return fail(KAMX_EINVAL, "linear_solver must be KAMX_SOLVER_AUTO, _DENSE or _SPARSE");
+    if (p->cr_iters < 1 || p->cr_iters > 1000) return fail(KAMX_EINVAL, "cr_iters must be in [1, 1000]");
     return KAMX_OK;
 }
 
@@ -205,6 +212,7 @@ static SolverParams to_solver(const kamx_params &p) {
     s.reset_height = p.reset_height;
     s.log_restarts = p.log_restarts;
     s.integrator = p.integrator;
+    s.cr_iters = p.cr_iters;
     return s;
 }
 
@@ -232,6 +240,8 @@ void kamx_default_params(kamx_params *p) {
     p->reset_height = -INFINITY;
     p->log_restarts = 0;
     p->integrator = KAMX_EULER;
+    p->linear_solver = KAMX_SOLVER_AUTO;
+    p->cr_iters = 9;
 }
 
 const char *kamx_last_error(void) { return g_error.c_str(); }
@@ -301,8 +311,10 @@ kamx_status kamx_model_create(const kamx_body_desc *bodies, int32_t nb, const ka
         cursor_b += W.nb;
         cursor_j += W.nj;
         cursor_p += W.np;
-        if (W.nb < 1 || W.nb > kMaxBodies) return fail(KAMX_EINVAL, "world %d: %d bodies (1..%d)", w, W.nb, kMaxBodies);
-        if (W.nj > kMaxJoints) return fail(KAMX_EINVAL, "world %d: %d joints (max %d)", w, W.nj, kMaxJoints);
+        if (W.nb < 1 || W.nb > KAMX_MAX_BODIES_SPARSE)
+            return fail(KAMX_EINVAL, "world %d: %d bodies (1..%d)", w, W.nb, KAMX_MAX_BODIES_SPARSE);
+        if (W.nj > KAMX_MAX_JOINTS_SPARSE)
+            return fail(KAMX_EINVAL, "world %d: %d joints (max %d)", w, W.nj, KAMX_MAX_JOINTS_SPARSE);
         if (W.np > kMaxContacts) return fail(KAMX_EINVAL, "world %d: %d probes (max %d)", w, W.np, kMaxContacts);
         W.nlim = 0;
         W.ndrv = 0;
@@ -332,8 +344,22 @@ kamx_status kamx_model_create(const kamx_body_desc *bodies, int32_t nb, const ka
                 return fail(KAMX_EINVAL, "probe %d: body %d not in world %d", k, probes[k].body, w);
         W.contact_cap = std::max(W.np, (int)max_contacts_per_world);
         W.row_cap = 5 * W.nj + W.nlim + W.ndrv + 3 * W.contact_cap;
-        if (W.row_cap > kMaxRows)
-            return fail(KAMX_EINVAL, "world %d: row capacity %d exceeds %d", w, W.row_cap, kMaxRows);
+        // dense (assembled and factored Delassus matrix) where the world fits
+        // the dense limits, matrix-free otherwise (Sec. 5.1), unless the
+        // parameters force one of them
+        {
+            const bool dense_ok = W.nb <= kMaxBodies && W.nj <= kMaxJoints && W.row_cap <= kMaxRows;
+            const int thread_rows = ((5 * W.nj + W.nlim + W.ndrv + 3) & ~3) + 4 * W.contact_cap;
+            const bool sparse_ok = thread_rows <= KAMX_MAX_THREAD_ROWS_SPARSE;
+            const int solver = params->linear_solver;
+            if (solver == KAMX_SOLVER_DENSE && !dense_ok)
+                return fail(KAMX_EINVAL, "world %d: %d bodies, %d joints, %d rows exceed the dense limits (%d, %d, %d)", w,
+                            W.nb, W.nj, W.row_cap, kMaxBodies, kMaxJoints, kMaxRows);
+            if ((solver == KAMX_SOLVER_SPARSE || !dense_ok) && !sparse_ok)
+                return fail(KAMX_EINVAL, "world %d: %d thread rows exceed the matrix-free limit %d", w, thread_rows,
+                            KAMX_MAX_THREAD_ROWS_SPARSE);
+            W.sparse = solver == KAMX_SOLVER_SPARSE || (solver == KAMX_SOLVER_AUTO && !dense_ok);
+        }
         W.row_base = row_off[w];
         row_off[w + 1] = row_off[w] + W.row_cap;
         if (reset_body && reset_body[w] >= 0) {
@@ -354,6 +380,11 @@ kamx_status kamx_model_create(const kamx_body_desc *bodies, int32_t nb, const ka
     m->params = *params;
     m->row_offsets = row_off;
     m->uniform = true;
+    for (int w = 0; w < n_worlds; ++w) {
+        m->has_sparse = m->has_sparse || wi[w].sparse;
+        m->max_nb = std::max(m->max_nb, (int)wi[w].nb);
+        m->max_nj = std::max(m->max_nj, (int)wi[w].nj);
+    }
     for (int w = 1; w < n_worlds; ++w)
         if (wi[w].nb != wi[0].nb || wi[w].nj != wi[0].nj || wi[w].nlim != wi[0].nlim ||
             wi[w].ndrv != wi[0].ndrv || wi[w].contact_cap != wi[0].contact_cap)
@@ -454,18 +485,27 @@ kamx_status kamx_model_create(const kamx_body_desc *bodies, int32_t nb, const ka
     M_TRY(up(m->d_pf, pf.data(), sizeof(float) * pf.size()));
 
     // size buckets: worlds grouped by the smallest row capacity class
-    std::vector<std::vector<int32_t>> groups(8);
-    std::vector<int> caps;
+    // (slots 0-6: dense buckets of 32, ..., 224 rows; 7-9: matrix-free
+    // buckets of 256, 512 and 1024 thread rows)
+    std::vector<std::vector<int32_t>> groups(10);
     for (int w = 0; w < n_worlds; ++w) {
-        int mc = bucket_capacity(std::max(wi[w].row_cap, 1));
-        if (mc < 0) return cleanup_fail(fail(KAMX_EINVAL, "world %d: no bucket for %d rows", w, wi[w].row_cap));
-        int slot = mc / 32 - 1;
+        int slot;
+        if (wi[w].sparse) {
+            const int tr = ((5 * wi[w].nj + wi[w].nlim + wi[w].ndrv + 3) & ~3) + 4 * wi[w].contact_cap;
+            const int nt = sparse_row_class(std::max(tr, 1));
+            if (nt < 0) return cleanup_fail(fail(KAMX_EINVAL, "world %d: no matrix-free class for %d rows", w, tr));
+            slot = nt == 256 ? 7 : (nt == 512 ? 8 : 9);
+        } else {
+            int mc = bucket_capacity(std::max(wi[w].row_cap, 1));
+            if (mc < 0) return cleanup_fail(fail(KAMX_EINVAL, "world %d: no bucket for %d rows", w, wi[w].row_cap));
+            slot = mc / 32 - 1;
+        }
         groups[slot].push_back(w);
     }
-    for (int s = 7; s >= 0; --s) {  // largest worlds first
+    for (int s = 9; s >= 0; --s) {  // largest worlds first
         if (groups[s].empty()) continue;
         Bucket b;
-        b.mc = 32 * (s + 1);
+        b.mc = s < 7 ? 32 * (s + 1) : (s == 7 ? 256 : (s == 8 ? 512 : 1024));
         int nts[4];
         if (step_threads_variants(b.mc, nts) < 1) return cleanup_fail(fail(KAMX_EINVAL, "no kernel for %d rows", b.mc));
         b.nt = nts[0];
@@ -499,6 +539,8 @@ kamx_status kamx_model_destroy(kamx_model m) {
 kamx_status kamx_set_params(kamx_model m, const kamx_params *params) {
     if (!m) return fail(KAMX_EINVAL, "model is NULL");
     K_TRY(validate_params(params));
+    if (params->linear_solver != m->params.linear_solver)
+        return fail(KAMX_EINVAL, "linear_solver is fixed at model creation");
     m->params = *params;
     drop_graphs(m);
     K_TRY(ensure_rlog(m));
@@ -995,6 +1037,9 @@ kamx_status kamx_forward_kinematics(kamx_model m, const float *targets_dev, int3
     if (!targets_dev) return fail(KAMX_EINVAL, "targets_dev is NULL");
     if (max_iters < 0 || max_iters > 10000) return fail(KAMX_EINVAL, "max_iters must be in [0, 10000]");
     if (!(tol >= 0.f)) return fail(KAMX_EINVAL, "tol must be >= 0");
+    if (m->max_nb > kMaxBodies || m->max_nj > kMaxJoints)
+        return fail(KAMX_EUNSUPPORTED, "forward kinematics supports worlds of at most %d bodies and %d joints",
+                    kMaxBodies, kMaxJoints);
     K_TRY(check_device());
     hipError_t e = launch_fk(m->d_worlds, m->n_worlds, m->d_jint, m->d_jf, m->d_mass, m->d_inertia, m->d_q, m->d_u,
                              targets_dev, max_iters, tol, iters_dev, resid_dev, reinterpret_cast<hipStream_t>(stream));
@@ -1013,6 +1058,7 @@ kamx_status kamx_set_iterate_log(kamx_model m, float *iterate_dev) {
 
 kamx_status kamx_model_feature_dims(kamx_model m, int32_t *n_features, int32_t *n_slots) {
     if (!m) return fail(KAMX_EINVAL, "model is NULL");
+    if (m->has_sparse) return fail(KAMX_EUNSUPPORTED, "matrix-free worlds have no learned warm start");
     if (!m->uniform) return fail(KAMX_EUNSUPPORTED, "worlds differ in structure: no common feature layout");
     if (n_features) *n_features = m->n_feat;
     if (n_slots) *n_slots = m->n_slots;
@@ -1021,6 +1067,7 @@ kamx_status kamx_model_feature_dims(kamx_model m, int32_t *n_features, int32_t *
 
 kamx_status kamx_model_features(kamx_model m, float *x_dev, kamx_stream stream) {
     if (!m || !x_dev) return fail(KAMX_EINVAL, "NULL argument");
+    if (m->has_sparse) return fail(KAMX_EUNSUPPORTED, "matrix-free worlds have no learned warm start");
     if (!m->uniform) return fail(KAMX_EUNSUPPORTED, "worlds differ in structure: no common feature layout");
     K_TRY(check_device());
     return enqueue_features(m, x_dev, reinterpret_cast<hipStream_t>(stream));
@@ -1028,6 +1075,7 @@ kamx_status kamx_model_features(kamx_model m, float *x_dev, kamx_stream stream) 
 
 kamx_status kamx_read_impulse_slots(kamx_model m, float *y_dev, kamx_stream stream) {
     if (!m || !y_dev) return fail(KAMX_EINVAL, "NULL argument");
+    if (m->has_sparse) return fail(KAMX_EUNSUPPORTED, "matrix-free worlds have no learned warm start");
     if (!m->uniform) return fail(KAMX_EUNSUPPORTED, "worlds differ in structure: no common slot layout");
     K_TRY(check_device());
     hipError_t e = launch_impulse_slots(m->d_worlds, m->n_worlds, m->n_contact_slots, m->n_slots, m->d_lambda,
@@ -1043,6 +1091,7 @@ kamx_status kamx_model_attach_mlp(kamx_model m, kamx_mlp net) {
         m->mlp = nullptr;
         return KAMX_OK;
     }
+    if (m->has_sparse) return fail(KAMX_EUNSUPPORTED, "matrix-free worlds have no learned warm start");
     if (!m->uniform) return fail(KAMX_EUNSUPPORTED, "worlds differ in structure: no common feature layout");
     if (mlp_n_in(net) != m->n_feat || mlp_n_out(net) != m->n_slots)
         return fail(KAMX_EINVAL, "network is %d -> %d, the model needs %d -> %d", mlp_n_in(net), mlp_n_out(net),

@@ -36,7 +36,8 @@ struct WorldInfo {
     int32_t contact_cap;    // contact capacity
     int32_t reset_body;     // world-local body index, or -1
     int32_t ndrv;           // joints with an implicit drive row
-    int32_t pad[4];
+    int32_t sparse;         // 1: solved matrix-free (Conjugate Residual inner solves)
+    int32_t pad[3];
 };
 
 struct SolverParams {
@@ -53,6 +54,7 @@ struct SolverParams {
     float reset_height;
     int32_t log_restarts;
     int32_t integrator;  // KAMX_EULER or KAMX_MOREAU_JEAN
+    int32_t cr_iters;    // Conjugate Residual iterations per x-update (matrix-free worlds)
 };
 
 // A pose advanced by time h with a twist: r + h v, and exp(h [w]x) R by

@@ -20,76 +20,11 @@
 #include <math.h>
 
 #include "kamx_boxbin.h"
+#include "kamx_device.h"
 #include "kamx_geom.h"
 #include "kamx_internal.h"
 
 namespace kamx {
-
-// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).
-__device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
-    for (int r = 0; r < 10; ++r) {
-        uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
-        uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
-        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
-        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
-        uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-        c[0] = n0;
-        c[1] = lo1;
-        c[2] = n2;
-        c[3] = lo0;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-}
-
-// A standard normal for (world, step, slot) by Box-Muller on two 24-bit
-// uniforms (u1 in (0, 1], u2 in [0, 1)).
-__device__ inline float noise_normal(uint32_t seed_lo, uint32_t seed_hi, uint32_t world, uint32_t step,
-                                     uint32_t slot) {
-    uint32_t c[4] = {world, step, slot, 0u};
-    philox4x32_10(c, seed_lo, seed_hi);
-    const float inv = 1.0f / 16777216.0f;
-    float u1 = ((float)(c[0] >> 8) + 1.0f) * inv;
-    float u2 = (float)(c[1] >> 8) * inv;
-    return sqrtf(-2.0f * logf(u1)) * cosf(6.28318530717958647692f * u2);
-}
-
-// Orthonormal tangents completing a unit normal (Duff et al., JCGT 2017).
-__device__ inline void tangents(const float n[3], float t1[3], float t2[3]) {
-    float sg = n[2] >= 0.f ? 1.f : -1.f;
-    float a = -1.f / (sg + n[2]);
-    float b = n[0] * n[1] * a;
-    t1[0] = 1.f + sg * n[0] * n[0] * a;
-    t1[1] = sg * b;
-    t1[2] = -sg * n[0];
-    t2[0] = b;
-    t2[1] = sg + n[1] * n[1] * a;
-    t2[2] = -n[1];
-}
-
-// Projection on the Coulomb cone K_mu = {|l_t| <= mu l_n}.
-// Square root and reciprocal by the hardware instructions (within 1 ulp;
-// the correctly rounded forms take about ten instructions each), for the
-// scalars the iteration recomputes every step.
-__device__ inline float hw_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
-__device__ inline float hw_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-
-__device__ inline void proj_cone(float mu, float w0, float w1, float w2, float &o0, float &o1, float &o2) {
-    float tn = hw_sqrt(w1 * w1 + w2 * w2);
-    if (tn <= mu * w0) {
-        o0 = w0;
-        o1 = w1;
-        o2 = w2;
-    } else if (mu * tn <= -w0) {
-        o0 = o1 = o2 = 0.f;
-    } else {
-        float ln = (mu * tn + w0) * hw_rcp(1.f + mu * mu);
-        float s = tn > 0.f ? mu * ln * hw_rcp(tn) : 0.f;
-        o0 = ln;
-        o1 = s * w1;
-        o2 = s * w2;
-    }
-}
 
 // ---------------------------------------------------------------------------
 // LDS views
@@ -209,66 +144,6 @@ __device__ inline void joint_rows(const Lds &L, int type, const JointGeo &g, int
 // Costs O(rows) instead of O(rows^2); used for the refinement residual of
 // every x-update and for the dual residual.
 // ---------------------------------------------------------------------------
-
-// Lane permutations inside a row of 16 lanes (DPP): swap neighbours
-// (lane ^ 1), swap pairs (lane ^ 2), mirror within 8 and within 16 lanes.
-// Every lane of the wave must be active where these are used.
-enum { kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppMirror8 = 0x141, kDppMirror16 = 0x140 };
-
-template <int CTRL>
-__device__ inline float dpp(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
-}
-
-template <int CTRL>
-__device__ inline double dpp(double v) {
-    const long long u = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(u & 0xffffffffll), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, 0xF, 0xF, false);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-// Sum over aligned groups of 2, 4, 8 or 16 lanes; every lane of a group
-// ends with the same bits (each step adds two values that the partner adds
-// in the other order).
-template <int G, typename T>
-__device__ inline T lane_group_sum(T v) {
-    if (G >= 2) v += dpp<kDppXor1>(v);
-    if (G >= 4) v += dpp<kDppXor2>(v);
-    if (G >= 8) v += dpp<kDppMirror8>(v);
-    if (G >= 16) v += dpp<kDppMirror16>(v);
-    return v;
-}
-
-// Maximum of values that are +0 or above, or NaN of either sign: as
-// unsigned integers their bit patterns order like the numbers and every NaN
-// lies above +inf, so one integer max keeps a NaN (a NaN residual must stop
-// the solve). Negative numbers and -0 would compare wrongly: callers pass
-// absolute values.
-__device__ inline float max_nonneg(float a, float b) {
-    const unsigned ua = __float_as_uint(a), ub = __float_as_uint(b);
-    return __uint_as_float(ub > ua ? ub : ua);
-}
-
-template <int G>
-__device__ inline float lane_group_max(float v) {
-    if (G >= 2) v = max_nonneg(v, dpp<kDppXor1>(v));
-    if (G >= 4) v = max_nonneg(v, dpp<kDppXor2>(v));
-    if (G >= 8) v = max_nonneg(v, dpp<kDppMirror8>(v));
-    if (G >= 16) v = max_nonneg(v, dpp<kDppMirror16>(v));
-    return v;
-}
-
-// Sum over the G lanes that share a row (fixed butterfly order).
-template <int G, typename T>
-__device__ inline T group_sum(T v) {
-    return lane_group_sum<G>(v);
-}
-
-// Broadcast a lane's value to the whole wave (lane index uniform).
-__device__ inline float rdlane(float v, int lane) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
-}
 
 template <int NT>
 __device__ inline void reduce4(float &m0, float &m1, float &m2, float &s3, float *red) {
@@ -1871,6 +1746,7 @@ int bucket_capacity(int rows) {
 // reduction is evaluated in the same order at every size.
 int step_threads_variants(int mc, int out[4]) {
     switch (mc) {
+    case 256: case 512: case 1024: out[0] = mc; return 1;  // matrix-free: one thread per row
     case 32: out[0] = 256; out[1] = 128; return 2;
     case 64: out[0] = 256; out[1] = 128; return 2;
     case 96: out[0] = 512; out[1] = 256; return 2;
@@ -1882,7 +1758,11 @@ int step_threads_variants(int mc, int out[4]) {
     }
 }
 
+hipError_t launch_sparse_step(const StepArgs &args, int nt, int n, hipStream_t stream);
+size_t sparse_smem_bytes(int nt);
+
 hipError_t launch_step(const StepArgs &args, int mc, int nt, int n, hipStream_t stream) {
+    if (mc > kMaxRows) return launch_sparse_step(args, nt, n, stream);  // matrix-free row classes
     switch (mc * 1024 + nt) {
     case 32 * 1024 + 128: return launch_mc<32, 128>(args, n, stream);
     case 32 * 1024 + 256: return launch_mc<32, 256>(args, n, stream);
@@ -1901,12 +1781,12 @@ hipError_t launch_step(const StepArgs &args, int mc, int nt, int n, hipStream_t 
     }
 }
 
-size_t step_smem_bytes(int mc) { return sizeof(float) * (size_t)smem_floats(mc); }
+size_t step_smem_bytes(int mc) { return mc > kMaxRows ? sparse_smem_bytes(mc) : sizeof(float) * (size_t)smem_floats(mc); }
 
 // whether the step kernel of a row bucket can generate box-bin contacts
 // itself (the candidates must fit in the LDS of its Delassus triangle)
 bool step_generates_box_contacts(int mc) {
-    return sizeof(float) * (size_t)tri_row_offset(mc) >= sizeof(BoxLds);
+    return mc <= kMaxRows && sizeof(float) * (size_t)tri_row_offset(mc) >= sizeof(BoxLds);
 }
 
 }  // namespace kamx

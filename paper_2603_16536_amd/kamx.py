@@ -23,6 +23,8 @@ WORLD_OK, WORLD_MAXITER, WORLD_NONFINITE, WORLD_FACTOR_FAIL = 0, 1, 2, 4
 WARM_COLD, WARM_PREVIOUS, WARM_EXTERNAL, WARM_LEARNED = 0, 1, 2, 3
 SCHED_INDEX, SCHED_LPT, SCHED_CHAIN = 0, 1, 2
 EULER, MOREAU_JEAN = 0, 1
+SOLVER_AUTO, SOLVER_DENSE, SOLVER_SPARSE = 0, 1, 2
+MAX_BODIES_SPARSE, MAX_JOINTS_SPARSE, MAX_THREAD_ROWS_SPARSE = 160, 200, 1024
 MAX_CONTACTS_PER_WORLD = 64
 
 
@@ -33,7 +35,7 @@ class kamx_params(C.Structure):
         ("accel", C.c_int32), ("restart_factor", C.c_float), ("precond", C.c_int32), ("baumgarte", C.c_float),
         ("warmstart", C.c_int32), ("contact_margin", C.c_float), ("torque_sigma", C.c_float),
         ("seed", C.c_uint64), ("reset_height", C.c_float), ("log_restarts", C.c_int32),
-        ("integrator", C.c_int32),
+        ("integrator", C.c_int32), ("linear_solver", C.c_int32), ("cr_iters", C.c_int32),
     ]
 
 

@@ -732,6 +732,120 @@ def biped_batch(n_worlds, seed=1002, dt=2e-3, sole_probes=4):
     return s
 
 
+FIGURE_PD = {"base": (400.0, 8.0), "leg": (200.0, 4.0), "torso": (300.0, 6.0), "head": (20.0, 0.4),
+             "arm": (100.0, 2.0), "finger": (0.2, 0.004)}  # N m / rad, N m s / rad
+
+
+def _perp_pair(a):
+    """Two unit vectors completing the unit axis a to a right-handed frame."""
+    a = np.asarray(a, np.float64)
+    h = np.array([1.0, 0.0, 0.0]) if abs(a[0]) < 0.9 else np.array([0.0, 1.0, 0.0])
+    d1 = np.cross(a, h)
+    d1 /= np.linalg.norm(d1)
+    return d1, np.cross(a, d1)
+
+
+def figure_world(rng, dt=2e-3, link_masses=None):
+    """A figure fixed to the ground with the size of the paper's largest
+    system (Tab. 1: 151 bodies, 27 actuated and 169 passive joints, 45
+    independent loops): a 61-body tree -- base on a yaw joint to the world,
+    two legs (hip yaw, roll, pitch, knee, ankle), torso (waist pitch, chest
+    roll, yaw), head (neck pitch, yaw, jaw), two arms (shoulder pitch, roll,
+    upper-arm yaw, elbow, forearm roll, wrist, hand) and five three-phalanx
+    fingers per hand -- whose hip-pitch, knee, ankle, waist, chest,
+    chest-yaw, neck, jaw, elbow and wrist joints and every finger joint are each driven
+    through a crank-rod parallelogram (2 bodies, 3 revolute joints: 45
+    loops).  196 revolute joints (980 bilateral rows), no contacts.  27 tree
+    joints (base, legs, torso, head, arms except forearm roll and hand) are
+    actuated: explicit PD toward the assembled pose plus noise; the other
+    34 tree joints (forearm roll, hand, fingers) are passive spring-damper
+    couplings toward the assembled pose, solved implicitly as drive rows
+    (Sec. 3), which makes 1014 rows.
+    The 3-30 g transmission links against the 8 kg base give a mass ratio
+    of about 3e3.  Exactly on the constraint manifold."""
+    if link_masses is None:
+        link_masses = rng.uniform(0.003, 0.030, 90)
+    lm = iter(link_masses)
+    B = _Builder()
+    ident = np.array([0.0, 0.0, 0.0, 1.0])
+    xa, ya, za = np.array([1.0, 0.0, 0.0]), np.array([0.0, 1.0, 0.0]), np.array([0.0, 0.0, 1.0])
+    H = 1.35
+    tree = []  # (parent, child, point, axis, kind, actuated, looped)
+
+    def link(parent, p0, p1, mass, width, axis, kind, act, looped, joint_point=None):
+        b = _rod_body(B, p0, p1, mass, width=width)
+        K = np.asarray(p0 if joint_point is None else joint_point, np.float64)
+        if act:
+            B.joint(REVOLUTE, b, parent, K, axis, actuated=1, pd=FIGURE_PD[kind])
+        else:  # a passive spring-damper coupling, solved as an implicit drive row
+            kp, kd = FIGURE_PD[kind]
+            B.joint(REVOLUTE, b, parent, K, axis, drive=(kp, kd, 0.0, 0.0, 0.0))
+        tree.append((parent, b, K, np.asarray(axis, np.float64), looped))
+        return b
+
+    base = B.body(8.0, box_inertia(8.0, 0.30, 0.22, 0.16), (0.0, 0.0, H), ident)
+    B.joint(REVOLUTE, base, -1, (0.0, 0.0, H - 0.08), za, actuated=1, pd=FIGURE_PD["base"])
+    # legs
+    for sd in (1.0, -1.0):
+        y = 0.1 * sd
+        hy = link(base, (0, y, H - 0.08), (0, y, H - 0.14), 0.8, 0.06, za, "leg", 1, False)
+        hr = link(hy, (0, y, H - 0.14), (0, y, H - 0.20), 0.8, 0.06, xa, "leg", 1, False)
+        th = link(hr, (0, y, H - 0.20), (0, y, H - 0.62), 3.0, 0.08, ya, "leg", 1, True)
+        sh = link(th, (0, y, H - 0.62), (0, y, H - 1.02), 2.0, 0.06, ya, "leg", 1, True)
+        link(sh, (0, y, H - 1.02), (0.12, y, H - 1.08), 0.8, 0.06, ya, "leg", 1, True)
+    # torso and head
+    wa = link(base, (0, 0, H + 0.08), (0, 0, H + 0.25), 4.0, 0.2, ya, "torso", 1, True)
+    ch = link(wa, (0, 0, H + 0.25), (0, 0, H + 0.45), 5.0, 0.25, xa, "torso", 1, True)
+    uc = link(ch, (0, 0, H + 0.45), (0, 0, H + 0.60), 3.0, 0.25, za, "torso", 1, True)
+    nk = link(uc, (0, 0, H + 0.60), (0, 0, H + 0.70), 0.6, 0.06, ya, "head", 1, True)
+    hd = link(nk, (0, 0, H + 0.70), (0, 0, H + 0.88), 2.5, 0.16, za, "head", 1, False)
+    link(hd, (0.05, 0, H + 0.75), (0.12, 0, H + 0.72), 0.3, 0.05, ya, "head", 1, True)
+    # arms and hands (T-pose along +-y)
+    for sd in (1.0, -1.0):
+        y0 = 0.16 * sd
+        z = H + 0.55
+        e = np.array([0.0, sd, 0.0])
+        p = lambda d: np.array([0.0, y0, z]) + d * e
+        s1 = link(uc, p(0.0), p(0.05), 0.6, 0.07, ya, "arm", 1, False)
+        s2 = link(s1, p(0.05), p(0.10), 0.6, 0.07, xa, "arm", 1, False)
+        ua = link(s2, p(0.10), p(0.38), 2.0, 0.07, e, "arm", 1, False)
+        fa = link(ua, p(0.38), p(0.58), 1.2, 0.06, za, "arm", 1, True)
+        fr = link(fa, p(0.58), p(0.64), 0.4, 0.05, e, "arm", 0, False)
+        wr = link(fr, p(0.64), p(0.68), 0.3, 0.05, za, "arm", 1, True)
+        hand = link(wr, p(0.68), p(0.78), 0.4, 0.06, xa, "arm", 0, False)
+        for f in range(5):
+            off = np.array([0.0, 0.0, -0.03 + 0.015 * f])
+            q0 = p(0.78) + off
+            prev = hand
+            for ph in range(3):
+                a0 = q0 + (0.035 * ph) * e
+                a1 = q0 + (0.035 * (ph + 1)) * e
+                prev = link(prev, a0, a1, 0.03 - 0.006 * ph, 0.012, xa, "finger", 0, True)
+    assert len(B.mass) == 61 and len(B.jt) == 61, (len(B.mass), len(B.jt))
+    # crank-rod parallelograms across the looped tree joints
+    loops = [t for t in tree if t[4]]
+    assert len(loops) == 45, len(loops)
+    for li, (par, chi, K, a, _) in enumerate(loops):
+        d1, d2 = _perp_pair(a)
+        s_ = 0.012 * (1 if li % 2 == 0 else -1)
+        Kp = K + 0.025 * d1 + s_ * a
+        Kc = Kp + 0.035 * d2
+        Kr = K + 0.035 * d2 + s_ * a
+        crank = _rod_body(B, Kp, Kc, next(lm), width=0.008)
+        rod = _rod_body(B, Kc, Kr, next(lm), width=0.008)
+        B.joint(REVOLUTE, crank, par, Kp, a)
+        B.joint(REVOLUTE, rod, crank, Kc, a)
+        B.joint(REVOLUTE, rod, chi, Kr, a)
+    return B.scene(dt, reset_body=-1)
+
+
+def figure_batch(n_worlds, seed=1007, dt=2e-3):
+    """n_worlds identical fixed figures (transmission masses drawn once)."""
+    rng = np.random.default_rng(seed)
+    one = figure_world(rng, dt)
+    return concat([one] * n_worlds)
+
+
 def _circle_intersection(c0, r0, c1, r1, side):
     """A point at distance r0 from c0 and r1 from c1 in the x-z plane
     (y of c0), on the side of the c0->c1 line given by the sign of side."""

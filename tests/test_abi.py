@@ -39,7 +39,7 @@ def test_struct_sizes_match_the_header_layout():
     assert C.sizeof(kamx.kamx_joint_desc) == 108
     assert C.sizeof(kamx.kamx_probe_desc) == 24
     assert kamx.CONTACT_DTYPE.itemsize == 44
-    assert C.sizeof(kamx.kamx_params) == 96
+    assert C.sizeof(kamx.kamx_params) == 104
 
 
 def test_defaults_and_host_side_validation(libkamx):
@@ -48,6 +48,7 @@ def test_defaults_and_host_side_validation(libkamx):
     from paper_2603_16536_amd import kamx
     p = kamx.default_params()
     assert abs(p.dt - 2e-3) < 1e-9 and p.max_iters == 2000 and p.accel == 1
+    assert p.linear_solver == kamx.SOLVER_AUTO and p.cr_iters == 9
     h = C.c_void_p()
     rc = kamx.lib().kamx_model_create(None, 0, None, 0, None, 0, None, 0, 0, C.byref(p), C.byref(h))
     assert rc == kamx.EINVAL

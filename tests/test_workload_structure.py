@@ -81,6 +81,7 @@ def test_cyclomatic_number_on_small_graphs():
     (lambda: scenes.biped_batch(8, seed=1002), 31, 40, 0, 10),
     (lambda: scenes.excavator_batch(8, seed=1003), 12, 13, 3, 4),
     (lambda: scenes.box_bin_batch(4, seed=1005), 20, 0, 0, 0),
+    (lambda: scenes.figure_batch(2, seed=1007), 151, 196, 0, 45),
 ])
 def test_generators_build_the_stated_topology(make, bodies, revolute, prismatic, loops):
     scene = make()
@@ -94,3 +95,14 @@ def test_heterogeneous_batch_mixes_the_three_topologies():
     scene = scenes.heterogeneous_batch(12, seed=1003)
     seen = {world_topology(scene, w)[2] for w in range(scene.n_worlds)}
     assert seen == {1, 10, 4}
+
+
+def test_fixed_figure_matches_the_largest_system_of_the_table():
+    """The fixed figure has the paper's largest system's counts (Tab. 1):
+    bodies, actuated and passive joints, loops, and its base on the world."""
+    row = [r for r in read_tab1() if r[0] == "Iron_Man"][0]
+    _, nb, na, npas, loops, base = row
+    scene = scenes.figure_batch(1, seed=1007)
+    got_nb, types, cyc = world_topology(scene, 0)
+    assert base == "fixed" and np.any(scene.joint_body[:, 1] < 0)
+    assert (got_nb, int(types.sum()), int(scene.joint_actuated.sum()), cyc) == (nb, na + npas, na, loops)
