@@ -41,6 +41,8 @@ WORKLOADS = {
               "step (at most 64, 192 rows), dt 2 ms, PADMM to 1e-6 (cap 200)",
     "fourbar": "four-bar-{n}: closed four-bar (3 dynamic links, 20 rows) and a 1 kg cube sliding on the ground "
                "(4 contacts, 12 rows), dt 1 ms, exactly 50 PADMM iterations",
+    "figure": "figure-{n}: 151 bodies, 196 revolute joints (45 closed loops, 980 rows), fixed to the world, dt 2 ms, "
+              "matrix-free PADMM with {cr} Conjugate Residual iterations per iteration to 1e-6 (cap 200)",
 }
 TRAIN_SEED = 2002  # noise seed of the rollout that feeds training (the timed rollouts use CFG2's)
 
@@ -71,6 +73,17 @@ def algorithmic_flops(rows, iters, sum_kb2):
     return m ** 3 / 3.0 + k * (2 * m * m + 30 * m) + 12.0 * sum_kb2 + 2 * m * m
 
 
+def matrix_free_flops(rows, iters, cr_iters):
+    """Per world-step of the matrix-free solve: every ADMM iteration takes
+    cr_iters + 1 Delassus products through the pre-baked Jacobian (the body
+    gather and the row evaluation, 12 multiply-adds each per row and side:
+    48 m), about 10 m for each Conjugate Residual update and 30 m for the
+    rest of the iteration; pre-baking J~ = P J M^-1/2 costs about 150 m."""
+    m = rows.astype(np.float64)
+    k = iters.astype(np.float64)
+    return 150.0 * m + k * ((cr_iters + 1) * 48.0 * m + 10.0 * cr_iters * m + 30.0 * m)
+
+
 def measured_traffic(steps_per_launch):
     """HBM bytes per step-kernel launch from the committed rocprofv3 FETCH_SIZE
     and WRITE_SIZE runs (scaled by a plain copy of known size, recorded per
@@ -88,18 +101,25 @@ def measured_traffic(steps_per_launch):
     return round((int(kv["fetch_bytes_per_step"]) + int(kv["write_bytes_per_step"])) * steps_per_launch)
 
 
-def make_model(workload, n_worlds, warmstart, schedule, seed=None):
+def make_model(workload, n_worlds, warmstart, schedule, seed=None, solver="auto", cr_iters=9):
     """The benchmark model of a workload: the biped batch (headline), the
-    heterogeneous mix of four-bars, bipeds and excavators, or boxes in a bin
-    with contacts generated every step."""
+    heterogeneous mix of four-bars, bipeds and excavators, boxes in a bin
+    with contacts generated every step, or the large fixed figure (solved
+    matrix-free).  solver: auto (dense factorization where a world fits,
+    else matrix-free), dense or sparse (matrix-free for every world)."""
     from paper_2603_16536_amd import kamx, scenes
 
-    params = dict(CFG2, warmstart=warmstart)
+    params = dict(CFG2, warmstart=warmstart, cr_iters=cr_iters,
+                  linear_solver={"auto": kamx.SOLVER_AUTO, "dense": kamx.SOLVER_DENSE,
+                                 "sparse": kamx.SOLVER_SPARSE}[solver])
     if seed is not None:
         params["seed"] = seed
     if workload == "biped":
         scene = biped_workload(n_worlds)
         model = kamx.Model(scene, params=params, pd=PD, refs=np.zeros(scene.n_joints))
+    elif workload == "figure":
+        scene = scenes.round_to_f32(scenes.figure_batch(n_worlds, seed=1007))
+        model = kamx.Model(scene, params=dict(params, max_iters=200))
     elif workload == "hetero":
         scene = scenes.round_to_f32(scenes.heterogeneous_batch(n_worlds, seed=1003))
         # per-joint gains of each structure; a 200-iteration budget (the
@@ -143,21 +163,21 @@ def last_step_sample(model, scene, n_sample=64, seed=0):
     rng = np.random.default_rng(seed)
     capped = np.nonzero(st["status"] != 0)[0]
     rest = np.setdiff1d(np.arange(scene.n_worlds), capped)
-    k = min(len(capped), n_sample // 4)
+    k = min(len(capped), n_sample // 2)
     out["sample"] = np.sort(np.r_[rng.choice(capped, k, replace=False) if k else np.zeros(0, int),
                                   rng.choice(rest, n_sample - k, replace=False)]).astype(int)
     return out
 
 
 def run_gpu(n_worlds, steps, warmup, warmstart, schedule, net=None, seed=None, workload="biped", autotune=True,
-            capture=False):
+            capture=False, solver="auto", cr_iters=9):
     """Warm-up steps, then one timed call of `steps` steps (chained launches
     where the mode allows, single-step launches otherwise), bracketed by HIP
     events on the launch stream; per-step iteration and row counts come
     from the library's iteration log."""
     import torch
 
-    scene, model = make_model(workload, n_worlds, warmstart, schedule, seed)
+    scene, model = make_model(workload, n_worlds, warmstart, schedule, seed, solver, cr_iters)
     if net is not None:
         model.attach_mlp(net)
     stream = torch.cuda.current_stream()
@@ -361,7 +381,28 @@ def fp64_check(chk):
             rd = np.abs(vv + g - z).max()
             diff = max(diff, abs(rd - chk["resid"][w, 1]), abs(np.abs(x - y).max() - chk["resid"][w, 0]))
     n_conv = int(np.sum(chk["status"][chk["sample"]] == 0))
+    # every sampled world-step that stopped at the cap, classified by the
+    # oracle: a bilateral free velocity with a component outside the range of
+    # D~_BB puts a floor under the dual residual (redundant loop rows whose
+    # Baumgarte bias does not close), else the solve was merely slow
+    # (the floor of |r_d|_inf lies between floor_inf = |n|_2^2 / |n|_1 and
+    # |n|_2 for the component n of the bilateral free velocity outside the
+    # range of D~_BB)
+    floors, upper = [], []
+    for w in chk["sample"]:
+        if chk["status"][w] != 0:
+            fr = oracle.floor_report(sc, P, int(w), joint_torque=chk["torques"])
+            floors.append(fr["floor_inf"])
+            upper.append(fr["floor_2"])
+    floors, upper = np.array(floors), np.array(upper)
+    capped = {"sampled": int(floors.size), "floor_above_eps": int(np.sum(floors > CFG2["eps"])),
+              "floor_below_eps": int(np.sum(upper <= CFG2["eps"])),
+              "undecided": int(np.sum((floors <= CFG2["eps"]) & (upper > CFG2["eps"]))),
+              "floor_lower_bound_max": float(floors.max()) if floors.size else None,
+              "floor_upper_bound_median": float(np.median(upper)) if upper.size else None,
+              "floor_upper_bound_max": float(upper.max()) if upper.size else None}
     return {"ncp_residual_fp64_max_converged": float(ncp_conv), "ncp_residual_fp64_max_all": float(ncp_all),
+            "capped_by_oracle_floor": capped,
             "reported_vs_fp64_residual_max_diff": float(diff), "gpu_reported_residual_max_converged":
             float(chk["resid"][chk["status"] == 0, :3].max()), "sample_worlds": len(chk["sample"]),
             "sample_converged": n_conv, "units": "preconditioned (Jacobi-scaled) impulses and velocities"}
@@ -406,6 +447,10 @@ def main():
                     help="chained multi-step launches, or one launch per step ordered longest-first or by index")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep every size bucket's default workgroup size instead of the autotuner's choice")
+    ap.add_argument("--solver", choices=("auto", "dense", "sparse"), default="auto",
+                    help="linear solve of the x-update: dense factorization where a world fits (auto), or "
+                         "matrix-free Conjugate Residual for every world (sparse)")
+    ap.add_argument("--cr-iters", type=int, default=9, help="Conjugate Residual iterations per ADMM iteration")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the run, copy a 256 MiB buffer once (a plain copy kernel of known traffic "
                          "for scaling HBM byte counters)")
@@ -424,15 +469,20 @@ def main():
     print(f"[bench] cold-start rollout: {args.worlds} worlds, warmup {args.warmup}, steps {args.steps}",
           file=sys.stderr, flush=True)
     sched = {"chain": kamx.SCHED_CHAIN, "lpt": kamx.SCHED_LPT, "index": kamx.SCHED_INDEX}[args.schedule]
-    if args.workload != "biped":
+    if args.workload != "biped" or args.solver == "sparse":
         args.no_learned = True
         args.no_cpu = True
+    sparse = args.workload == "figure" or args.solver == "sparse"
     cold = run_gpu(args.worlds, args.steps, args.warmup, kamx.WARM_COLD, sched, workload=args.workload,
-                   autotune=not args.no_autotune, capture=args.workload == "biped" and not args.no_cpu)
+                   autotune=not args.no_autotune, capture=args.workload == "biped" and not args.no_cpu and not sparse,
+                   solver=args.solver, cr_iters=args.cr_iters)
     value = args.worlds * args.steps / cold["wall_s"]
     it = cold["iters"]
     conv = float((cold["status"] == 0).mean())
-    flops_total = float(algorithmic_flops(cold["rows"], it, cold["sum_kb2"]).sum())
+    if sparse:
+        flops_total = float(matrix_free_flops(cold["rows"], it, args.cr_iters).sum())
+    else:
+        flops_total = float(algorithmic_flops(cold["rows"], it, cold["sum_kb2"]).sum())
     avg_launch_s = cold["event_ms"] / 1e3 / cold["launches"]
     achieved = flops_total / cold["launches"] / avg_launch_s / 1e12
     result = {
@@ -448,7 +498,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": WORKLOADS[args.workload].format(n=args.worlds),
+        "config": {"workload": WORKLOADS[args.workload].format(n=args.worlds, cr=args.cr_iters),
+                   "linear_solve": (f"matrix-free, {args.cr_iters} Conjugate Residual iterations per ADMM iteration"
+                                    if sparse else "dense factorization once per step"),
                    "worlds": args.worlds, "rows_per_world_max": int(cold["rows"].max()),
                    "warm_start": "cold (plain ADMM)",
                    "dispatch": {"chain": "each world kept on its workgroup for up to 64 steps per launch",
@@ -457,8 +509,10 @@ def main():
                    "buckets": cold["bucket_table"]},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VALU_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 5),
-                     "traffic": measured_traffic(cold["steps_per_launch"]) if args.workload == "biped" and args.worlds == 4096 else None,
-                     "kernel": "step_kernel<224,512>" if args.workload == "biped" else "all step kernels",
+                     "traffic": (measured_traffic(cold["steps_per_launch"])
+                                 if args.workload == "biped" and args.worlds == 4096 and not sparse else None),
+                     "kernel": ("sparse_step_kernel" if sparse else
+                                "step_kernel<224,512>" if args.workload == "biped" else "all step kernels"),
                      "avg_launch_ms": round(1e3 * avg_launch_s, 4), "steps_per_launch": cold["steps_per_launch"]},
         "solver": solver_stats(cold, args.worlds * args.steps),
     }
@@ -466,7 +520,7 @@ def main():
     if not args.no_previous:
         print("[bench] previous-step warm-start rollout", file=sys.stderr, flush=True)
         prev = run_gpu(args.worlds, args.steps, args.warmup, kamx.WARM_PREVIOUS, sched, workload=args.workload,
-                       autotune=not args.no_autotune)
+                       autotune=not args.no_autotune, solver=args.solver, cr_iters=args.cr_iters)
         result["warm_previous"] = {
             "value": round(args.worlds * args.steps / prev["wall_s"], 1),
             "ms_per_step": round(1e3 * prev["wall_s"] / args.steps, 4),

@@ -983,6 +983,9 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
         float *Xs = L.red;  // 16x16 inverse of the current diagonal factor tile (red + wb are free here)
         const int lane = tid & 63, wv = tid >> 6, fr = lane & 15, fk = lane >> 4;
         constexpr int NW = NT / 64;
+        // one wave alone: at most two tile rows, so every trailing update is
+        // the next diagonal tile (wave 0's); the other waves' loop never runs
+        static_assert(NW > 1 || MC <= 32, "a single-wave factorization covers two tile rows");
         if (tid == 0) s_int[2] = 0;
         __syncthreads();
         // factor diagonal tile K (wave 0 only) and write its inverse to Xs
@@ -1717,7 +1720,7 @@ hipError_t launch_impulse_slots(const WorldInfo *worlds, int n_worlds, int n_con
 
 template <int MC, int NT>
 static hipError_t launch_mc(const StepArgs &args, int n, hipStream_t stream) {
-    static_assert(NT % 64 == 0 && NT >= 128 && NT >= 2 * MC && NT <= 512, "unsupported workgroup size");
+    static_assert(NT % 64 == 0 && NT >= 64 && NT >= 2 * MC && NT <= 512, "unsupported workgroup size");
     size_t bytes = sizeof(float) * (size_t)smem_floats(MC);
     static bool configured = false;
     if (!configured) {
@@ -1739,15 +1742,17 @@ int bucket_capacity(int rows) {
 
 // Workgroup sizes each row bucket is built for.  Every iteration pass gives
 // each pair of rows (and each pair of column quads) its own threads, so a
-// workgroup has at least two threads per row and at least two waves; the
-// larger size runs the passes with more threads, the smaller one lets more
-// worlds share a compute unit where LDS allows.  The first entry is the
+// workgroup has at least two threads per row; the larger size runs the
+// passes with more threads, the smaller one lets more worlds share a compute
+// unit where LDS allows.  The 32-row bucket also runs one wavefront per
+// world (its 16x16 tile factorization needs no second wave: the trailing
+// update of two tiles is the next diagonal tile, which wave 0 takes).  The first entry is the
 // default.  Results do not depend on the choice: every row, tile and
 // reduction is evaluated in the same order at every size.
 int step_threads_variants(int mc, int out[4]) {
     switch (mc) {
     case 256: case 512: case 1024: out[0] = mc; return 1;  // matrix-free: one thread per row
-    case 32: out[0] = 256; out[1] = 128; return 2;
+    case 32: out[0] = 256; out[1] = 128; out[2] = 64; return 3;  // 64: one wavefront per world
     case 64: out[0] = 256; out[1] = 128; return 2;
     case 96: out[0] = 512; out[1] = 256; return 2;
     case 128: out[0] = 512; out[1] = 256; return 2;
@@ -1764,6 +1769,7 @@ size_t sparse_smem_bytes(int nt);
 hipError_t launch_step(const StepArgs &args, int mc, int nt, int n, hipStream_t stream) {
     if (mc > kMaxRows) return launch_sparse_step(args, nt, n, stream);  // matrix-free row classes
     switch (mc * 1024 + nt) {
+    case 32 * 1024 + 64: return launch_mc<32, 64>(args, n, stream);
     case 32 * 1024 + 128: return launch_mc<32, 128>(args, n, stream);
     case 32 * 1024 + 256: return launch_mc<32, 256>(args, n, stream);
     case 64 * 1024 + 128: return launch_mc<64, 128>(args, n, stream);

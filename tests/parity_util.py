@@ -16,7 +16,8 @@ def oracle_params(p: "kamx.kamx_params", **over):
     return P.replace(**over)
 
 
-def gpu_step(scene, params, explicit_contacts=True, ext=None, max_contacts=None, warm=None, setup=None):
+def gpu_step(scene, params, explicit_contacts=True, ext=None, max_contacts=None, warm=None, setup=None,
+             after=None):
     """One step of every world on the GPU.  Returns numpy outputs, the
     contacts the library used (for checking its own contact generation) and
     the inputs the oracle needs to rebuild the step on its side."""
@@ -47,8 +48,28 @@ def gpu_step(scene, params, explicit_contacts=True, ext=None, max_contacts=None,
     out["used_scene"] = kamx.contacts_to_scene(scene, raw, cnt)
     out["inputs"] = dict(ext=None if ext is None else np.asarray(ext, np.float64), explicit=explicit_contacts,
                          step=0, pd=None, refs=None)
+    if after is not None:
+        after(model, out)  # e.g. reading what the step used before the model goes
     model.close()
     return out
+
+
+def slots_to_rows(pred, model, scene):
+    """Impulses by slot (joint rows, then three slots per contact key) put on
+    the rows of the contacts the model's last step used (host mapping)."""
+    raw, cnt = model.contacts()
+    used = kamx.contacts_to_scene(scene, raw, cnt)
+    nj = scene.joint_offsets()
+    ro = model.row_offsets
+    lam = np.zeros(int(ro[-1]), np.float32)
+    co = used.contact_offsets()
+    for w in range(scene.n_worlds):
+        rc0 = 5 * (nj[w + 1] - nj[w])
+        lam[ro[w]:ro[w] + rc0] = pred[w, :rc0]
+        for c in range(co[w], co[w + 1]):
+            k = int(used.contact_key[c])
+            lam[ro[w] + rc0 + 3 * (c - co[w]):ro[w] + rc0 + 3 * (c - co[w]) + 3] = pred[w, rc0 + 3 * k:rc0 + 3 * k + 3]
+    return lam, used
 
 
 def oracle_torques(scene, params, w, ext=None, step=0, pd=None, refs=None):
@@ -224,10 +245,22 @@ def oracle_inputs(scene, params, g, worlds, inputs=None):
     so, go = sub.contact_offsets(), gsub.contact_offsets()
     perms = []
     match = []
+    own = []  # worlds whose oracle-side contact set differs: they take the GPU's
     for k in range(len(worlds)):
         kk = sub.contact_key[so[k]:so[k + 1]]
         gk = gsub.contact_key[go[k]:go[k + 1]]
-        assert np.array_equal(np.sort(gk), np.sort(kk)), f"contact sets differ in world {worlds[k]}"
+        if not np.array_equal(np.sort(gk), np.sort(kk)):
+            # a vertex within rounding of a face edge or of the margin is kept
+            # (or dropped) by one side only: the two steps have different
+            # inputs.  The oracle then solves the GPU's contact set (FP32
+            # geometry) so the solve is still compared, and the world is
+            # flagged as not matching the oracle's own contact generation.
+            print(f"  contact sets differ in world {worlds[k]}: GPU {len(gk)} contacts, oracle {len(kk)}; "
+                  f"the oracle takes the GPU's", flush=True)
+            own.append(k)
+            perms.append(list(range(len(gk))))
+            match.append(False)
+            continue
         g_of_key = {int(x): i for i, x in enumerate(gk)}
         perm = [g_of_key[int(x)] for x in kk]
         perms.append(perm)
@@ -241,17 +274,39 @@ def oracle_inputs(scene, params, g, worlds, inputs=None):
                   np.abs(sub.contact_point[a] - gsub.contact_point[b]).max() < 1e-5 and
                   np.array_equal(sub.contact_body[a] - sub.body_offsets()[k], gsub.contact_body[b] - gsub.body_offsets()[k]))
         match.append(bool(ok))
+    if own:
+        from paper_2603_16536_amd import scenes as _scenes
+        sub = _scenes.concat([gsub._one(k) if k in own else sub._one(k) for k in range(len(worlds))],
+                             gravity=sub.gravity, dt=sub.dt, reset_height=sub.reset_height)
     tau = np.concatenate([oracle_torques(scene, params, int(w), ext=inp.get("ext"), step=inp.get("step", 0),
                                          pd=inp.get("pd"), refs=inp.get("refs")) for w in worlds] or [np.zeros(0)])
     return sub, perms, tau, match
 
 
-def fp64_residuals_at_iterate(S, it, kind, mu):
+def fp32_jacobian_system(S):
+    """D and v_f of a world built from its Jacobian rounded to FP32 (the
+    GPU forms J in FP32 from FP64 geometry), in FP64 arithmetic: the problem
+    the GPU solves, up to the rounding of its other inputs."""
+    J32 = S["J"].astype(np.float32).astype(np.float64)
+    nb = S["Minv"].shape[0]
+    Mi = np.zeros((6 * nb, 6 * nb))
+    for b in range(nb):
+        Mi[6 * b:6 * b + 6, 6 * b:6 * b + 6] = S["Minv"][b]
+    D = J32 @ Mi @ J32.T + np.diag(S["R"])
+    vf = J32 @ S["uf"] + S["vstar"]
+    return D, vf
+
+
+def fp64_residuals_at_iterate(S, it, kind, mu, rounded_jacobian=True):
     """r_p, r_d, r_c (Alg. 1 step 9, in preconditioned units) evaluated in
-    FP64 at the GPU's returned iterate (x~, y~, z~) with the GPU's scales p
-    and the oracle's D and v_f."""
+    FP64 at the GPU's returned iterate (x~, y~, z~) with the GPU's scales p,
+    on the problem built from the FP32-rounded Jacobian (default) or on the
+    oracle's FP64 D and v_f.  (On an active limit or contact the
+    complementarity term y (v~ + Gamma) multiplies the velocity by the
+    impulse, so the 1e-7 relative rounding of J alone moves it by about
+    |y| 1e-6 between the two problems.)"""
     x, y, z, p = it[:, 0], it[:, 1], it[:, 2], it[:, 3]
-    D, vf = S["D"], S["vf"]
+    D, vf = fp32_jacobian_system(S) if rounded_jacobian else (S["D"], S["vf"])
     v = p * (D @ (p * x)) + p * vf
     m = len(x)
     g = np.zeros(m)
@@ -275,7 +330,7 @@ def fp64_residuals_at_iterate(S, it, kind, mu):
 
 
 def compare_worlds(scene, params, g, worlds, mode="reference", oracle_over=None, warm=None, inputs=None,
-                   log_iters=None):
+                   log_iters=None, tol_run=False):
     """Run the oracle on ``worlds`` (one OpenMP call) and compare each world
     with the GPU step in ``g``.
 
@@ -290,7 +345,12 @@ def compare_worlds(scene, params, g, worlds, mode="reference", oracle_over=None,
     of the GPU impulses, the GPU's reported residuals next to their FP64
     values at its returned iterate, and (when the GPU logged them) the
     first iteration at which its restart decisions differ from the oracle's
-    own (0: never within the shorter run)."""
+    own (0: never within the shorter run).
+
+    tol_run (reference mode): the oracle also runs from the same start to
+    the GPU's own tolerance and cap; e_imp_tol and e_mom_tol are that
+    solve's distance from the reference, the distance the tolerance alone
+    allows on this world (FP64, no FP32 rounding)."""
     worlds = [int(w) for w in worlds]
     sub, perms, tau, match = oracle_inputs(scene, params, g, worlds, inputs)
     over = dict(oracle_over or {})
@@ -310,6 +370,10 @@ def compare_worlds(scene, params, g, worlds, mode="reference", oracle_over=None,
         ro = g["row_offsets"]
         ws_sub = np.concatenate([np.asarray(warm, np.float64)[ro[w]:ro[w + 1]] for w in worlds])
     results = [None] * len(worlds)
+    tol_results = None
+    if tol_run and mode == "reference":
+        tol_results = compare_worlds(scene, params, g, worlds, mode="same", oracle_over=oracle_over, warm=warm,
+                                     inputs=inputs)
     for n, ks in groups.items():
         o = dict(over)
         if n is not None:
@@ -376,6 +440,19 @@ def compare_worlds(scene, params, g, worlds, mode="reference", oracle_over=None,
         if "iterate" in g:
             it = g["iterate"][r0:r0 + m][rowperm]
             res["fp64_resid"] = fp64_residuals_at_iterate(S, it, kind, mu)
+            res["fp64_resid_j64"] = fp64_residuals_at_iterate(S, it, kind, mu, rounded_jacobian=False)
+        if tol_results is not None:
+            t = tol_results[k]["ref"]
+            imp_t = S["J"].T @ t["lam"]
+            du = (t["u"] - ref["u"]).reshape(-1, 6)
+            mom_t = np.zeros_like(du)
+            for j, b in enumerate(range(b0, b1)):
+                R = scenes.quat_to_mat(scene.q[b, 3:])
+                mom_t[j, :3] = scene.body_mass[b] * du[j, :3]
+                mom_t[j, 3:] = R @ (scene.body_inertia[b] * (R.T @ du[j, 3:]))
+            res["e_imp_tol"] = np.abs(imp_t - imp_o).max() / max(np.abs(imp_o).max(), floor_imp)
+            res["e_mom_tol"] = np.abs(mom_t).max() / max(np.abs(imp_o).max(), floor_imp)
+            res["tol_iters"] = int(t["iters"])
         if mode != "replay" and ref.get("restart_log") is not None and "restart_log" in g:
             n = min(res["iters"], ref["iters"], len(ref["restart_log"]))
             a, b = g["restart_log"][w, :n], ref["restart_log"][:n]
@@ -386,10 +463,25 @@ def compare_worlds(scene, params, g, worlds, mode="reference", oracle_over=None,
     return out
 
 
+def within_tolerance_bound(rs, tol, factor=4.0):
+    """Per world, the GPU's J^T lambda and momentum-weighted u+ errors
+    against the reference, each within max(tol, factor x the distance the
+    oracle's own solve at the same tolerance keeps from it); returns the
+    worst ratio error / bound over the two."""
+    worst = 0.0
+    for r in rs:
+        for e, et in (("e_imp", "e_imp_tol"), ("e_mom", "e_mom_tol")):
+            worst = max(worst, r[e] / max(tol, factor * r[et]))
+    return worst
+
+
 def summary(name, rs):
     e = np.array([[r["e_u"], r["e_imp"], r["e_lam"], r["e_mom"], r["r_ncp"]] for r in rs])
     line = (f"\n{name}: max rel err u+ {e[:, 0].max():.2e}  J^T lambda {e[:, 1].max():.2e}  lambda {e[:, 2].max():.2e}"
             f"  momentum-weighted u+ {e[:, 3].max():.2e}  FP64 r_ncp of GPU lambda {e[:, 4].max():.2e}")
+    if all("e_imp_tol" in r for r in rs):
+        line += (f"\n  the oracle's own solve at the GPU's tolerance, from the reference: J^T lambda max "
+                 f"{max(r['e_imp_tol'] for r in rs):.2e}, momentum-weighted u+ max {max(r['e_mom_tol'] for r in rs):.2e}")
     if all("fp64_resid" in r for r in rs):
         gr = np.array([r["gpu_resid"][:3] for r in rs])
         fr = np.array([r["fp64_resid"] for r in rs])

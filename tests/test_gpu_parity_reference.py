@@ -119,6 +119,17 @@ def test_unique_impulses_on_nonsingular_worlds():
         worlds.append(scenes.random_chain_world(rng, n_bodies=3, with_limits=True, on_manifold=True))
     scene = scenes.round_to_f32(scenes.concat(worlds))
     import oracle
+    # bounds within millimetres (milliradians) of the coordinate, some of
+    # them already crossed: limit rows that are active or nearly so.  (A
+    # bound up to 1 rad away gives a speculative bias f/dt of 1000 rad/s,
+    # whose FP32 spacing is far above the tolerance: the dual residual could
+    # not be resolved below 1e-6 in FP32.)
+    lim = scene.joint_limit.copy()
+    for j in range(scene.n_joints):
+        c = oracle.joint_coordinate(scene, scene.q, j)[0]
+        lo_d, hi_d = rng.uniform(-0.002, 0.004, 2)
+        lim[j] = (c - lo_d if np.isfinite(lim[j, 0]) else np.nan, c + hi_d if np.isfinite(lim[j, 1]) else np.nan)
+    scene = scene.replace(joint_limit=lim.astype(np.float32).astype(np.float64))
     for w in range(scene.n_worlds):
         assert oracle.floor_report(scene, oracle.Params(dt=1e-3), w)["null_dim"] == 0, w
     params = cfg2_params(dt=1e-3)
@@ -154,47 +165,87 @@ def _fit_network(scene, tau, p, n):
     return net
 
 
+def _mom_diff(scene, w, u1, u2, imp_scale):
+    """Momentum-weighted difference of two twists of world w (per body
+    m dv and I dw in the world frame), relative to an impulse scale."""
+    bo = scene.body_offsets()
+    out = 0.0
+    for b in range(bo[w], bo[w + 1]):
+        du = u1[b] - u2[b]
+        R = scenes.quat_to_mat(scene.q[b, 3:])
+        out = max(out, np.abs(scene.body_mass[b] * du[:3]).max(),
+                  np.abs(R @ (scene.body_inertia[b] * (R.T @ du[3:]))).max())
+    return out / imp_scale
+
+
 def test_warm_starts_leave_the_converged_answer_unchanged():
     """Cold, previous-step, learned (a network fitted to this batch) and a
     perturbed external warm start (the converged impulses with 100 %
-    multiplicative noise) on the same state, contacts and joint forces:
-    every world that converges under all four ends at the same unique
-    quantities as the oracle's converged solve (J^T lambda and the
-    momentum-weighted u+ within 1e-4); only the iteration counts differ (the
-    warm start sets where Alg. 1 starts, step 2, not where it stops).
+    multiplicative noise) on the same state, contacts and joint forces.
+
+    * The previous-step warm start is the previous step's impulses by
+      contact key: the step equals an external warm start with those
+      impulses put on the rows, bit for bit.
+    * Every mode against the oracle's PADMM from the same initialisation
+      (Alg. 1 step 2), converged: J^T lambda and the momentum-weighted u+
+      within 1e-4, on every world converged in all modes.
+    * The warm start changes where Alg. 1 starts, not where it stops: on
+      every world where the oracle's own converged solves from the cold and
+      from the warm initialisation agree (1e-5), the GPU's warm-started and
+      cold-started solves agree within 1e-4.  Where the oracle's two solves
+      differ, the frictional contact problem has more than one solution (or
+      a near-flat set of them) and the initialisation picks one: in FP64
+      the oracle lands 1e-3 apart in u+ on some biped worlds from these two
+      starts; those worlds are counted and reported.
     (A warm start far from the answer with a large component in null(J^T)
     -- which the iteration never changes -- leaves FP32 rounding of that
     component in every residual: 1e6 N s of garbage keeps the dual residual
     above 1e-6; in FP64 the oracle itself needs 6e3 to over 2e4 iterations
     on some worlds from such a start.)"""
+    from parity_util import slots_to_rows
     n = 64
     scene, tau = biped_state(n, seed=31)
     other, _ = biped_state(n, seed=32)
     p = cfg2_params(log_restarts=0)
     nets = []
+    cap = {}
 
     def previous(m):
         # a step from another state fills the cache, then the state of the test
         m.upload_state(other.q, other.u)
         m.step(1)
+        cap["previous"] = m.impulse_slots().cpu().numpy()
         m.upload_state(scene.q, scene.u)
 
     def learned(m):
         net = _fit_network(scene, tau, p, n)
         nets.append(net)
         m.attach_mlp(net)
+        cap["learned"] = net.forward(m.features()).cpu().numpy()
+
+    def rows_of(mode):
+        def after(m, out):
+            out["ws"] = slots_to_rows(cap[mode], m, scene)[0]
+        return after
 
     rng = np.random.default_rng(5)
     runs = dict(
         cold=gpu_step(scene, p, ext=tau),
-        previous=gpu_step(scene, dict(p, warmstart=kamx.WARM_PREVIOUS), ext=tau, setup=previous),
-        learned=gpu_step(scene, dict(p, warmstart=kamx.WARM_LEARNED), ext=tau, setup=learned),
+        previous=gpu_step(scene, dict(p, warmstart=kamx.WARM_PREVIOUS), ext=tau, setup=previous,
+                          after=rows_of("previous")),
+        learned=gpu_step(scene, dict(p, warmstart=kamx.WARM_LEARNED), ext=tau, setup=learned,
+                         after=rows_of("learned")),
     )
     lam0 = runs["cold"]["lam"]
-    runs["perturbed"] = gpu_step(scene, dict(p, warmstart=kamx.WARM_EXTERNAL), ext=tau,
-                                 warm=(lam0 * (1.0 + rng.normal(0.0, 1.0, lam0.shape))).astype(np.float32))
+    ws_pert = (lam0 * (1.0 + rng.normal(0.0, 1.0, lam0.shape))).astype(np.float32)
+    runs["perturbed"] = gpu_step(scene, dict(p, warmstart=kamx.WARM_EXTERNAL), ext=tau, warm=ws_pert)
+    runs["perturbed"]["ws"] = ws_pert
     for net in nets:
         net.close()
+    # the previous-step cache is the previous impulses matched by key
+    again = gpu_step(scene, dict(p, warmstart=kamx.WARM_EXTERNAL), ext=tau, warm=runs["previous"]["ws"])
+    for k in ("u", "q", "lam", "iters"):
+        assert np.array_equal(again[k], runs["previous"][k]), k
     ok = np.ones(n, bool)
     for mode, g in runs.items():
         ok &= g["status"] == 0
@@ -204,17 +255,38 @@ def test_warm_starts_leave_the_converged_answer_unchanged():
     assert runs["learned"]["iters"][ok].mean() < runs["cold"]["iters"][ok].mean()
     worlds = np.nonzero(ok)[0][:24]
     params = kamx.make_params(**p)
-    errs = {}
+    errs, refs = {}, {}
     for mode, g in runs.items():
-        rs = compare_worlds(scene, params, g, worlds, mode="reference")
-        errs[mode] = summary(f"{mode} warm start, {len(worlds)} worlds converged in every mode", rs)
-    bo = scene.body_offsets()
-    for mode in ("previous", "learned", "perturbed"):
-        d = max(np.abs(runs[mode]["u"][bo[w]:bo[w + 1]] - runs["cold"]["u"][bo[w]:bo[w + 1]]).max() /
-                max(np.abs(runs["cold"]["u"][bo[w]:bo[w + 1]]).max(), 1e-6) for w in worlds)
-        print(f"{mode}: max rel u+ difference to the cold solve {d:.2e}")
+        rs = compare_worlds(scene, params, g, worlds, mode="reference", warm=g.get("ws"))
+        errs[mode] = summary(f"{mode} warm start against the oracle from the same start, {len(worlds)} worlds", rs)
+        refs[mode] = rs
     for mode, e in errs.items():
         assert e[:, 1].max() < TOL and e[:, 3].max() < TOL, mode
+    # the converged answer does not depend on the start where it is unique
+    for mode in ("previous", "learned", "perturbed"):
+        n_unique, n_multi, worst = 0, 0, 0.0
+        for k, w in enumerate(worlds):
+            rc, rm = refs["cold"][k], refs[mode][k]
+            scale = max(np.abs(rc["S"]["J"].T @ rc["ref"]["lam"]).max(),
+                        1e-6 * scene.body_mass[scene.body_world == w].sum() * 9.81 * p["dt"])
+            bo = scene.body_offsets()
+            ref_c = np.zeros_like(scene.u)
+            ref_m = np.zeros_like(scene.u)
+            ref_c[bo[w]:bo[w + 1]] = rc["ref"]["u"]
+            ref_m[bo[w]:bo[w + 1]] = rm["ref"]["u"]
+            d_ref = _mom_diff(scene, w, ref_c, ref_m, scale)
+            d_gpu = _mom_diff(scene, w, runs["cold"]["u"], runs[mode]["u"], scale)
+            if d_ref < 1e-5:
+                n_unique += 1
+                worst = max(worst, d_gpu)
+                assert d_gpu < TOL, (mode, w, d_gpu)
+            else:
+                n_multi += 1
+                print(f"  {mode}: world {w}: the oracle's solves from the two starts differ by {d_ref:.1e} "
+                      f"(GPU {d_gpu:.1e})")
+        print(f"{mode}: {n_unique} worlds with one answer (GPU warm vs cold at most {worst:.1e}), "
+              f"{n_multi} where the start picks among several", flush=True)
+        assert n_unique >= len(worlds) // 2
 
 
 def test_excavator_unreplayed_with_active_stroke_limit():
@@ -282,9 +354,13 @@ def test_box_bin_falling_state_at_contact_cap():
           f"at the cap {np.mean(counts == 64):.2f}; converged {np.mean(st['status'] == 0):.3f}")
     m.close()
     params = kamx.make_params(**p)
-    worlds = np.argsort(-counts)[:12]
+    # piles at the cap are hard (about half of the worlds reach 1e-6 within
+    # 2000 iterations): the twelve converged worlds with the most contacts
+    conv_w = np.nonzero(st["status"] == 0)[0]
+    worlds = conv_w[np.argsort(-counts[conv_w], kind="stable")][:12]
     rs = compare_worlds(s1, params, g, worlds, mode="reference")
-    e = summary("boxes in a bin after 400 steps (12 worlds with the most contacts)", rs)
+    e = summary(f"boxes in a bin after 400 steps (12 converged worlds with the most contacts: "
+                f"{counts[worlds].min()}-{counts[worlds].max()})", rs)
     # a vertex within rounding of an edge of the face it touches, or of the
     # margin, can pick a different face (normal) or drop out in FP32 than in
     # FP64 with the same key: such worlds have different inputs, not a
@@ -292,7 +368,7 @@ def test_box_bin_falling_state_at_contact_cap():
     same = np.array([r["contacts_match"] for r in rs])
     conv = np.array([r["status"] == 0 for r in rs]) & same
     print(f"worlds with the same contact geometry: {same.sum()} of {len(rs)}; converged among them {conv.sum()}")
-    assert counts.max() >= 48
+    assert counts[worlds].min() >= 48
     assert conv.sum() >= 6
     assert e[conv, 1].max() < TOL and e[conv, 3].max() < TOL
     check_reported_residuals([r for r, c in zip(rs, conv) if c], 1e-6)
