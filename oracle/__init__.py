@@ -43,6 +43,7 @@ class _Params(C.Structure):
         ("restart_factor", C.c_double), ("precond", C.c_int32), ("baumgarte", C.c_double),
         ("warmstart", C.c_int32), ("replay", C.c_int32), ("log_stride", C.c_int32),
         ("integrator", C.c_int32), ("cr_iters", C.c_int32),
+        ("adapt_ratio", C.c_double), ("adapt_factor", C.c_double), ("adapt_first", C.c_int32),
     ]
 
 
@@ -86,6 +87,12 @@ class Params:
     warmstart: int = 0
     integrator: int = 0  # 0 semi-implicit Euler, 1 Moreau-Jean midpoint (Sec. 3)
     cr_iters: int = 0    # 0 Cholesky; > 0 Conjugate Residual iterations per x-update (Sec. 5.1)
+    # adaptive penalty on limit and contact rows (not in the paper; residual
+    # balancing): 0 = off, else the ratio tau of r_d and r_p that triggers a
+    # change by adapt_factor at iterations adapt_first * 2^j
+    adapt_ratio: float = 0.0
+    adapt_factor: float = 5.0
+    adapt_first: int = 100
 
     def replace(self, **kw):
         return dataclasses.replace(self, **kw)
@@ -101,6 +108,7 @@ class Params:
         p.warmstart, p.replay, p.log_stride = self.warmstart, replay, log_stride
         p.integrator = self.integrator
         p.cr_iters = self.cr_iters
+        p.adapt_ratio, p.adapt_factor, p.adapt_first = self.adapt_ratio, self.adapt_factor, self.adapt_first
         return p
 
 

@@ -77,6 +77,10 @@ typedef struct {
     int32_t integrator;    /* 0 semi-implicit Euler, 1 Moreau-Jean midpoint */
     int32_t cr_iters;      /* 0: Cholesky; > 0: that many Conjugate Residual
                               iterations per x-update (Sec. 5.1)          */
+    double adapt_ratio;    /* > 0: adaptive penalty on limit and contact
+                              rows (residual balancing, see the solver)   */
+    double adapt_factor;   /* factor of one penalty change                 */
+    int32_t adapt_first;   /* first checkpoint iteration (then doubling)   */
 } orc_params;
 
 typedef struct {
@@ -920,6 +924,8 @@ int orc_solve_ncp(int m, const double *D, const double *vf, const int *kind, con
     double a_k = 1.0;
     double c_prev = INFINITY;
     int N = P->fixed_iters > 0 ? P->fixed_iters : P->max_iters;
+    int n_uni = 0; /* limit and contact rows: the rows an adaptive penalty acts on */
+    for (int i = 0; i < m; ++i) n_uni += kind[i] != ORC_ROW_BILATERAL;
     int it = 0;
     double rp = INFINITY, rd = INFINITY, rc = INFINITY;
     int converged = 0;
@@ -984,7 +990,7 @@ int orc_solve_ncp(int m, const double *D, const double *vf, const int *kind, con
                 c += rho[i] * dy * dy + dz * dz / rho[i];
             }
             int restart;
-            if (P->replay && replay_log) restart = replay_log[it - 1] != 0;
+            if (P->replay && replay_log) restart = (replay_log[it - 1] & 1) != 0;
             else restart = !(c < P->restart_factor * c_prev);
             /* the log holds log_stride decisions per world (0: as many as iterations) */
             if (log_out && (P->log_stride <= 0 || it <= P->log_stride)) log_out[it - 1] = (uint8_t)restart;
@@ -1026,6 +1032,42 @@ int orc_solve_ncp(int m, const double *D, const double *vf, const int *kind, con
         if (P->fixed_iters <= 0 && rp < P->eps && rd < P->eps && rc < P->eps) {
             converged = 1;
             break;
+        }
+        /* Adaptive penalty on the limit and contact rows (not in the paper,
+         * whose penalty is fixed: residual balancing after Boyd, Parikh, Chu,
+         * Peleato and Eckstein 2011, Sec. 3.4.1, here on the unilateral rows'
+         * share of a per-row penalty).  At the checkpoint iterations
+         * first, 2 first, 4 first, ...: when r_d > tau r_p the unilateral
+         * penalty is divided by f, when r_p > tau r_d it is multiplied by f.
+         * A change refactors D~ + diag(eta + rho) and restarts the
+         * acceleration from the current iterate (a = 1, y^ = y, z^ = z);
+         * x, y and z carry over (z is not scaled by rho).  The decision is
+         * logged in bits 1 (lowered) and 2 (raised) of the iteration's log
+         * byte and read from there in replay. */
+        if (P->adapt_ratio > 0.0 && n_uni > 0 && P->adapt_first > 0 && it >= P->adapt_first &&
+            it % P->adapt_first == 0 && ((it / P->adapt_first) & (it / P->adapt_first - 1)) == 0) {
+            int dir = 0;
+            if (P->replay && replay_log) dir = (replay_log[it - 1] >> 1) & 3;
+            else if (rd > P->adapt_ratio * rp) dir = 1;
+            else if (rp > P->adapt_ratio * rd) dir = 2;
+            if (log_out && (P->log_stride <= 0 || it <= P->log_stride)) log_out[it - 1] |= (uint8_t)(dir << 1);
+            if (dir == 1 || dir == 2) {
+                const double f = dir == 1 ? 1.0 / P->adapt_factor : P->adapt_factor;
+                for (int i = 0; i < m; ++i)
+                    if (kind[i] != ORC_ROW_BILATERAL) rho[i] *= f;
+                for (size_t k = 0; k < mm; ++k) A[k] = Dt[k];
+                for (int i = 0; i < m; ++i) A[(size_t)i * m + i] += P->eta + rho[i];
+                if (P->cr_iters <= 0 && orc_cholesky(m, A, L) != 0) {
+                    status |= ORC_FACTOR_FAIL;
+                    break;
+                }
+                a_k = 1.0;
+                c_prev = INFINITY;
+                for (int i = 0; i < m; ++i) {
+                    yh[i] = y[i];
+                    zh[i] = z[i];
+                }
+            }
         }
     }
     if (it > N) it = N;
