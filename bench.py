@@ -30,7 +30,8 @@ def biped_workload(n_worlds, seed=1002):
 
 
 CFG2 = dict(dt=2e-3, eta=1e-4, rho_bilateral=1e-4, rho_contact=0.3, eps=1e-6, max_iters=2000,
-            baumgarte=0.2, contact_margin=0.02, torque_sigma=5.0, seed=1002, reset_height=0.2)
+            baumgarte=0.2, contact_margin=0.02, torque_sigma=5.0, seed=1002, reset_height=0.2,
+            adapt_ratio=20.0, adapt_factor=5.0, adapt_first=100)
 PD = (15.0, 0.6)   # the paper's DR Legs gains (N m / rad, N m s / rad)
 WORKLOADS = {
     "biped": "biped-{n}: 31 bodies, 40 revolute joints (10 closed loops), 8 sole probes, dt 2 ms, cold-start "
@@ -101,7 +102,8 @@ def measured_traffic(steps_per_launch):
     return round((int(kv["fetch_bytes_per_step"]) + int(kv["write_bytes_per_step"])) * steps_per_launch)
 
 
-def make_model(workload, n_worlds, warmstart, schedule, seed=None, solver="auto", cr_iters=9):
+def make_model(workload, n_worlds, warmstart, schedule, seed=None, solver="auto", cr_iters=9, extra=None,
+               scene_seed=None):
     """The benchmark model of a workload: the biped batch (headline), the
     heterogeneous mix of four-bars, bipeds and excavators, boxes in a bin
     with contacts generated every step, or the large fixed figure (solved
@@ -114,6 +116,7 @@ def make_model(workload, n_worlds, warmstart, schedule, seed=None, solver="auto"
                                  "sparse": kamx.SOLVER_SPARSE}[solver])
     if seed is not None:
         params["seed"] = seed
+    params.update(extra or {})
     if workload == "biped":
         scene = biped_workload(n_worlds)
         model = kamx.Model(scene, params=params, pd=PD, refs=np.zeros(scene.n_joints))
@@ -130,10 +133,10 @@ def make_model(workload, n_worlds, warmstart, schedule, seed=None, solver="auto"
         # the cube's corner probes give its contacts every step
         model = kamx.Model(scene, params=dict(dt=1e-3, eta=1e-4, rho_bilateral=1e-6, rho_contact=1.0, fixed_iters=50,
                                               max_iters=50, torque_sigma=0.0, contact_margin=0.02,
-                                              warmstart=warmstart),
+                                              warmstart=warmstart, **(extra or {})),
                            max_contacts=4)
     elif workload == "boxbin":
-        scene = scenes.round_to_f32(scenes.box_bin_batch(n_worlds, seed=1005))
+        scene = scenes.round_to_f32(scenes.box_bin_batch(n_worlds, seed=1005 if scene_seed is None else scene_seed))
         model = kamx.Model(scene, params=dict(params, torque_sigma=0.0, max_iters=200), max_contacts=64)
         model.contacts_box_bin(scenes.BIN_HALF, 0.01)
     else:
@@ -170,14 +173,14 @@ def last_step_sample(model, scene, n_sample=64, seed=0):
 
 
 def run_gpu(n_worlds, steps, warmup, warmstart, schedule, net=None, seed=None, workload="biped", autotune=True,
-            capture=False, solver="auto", cr_iters=9):
+            capture=False, solver="auto", cr_iters=9, extra=None):
     """Warm-up steps, then one timed call of `steps` steps (chained launches
     where the mode allows, single-step launches otherwise), bracketed by HIP
     events on the launch stream; per-step iteration and row counts come
     from the library's iteration log."""
     import torch
 
-    scene, model = make_model(workload, n_worlds, warmstart, schedule, seed, solver, cr_iters)
+    scene, model = make_model(workload, n_worlds, warmstart, schedule, seed, solver, cr_iters, extra)
     if net is not None:
         model.attach_mlp(net)
     stream = torch.cuda.current_stream()
@@ -304,7 +307,9 @@ def oracle_rollout(min_seconds, n_worlds, max_steps):
 
     scene = biped_workload(n_worlds)
     P = oracle.Params(dt=CFG2["dt"], eta=CFG2["eta"], rho_bil=CFG2["rho_bilateral"], rho_c=CFG2["rho_contact"],
-                      eps=CFG2["eps"], max_iters=CFG2["max_iters"], baumgarte=CFG2["baumgarte"])
+                      eps=CFG2["eps"], max_iters=CFG2["max_iters"], baumgarte=CFG2["baumgarte"],
+                      adapt_ratio=CFG2["adapt_ratio"], adapt_factor=CFG2["adapt_factor"],
+                      adapt_first=CFG2["adapt_first"])
     act = np.where(scene.joint_actuated)[0]
     jo = scene.joint_offsets()
     q, u = scene.q.copy(), scene.u.copy()
@@ -341,7 +346,8 @@ def fp64_check(chk):
 
     sc = chk["scene"]
     P = oracle.Params(dt=CFG2["dt"], eta=CFG2["eta"], rho_bil=CFG2["rho_bilateral"], rho_c=CFG2["rho_contact"],
-                      baumgarte=CFG2["baumgarte"])
+                      baumgarte=CFG2["baumgarte"], adapt_ratio=CFG2["adapt_ratio"], adapt_factor=CFG2["adapt_factor"],
+                      adapt_first=CFG2["adapt_first"])
     jo = sc.joint_offsets()
     ncp_conv, ncp_all, diff = 0.0, 0.0, 0.0
     for w in chk["sample"]:
@@ -451,6 +457,8 @@ def main():
                     help="linear solve of the x-update: dense factorization where a world fits (auto), or "
                          "matrix-free Conjugate Residual for every world (sparse)")
     ap.add_argument("--cr-iters", type=int, default=9, help="Conjugate Residual iterations per ADMM iteration")
+    ap.add_argument("--no-fixed-penalty", action="store_true",
+                    help="skip the rollout with the fixed penalty of the paper's iteration (no adaptive penalty)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the run, copy a 256 MiB buffer once (a plain copy kernel of known traffic "
                          "for scaling HBM byte counters)")
@@ -469,8 +477,9 @@ def main():
     print(f"[bench] cold-start rollout: {args.worlds} worlds, warmup {args.warmup}, steps {args.steps}",
           file=sys.stderr, flush=True)
     sched = {"chain": kamx.SCHED_CHAIN, "lpt": kamx.SCHED_LPT, "index": kamx.SCHED_INDEX}[args.schedule]
-    if args.workload != "biped" or args.solver == "sparse":
+    if args.workload not in ("biped", "boxbin") or args.solver == "sparse":
         args.no_learned = True
+    if args.workload != "biped" or args.solver == "sparse":
         args.no_cpu = True
     sparse = args.workload == "figure" or args.solver == "sparse"
     cold = run_gpu(args.worlds, args.steps, args.warmup, kamx.WARM_COLD, sched, workload=args.workload,
@@ -516,7 +525,19 @@ def main():
                      "avg_launch_ms": round(1e3 * avg_launch_s, 4), "steps_per_launch": cold["steps_per_launch"]},
         "solver": solver_stats(cold, args.worlds * args.steps),
     }
+    result["config"]["penalty"] = ("per-row rho (bilateral 1e-4, limit and contact 0.3), the limit and contact rows' "
+                                   "share adapted by residual balancing (ratio 20, factor 5, at iterations 100 * 2^j; "
+                                   "not in the paper)")
     result["solver"]["resets"] = int(cold["resets"])
+    if not args.no_fixed_penalty:
+        print("[bench] fixed-penalty rollout (the paper's iteration as printed)", file=sys.stderr, flush=True)
+        fx = run_gpu(args.worlds, args.steps, args.warmup, kamx.WARM_COLD, sched, workload=args.workload,
+                     autotune=not args.no_autotune, solver=args.solver, cr_iters=args.cr_iters,
+                     extra=dict(adapt_ratio=0.0))
+        result["fixed_penalty"] = {
+            "value": round(args.worlds * args.steps / fx["wall_s"], 1),
+            "ms_per_step": round(1e3 * fx["wall_s"] / args.steps, 4),
+            **solver_stats(fx, args.worlds * args.steps)}
     if not args.no_previous:
         print("[bench] previous-step warm-start rollout", file=sys.stderr, flush=True)
         prev = run_gpu(args.worlds, args.steps, args.warmup, kamx.WARM_PREVIOUS, sched, workload=args.workload,
@@ -532,22 +553,26 @@ def main():
         t0 = time.perf_counter()
 
         def factory():
-            sc = biped_workload(args.worlds)
-            m = kamx.Model(sc, params=dict(CFG2, seed=TRAIN_SEED), pd=PD, refs=np.zeros(sc.n_joints))
-            m.set_schedule(sched)
+            # the same structure under another noise seed (biped) or other
+            # drops of the boxes (box bin)
+            _, m = make_model(args.workload, args.worlds, kamx.WARM_COLD, sched, seed=TRAIN_SEED,
+                              scene_seed=TRAIN_SEED + 3)
             return m
 
         net, info = learn.fit(factory, args.train_steps, epochs=args.epochs, batch=min(4096, args.worlds), lr=1e-3,
-                              seed=1004, log=lambda msg: print(f"[bench]   {msg}", file=sys.stderr, flush=True))
+                              seed=1004, log=lambda msg: print(f"[bench]   {msg}", file=sys.stderr, flush=True),
+                              capacity=args.worlds)
         t_train = time.perf_counter() - t0
         print("[bench] learned warm-start rollout", file=sys.stderr, flush=True)
-        lrn = run_gpu(args.worlds, args.steps, args.warmup, kamx.WARM_LEARNED, sched, net=net)
+        lrn = run_gpu(args.worlds, args.steps, args.warmup, kamx.WARM_LEARNED, sched, net=net, workload=args.workload,
+                      autotune=not args.no_autotune)
         result["learned"] = {
             "value": round(args.worlds * args.steps / lrn["wall_s"], 1),
             "ms_per_step": round(1e3 * lrn["wall_s"] / args.steps, 4),
             "speedup_vs_plain": round((args.worlds * args.steps / lrn["wall_s"]) / value, 4),
             **solver_stats(lrn, args.worlds * args.steps),
-            "network": "667 -> 256 -> 256 -> 224 (GELU), BF16 matrix-core kernels, FP32 accumulation",
+            "network": f"{net.n_in} -> {net.n_hidden} -> {net.n_hidden} -> {net.n_out} (GELU), BF16 matrix-core "
+                       "kernels, FP32 accumulation",
             "training": {"samples": info["samples"], "held_out": info["held_out"], "epochs": args.epochs,
                          "final_train_loss": round(info["train_loss"][-1], 5), "val_loss": round(info["val_loss"], 5),
                          "data_and_training_s": round(t_train, 2), "noise_seed": TRAIN_SEED},

@@ -214,12 +214,24 @@ typedef struct {
     int32_t linear_solver; /* KAMX_SOLVER_*; fixed at model creation          */
     int32_t cr_iters;     /* Conjugate Residual iterations per ADMM iteration
                              (matrix-free worlds; 1..1000)                   */
+    /* Adaptive penalty on limit and contact rows (not in the paper, whose
+     * penalty is fixed through a solve: residual balancing after Boyd et al.
+     * 2011, Sec. 3.4.1).  At iterations adapt_first * 2^j a solve that has
+     * not exited compares its residuals: r_d > adapt_ratio r_p divides the
+     * limit and contact rows' penalty by adapt_factor, r_p > adapt_ratio r_d
+     * multiplies it; a change refactors D~ + diag(eta + rho) (dense worlds)
+     * and restarts the acceleration at the current iterate.  The fixed point
+     * is unchanged.  adapt_ratio 0 switches it off. */
+    float adapt_ratio;
+    float adapt_factor;
+    int32_t adapt_first;
 } kamx_params;
 
 /* Fill *p with defaults (dt 2 ms, gravity -9.81 z, eta 1e-4, rho 1e-4 / 0.3,
  * eps 1e-6, 2000 iterations, acceleration and preconditioning on, restart
  * factor 0.999, beta 0.2, cold start, margin 0.02 m, no noise, semi-implicit
- * Euler, solver chosen by world size, 9 Conjugate Residual iterations).  Position-level terms act over the time from the configuration
+ * Euler, solver chosen by world size, 9 Conjugate Residual iterations,
+ * adaptive unilateral penalty with ratio 20 and factor 5 from iteration 100).  Position-level terms act over the time from the configuration
  * the rows are built at to the end of the step: the Baumgarte bias of a
  * bilateral row is beta f / h, a separated contact or limit f / h, a
  * penetrating one beta f / h, with h = dt (Euler) or dt/2 (Moreau-Jean). */
@@ -422,7 +434,9 @@ kamx_status kamx_read_stats(kamx_model m, int32_t *iters_dev, float *resid_dev, 
                             int32_t *rows_dev, kamx_stream stream);
 
 /* Restart decisions of the last step when log_restarts was set:
- * log_dev [n_worlds * max_iters] bytes (1 = restart at that iteration). */
+ * log_dev [n_worlds * max_iters] bytes, one per iteration: bit 0 = restart
+ * of the acceleration (Alg. 1 step 8), bits 1-2 = the adaptive penalty's
+ * change at that iteration (1 lowered, 2 raised, 0 none). */
 kamx_status kamx_read_restart_log(kamx_model m, uint8_t *log_dev, kamx_stream stream);
 
 /* Generalized joint forces applied in the last step (actuation, noise and

@@ -119,6 +119,7 @@ struct kamx_model_s {
     // learned warm start (worlds of identical structure only)
     bool uniform = false;
     int n_feat = 0, n_slots = 0, n_contact_slots = 0;
+    int contact_cap0 = 0, n_slots_joint = 0, n_feat_body = 0, n_feat_joint = 0;  // parts of the layout
     kamx_mlp mlp = nullptr;
     float *d_ws = nullptr;  // network prediction by slot [n_worlds * n_slots]
     // generated contacts (boxes in a bin)
@@ -185,6 +186,8 @@ static kamx_status validate_params(const kamx_params *p) {
     if (p->linear_solver < KAMX_SOLVER_AUTO || p->linear_solver > KAMX_SOLVER_SPARSE)
         return fail(KAMX_EINVAL, "linear_solver must be KAMX_SOLVER_AUTO, _DENSE or _SPARSE");
     if (p->cr_iters < 1 || p->cr_iters > 1000) return fail(KAMX_EINVAL, "cr_iters must be in [1, 1000]");
+    if (!(p->adapt_ratio >= 0.f) || (p->adapt_ratio > 0.f && (!(p->adapt_factor > 1.f) || p->adapt_first < 1)))
+        return fail(KAMX_EINVAL, "adapt_ratio must be >= 0; when on, adapt_factor > 1 and adapt_first >= 1");
     return KAMX_OK;
 }
 
@@ -213,6 +216,9 @@ static SolverParams to_solver(const kamx_params &p) {
     s.log_restarts = p.log_restarts;
     s.integrator = p.integrator;
     s.cr_iters = p.cr_iters;
+    s.adapt_ratio = p.adapt_ratio;
+    s.adapt_factor = p.adapt_factor;
+    s.adapt_first = p.adapt_first;
     return s;
 }
 
@@ -242,6 +248,9 @@ void kamx_default_params(kamx_params *p) {
     p->integrator = KAMX_EULER;
     p->linear_solver = KAMX_SOLVER_AUTO;
     p->cr_iters = 9;
+    p->adapt_ratio = 20.f;
+    p->adapt_factor = 5.f;
+    p->adapt_first = 100;
 }
 
 const char *kamx_last_error(void) { return g_error.c_str(); }
@@ -389,9 +398,12 @@ kamx_status kamx_model_create(const kamx_body_desc *bodies, int32_t nb, const ka
         if (wi[w].nb != wi[0].nb || wi[w].nj != wi[0].nj || wi[w].nlim != wi[0].nlim ||
             wi[w].ndrv != wi[0].ndrv || wi[w].contact_cap != wi[0].contact_cap)
             m->uniform = false;
-    m->n_contact_slots = wi[0].contact_cap;
-    m->n_slots = 5 * wi[0].nj + wi[0].nlim + wi[0].ndrv + 3 * wi[0].contact_cap;
-    m->n_feat = 13 * wi[0].nb + m->n_slots + wi[0].nj;
+    m->n_contact_slots = m->contact_cap0 = wi[0].contact_cap;
+    m->n_slots_joint = 5 * wi[0].nj + wi[0].nlim + wi[0].ndrv;
+    m->n_feat_body = 13 * wi[0].nb;
+    m->n_feat_joint = wi[0].nj;
+    m->n_slots = m->n_slots_joint + 3 * m->n_contact_slots;
+    m->n_feat = m->n_feat_body + m->n_slots + m->n_feat_joint;
 
     auto cleanup_fail = [&](kamx_status st) {
         kamx_model_destroy(m);
@@ -1115,9 +1127,13 @@ kamx_status kamx_model_attach_mlp(kamx_model m, kamx_mlp net) {
 kamx_status kamx_contacts_box_bin(kamx_model m, const kamx_box_desc *boxes, float half_x, float half_y,
                                   float margin) {
     if (!m) return fail(KAMX_EINVAL, "model is NULL");
+    if (m->mlp) return fail(KAMX_ESTATE, "set up box contacts before attaching a network (the slot layout changes)");
     drop_graphs(m);
     if (!boxes) {
         m->box_bin = false;
+        m->n_contact_slots = m->contact_cap0;
+        m->n_slots = m->n_slots_joint + 3 * m->n_contact_slots;
+        m->n_feat = m->n_feat_body + m->n_slots + m->n_feat_joint;
         return KAMX_OK;
     }
     if (!(half_x > 0.f) || !(half_y > 0.f) || !(margin >= 0.f))
@@ -1146,6 +1162,12 @@ kamx_status kamx_contacts_box_bin(kamx_model m, const kamx_box_desc *boxes, floa
         K_TRY(dalloc(m, &m->d_gen_count, (size_t)m->n_worlds));
     }
     HIP_TRY(hipMemcpy(m->d_box_geom, geom.data(), sizeof(float) * geom.size(), hipMemcpyHostToDevice));
+    int most = 0;
+    for (int w = 0; w < m->n_worlds; ++w) most = std::max(most, per_world[w]);
+    // learned warm start: a slot per box vertex (contact_slot of a box key)
+    m->n_contact_slots = 8 * most;
+    m->n_slots = m->n_slots_joint + 3 * m->n_contact_slots;
+    m->n_feat = m->n_feat_body + m->n_slots + m->n_feat_joint;
     m->bin_wx = half_x;
     m->bin_wy = half_y;
     m->bin_margin = margin;

@@ -55,7 +55,25 @@ struct SolverParams {
     int32_t log_restarts;
     int32_t integrator;  // KAMX_EULER or KAMX_MOREAU_JEAN
     int32_t cr_iters;    // Conjugate Residual iterations per x-update (matrix-free worlds)
+    float adapt_ratio;   // adaptive unilateral penalty: residual ratio (0: off)
+    float adapt_factor;  // factor of one penalty change
+    int32_t adapt_first; // first checkpoint iteration (then doubling)
 };
+
+// Slot of a contact key in the learned warm start's per-world layout (three
+// slots per contact): the key modulo 8 * kMaxBodies -- the probe index for
+// probe contacts, box * 8 + vertex for generated box contacts (the target
+// the vertex touches is dropped, so a vertex stays in its slot as it slides
+// from one face to another), the caller's key modulo 512 otherwise.
+__host__ __device__ inline int contact_slot(int key) { return key & (8 * kMaxBodies - 1); }
+
+// Whether iteration it is a checkpoint of the adaptive penalty: first,
+// 2 first, 4 first, ...
+__host__ __device__ inline bool adapt_checkpoint(int it, int first) {
+    if (first <= 0 || it < first || it % first != 0) return false;
+    const int q = it / first;
+    return (q & (q - 1)) == 0;
+}
 
 // A pose advanced by time h with a twist: r + h v, and exp(h [w]x) R by
 // the quaternion exponential (left multiplication, world-frame w),

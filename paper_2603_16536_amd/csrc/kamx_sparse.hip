@@ -637,10 +637,11 @@ __device__ __attribute__((noinline)) void sparse_step_world(const StepArgs &a, i
     R.preg = p * p * reg;
     __syncthreads();  // raw rows read, incidence lists complete
     for (int e = 0; e < 12; ++e) L.J[e * NT + tid] = R.jt[e];
-    const float rho = R.kind == kRowBilateral ? P.rho_bil : (R.kind == kRowPad ? 1.f : P.rho_c);
-    const float rinv = 1.f / rho;
+    // (rho, 1/rho and the shift change only with the adaptive penalty)
+    float rho = R.kind == kRowBilateral ? P.rho_bil : (R.kind == kRowPad ? 1.f : P.rho_c);
+    float rinv = 1.f / rho;
     const float eta = P.eta;
-    const float shift = eta + rho;  // diagonal of D~ + diag(eta + rho) beyond D~
+    float shift = eta + rho;  // diagonal of D~ + diag(eta + rho) beyond D~
     const bool unilateral = R.kind == kRowLimit || R.kind == kRowNormal || R.kind == kRowTangent;
 
     // ---- warm start (Alg. 1 step 2; Sec. 4.1): y = x = Pi_K(lambda_ws / p),
@@ -689,6 +690,7 @@ __device__ __attribute__((noinline)) void sparse_step_world(const StepArgs &a, i
     float rp = 0.f, rd = 0.f, rc = 0.f, rncp = 0.f;
     const int N = P.fixed_iters > 0 ? P.fixed_iters : P.max_iters;
     const int ncr = P.cr_iters > 0 ? P.cr_iters : 1;
+    const int n_uni = W.nlim + 3 * nc;  // limit and contact rows: what the adaptive penalty acts on
     bool converged = false;
     for (it = 1; it <= N; ++it) {
         // steps 4-5: s = Gamma(z^), rhs = -v~_f - s + eta x + rho y^ + z^
@@ -768,8 +770,17 @@ __device__ __attribute__((noinline)) void sparse_step_world(const StepArgs &a, i
         }
         yp = yb;
         zp = zb;
+        // adaptive penalty (not in the paper: residual balancing) at the
+        // checkpoints of a solve that does not exit here; the residuals are
+        // the same in every thread, so the decision is uniform
+        int adapt_dir = 0;
+        if (P.adapt_ratio > 0.f && n_uni > 0 && adapt_checkpoint(it, P.adapt_first) &&
+            !(P.fixed_iters <= 0 && rp < P.eps && rd < P.eps && rc < P.eps)) {
+            if (rd > P.adapt_ratio * rp) adapt_dir = 1;
+            else if (rp > P.adapt_ratio * rd) adapt_dir = 2;
+        }
         if (tid == 0 && a.rlog && P.log_restarts && it <= P.max_iters)
-            a.rlog[(size_t)w * P.max_iters + (it - 1)] = (uint8_t)restart;
+            a.rlog[(size_t)w * P.max_iters + (it - 1)] = (uint8_t)(restart | (adapt_dir << 1));
         if (!(isfinite(rp) && isfinite(rd) && isfinite(rc))) {
             status = KAMX_WORLD_NONFINITE;
             break;
@@ -777,6 +788,20 @@ __device__ __attribute__((noinline)) void sparse_step_world(const StepArgs &a, i
         if (P.fixed_iters <= 0 && rp < P.eps && rd < P.eps && rc < P.eps) {
             converged = true;
             break;
+        }
+        if (adapt_dir) {
+            // the limit and contact rows' penalty changes by the factor (the
+            // operator is applied matrix-free, so nothing is refactored) and
+            // the acceleration restarts at the current (y, z)
+            if (unilateral) {
+                rho *= adapt_dir == 1 ? 1.f / P.adapt_factor : P.adapt_factor;
+                rinv = 1.f / rho;
+                shift = eta + rho;
+            }
+            a_k = 1.f;
+            c_prev = INFINITY;
+            yh = yp;
+            zh = zp;
         }
     }
     if (it > N) it = N;

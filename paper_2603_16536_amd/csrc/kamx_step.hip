@@ -341,6 +341,319 @@ __device__ inline void delassus_apply(const Lds &L, int m, int nb, const float *
 // One step of world w (every phase of the step; the workgroup owns the
 // world).  step is the step index that keys the actuation noise; k the
 // position of the step inside the launch.
+// Cholesky of D~ + diag(eta + rho) held packed in A, then the explicit
+// inverse of the factor in place (Alg. 1 step 1), for a refactorization
+// after the adaptive penalty changed rho: the step's own factorization
+// (the same operations) is written out where the step factors first, so
+// this out-of-line copy leaves that code and its schedule alone.  Returns
+// nonzero when a pivot is not positive.
+template <int MC, int NT>
+__device__ __attribute__((noinline)) int factor_invert_again(const Lds &L, float *A, int m, int *s_int,
+                                                             const StepArgs &a, int w) {
+    const int tid = threadIdx.x;
+    // ---- Cholesky of D~ + diag(eta + rho), in place (Alg. 1 step 1):
+    //      right-looking over 16x16 tiles.  Wave 0 factors a diagonal tile in
+    //      registers (lane r holds row r) and forms its inverse; the panel
+    //      below is multiplied by that inverse on the matrix cores; the
+    //      trailing tiles get their rank-16 update on the matrix cores.  With
+    //      one step of lookahead, wave 0 updates and factors the next
+    //      diagonal tile while the other waves update the rest.
+    {
+        const int T = (m + 15) >> 4;
+        float *Xs = L.red;  // 16x16 inverse of the current diagonal factor tile (red + wb are free here)
+        const int lane = tid & 63, wv = tid >> 6, fr = lane & 15, fk = lane >> 4;
+        constexpr int NW = NT / 64;
+        // one wave alone: at most two tile rows, so every trailing update is
+        // the next diagonal tile (wave 0's); the other waves' loop never runs
+        static_assert(NW > 1 || MC <= 32, "a single-wave factorization covers two tile rows");
+        if (tid == 0) s_int[2] = 0;
+        __syncthreads();
+        // factor diagonal tile K (wave 0 only) and write its inverse to Xs
+        auto factor_diag = [&](int K) {
+            const int k0 = 16 * K;
+            const int r = lane;
+            float a[16];
+            const float *Rr = A + tri_row_offset(k0 + (r & 15)) + k0;
+#pragma unroll
+            for (int c = 0; c < 16; ++c) a[c] = (r < 16 && c <= r) ? Rr[c] : 0.f;
+            bool ok = true;
+            float ild[16];  // 1 / l_kk (the same in every lane)
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                float d = rdlane(a[k], k);
+                ok = ok && (d > 0.f) && isfinite(d);
+                // hardware reciprocal square root (1 ulp); l_kk = d / sqrt(d)
+                float il = __builtin_amdgcn_rsqf(d), lkk = d * il;
+                ild[k] = il;
+                if (r == k) a[k] = lkk;
+                else if (r > k) a[k] *= il;
+#pragma unroll
+                for (int j = k + 1; j < 16; ++j) {
+                    float ljk = rdlane(a[k], j);
+                    if (r >= j) a[j] -= a[k] * ljk;
+                }
+            }
+            // column r of the tile's inverse (forward substitution)
+            float xc[16];
+#pragma unroll
+            for (int rr = 0; rr < 16; ++rr) {
+                float acc = (r == rr) ? 1.f : 0.f;
+#pragma unroll
+                for (int kk = 0; kk < rr; ++kk) acc -= rdlane(a[kk], rr) * xc[kk];
+                xc[rr] = acc * ild[rr];
+            }
+            if (r < 16) {
+                float *Rw = A + tri_row_offset(k0 + r) + k0;
+#pragma unroll
+                for (int c = 0; c < 16; ++c)
+                    if (c <= r) Rw[c] = a[c];
+#pragma unroll
+                for (int rr = 0; rr < 16; ++rr) Xs[16 * rr + r] = xc[rr];  // zero above the diagonal
+            }
+            if (!ok && r == 0) s_int[2] = 1;
+        };
+        // A_IJ -= L_IK L_JK^T for one tile pair (one wave, matrix cores)
+        auto update_pair = [&](int I, int J, int k0) {
+            const float *Ri = A + tri_row_offset(16 * I + fr) + k0;
+            const float *Rj = A + tri_row_offset(16 * J + fr) + k0;
+            mfx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ch = 0; ch < 4; ++ch) acc = mfma4(Ri[4 * ch + fk], Rj[4 * ch + fk], acc);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int rr = 4 * fk + c;
+                if (I != J || fr <= rr) A[tri_row_offset(16 * I + rr) + 16 * J + fr] -= acc[c];
+            }
+        };
+#ifdef KAMX_FACTOR_TIMING
+        uint64_t fsub[4] = {0, 0, 0, 0}, fmark = a.phase_clk && tid == 0 ? wall_clock64() : 0;
+#define KAMX_FMARK(k)                                   \
+    if (a.phase_clk && tid == 0) {                      \
+        uint64_t now_ = wall_clock64();                 \
+        fsub[k] += now_ - fmark;                        \
+        fmark = now_;                                   \
+    }
+#else
+#define KAMX_FMARK(k)
+#endif
+        if (wv == 0) factor_diag(0);
+        __syncthreads();
+        KAMX_FMARK(0);
+        for (int K = 0; K < T; ++K) {
+            if (s_int[2]) break;
+            const int k0 = 16 * K;
+            const int nI = T - K - 1;
+            // panel: L_IK = A_IK Xkk^T for the tiles I below the diagonal,
+            // one wave per tile (each wave reads its tile before overwriting it)
+            for (int Ii = wv; Ii < nI; Ii += NW) {
+                const int I = K + 1 + Ii;
+                mfx4 acc = {0.f, 0.f, 0.f, 0.f};
+                const float *Ar = A + tri_row_offset(16 * I + fr) + k0;
+#pragma unroll
+                for (int ch = 0; ch < 4; ++ch) acc = mfma4(Ar[4 * ch + fk], Xs[16 * fr + 4 * ch + fk], acc);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) A[tri_row_offset(16 * I + 4 * fk + c) + k0 + fr] = acc[c];
+            }
+            __syncthreads();
+            KAMX_FMARK(1);
+            if (nI == 0) break;
+            // trailing update A_IJ -= L_IK L_JK^T, K < J <= I.  Pair 0 is the
+            // next diagonal tile: wave 0 updates and factors it; the other
+            // waves take the remaining pairs.
+            const int npair = nI * (nI + 1) / 2;
+            if (wv == 0) {
+                update_pair(K + 1, K + 1, k0);
+                factor_diag(K + 1);
+            } else {
+                for (int p = wv; p < npair; p += NW - 1) {
+                    int Ii = (int)((sqrtf(8.f * (float)p + 1.f) - 1.f) * 0.5f);
+                    while ((Ii + 1) * (Ii + 2) / 2 <= p) ++Ii;
+                    while (Ii * (Ii + 1) / 2 > p) --Ii;
+                    const int Jj = p - Ii * (Ii + 1) / 2;
+                    update_pair(K + 1 + Ii, K + 1 + Jj, k0);
+                }
+            }
+            __syncthreads();
+            KAMX_FMARK(2);
+        }
+#ifdef KAMX_FACTOR_TIMING
+        if (a.phase_clk && tid == 0)
+            for (int q = 0; q < 3; ++q) a.phase_clk[16 * w + 8 + q] = fsub[q];
+#endif
+#undef KAMX_FMARK
+    }
+    __syncthreads();
+    const int factor_fail = s_int[2];
+
+    if (a.phase_clk && tid == 0) a.phase_clk[16 * w + 4] = wall_clock64();
+    // ---- explicit inverse of the factor, in place: X = L^-1 over 16x16
+    //      tiles.  Diagonal tiles are inverted in registers (one wave per
+    //      tile); then tile row by tile row, M_ik = X_ii L_ik (k < i) and
+    //      X_ij = -sum_{k=j}^{i-1} M_ik X_kj, one wave per tile on the
+    //      matrix cores, results held in registers until every wave has read
+    //      the row.
+    if (!factor_fail) {
+        const int T = (m + 15) >> 4;
+        const int lane = tid & 63, wv = tid >> 6, fr = lane & 15, fk = lane >> 4;
+        constexpr int NW = NT / 64;
+        static_assert(2 * NW >= MC / 16 - 1, "two off-diagonal tiles per wave must cover a tile row");
+        for (int Ti = wv; Ti < T; Ti += NW) {
+            const int k0 = 16 * Ti, r = lane;
+            float a[16];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) a[c] = (r < 16 && c <= r) ? A[tri_row_offset(k0 + (r & 15)) + k0 + c] : 0.f;
+            float xc[16];
+#pragma unroll
+            for (int rr = 0; rr < 16; ++rr) {
+                float acc = (r == rr) ? 1.f : 0.f;
+#pragma unroll
+                for (int kk = 0; kk < rr; ++kk) acc -= rdlane(a[kk], rr) * xc[kk];
+                xc[rr] = acc * __builtin_amdgcn_rcpf(rdlane(a[rr], rr));  // hardware reciprocal (1 ulp)
+            }
+            if (r < 16) {
+#pragma unroll
+                for (int rr = 0; rr < 16; ++rr)
+                    if (rr >= r) A[tri_row_offset(k0 + rr) + k0 + r] = xc[rr];
+            }
+        }
+        __syncthreads();
+        for (int Ti = 1; Ti < T; ++Ti) {
+            const int i0 = 16 * Ti;
+            // M_ik = X_ii L_ik in place
+            for (int Tk = wv; Tk < Ti; Tk += NW) {
+                mfx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int ch = 0; ch < 4; ++ch)
+                    acc = mfma4(tri_at(A, i0 + fr, i0 + 4 * ch + fk),
+                                A[tri_row_offset(i0 + 4 * ch + fk) + 16 * Tk + fr], acc);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) A[tri_row_offset(i0 + 4 * fk + c) + 16 * Tk + fr] = acc[c];
+            }
+            __syncthreads();
+            // X_ij = -sum_k M_ik X_kj (two tiles per wave at most: 14 tile rows, 8 waves)
+            mfx4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int Tj = wv + q * NW;
+                if (Tj >= Ti) continue;
+                // the diagonal tile X_jj (lower triangular) first, then the full
+                // tiles below it with unconditional loads, alternating between
+                // two accumulators so consecutive products do not wait on
+                // each other
+                mfx4 acc = {0.f, 0.f, 0.f, 0.f}, accb = {0.f, 0.f, 0.f, 0.f};
+                const float *Mr = A + tri_row_offset(i0 + fr);
+                const int jc = 16 * Tj + fr;
+#pragma unroll
+                for (int ch = 0; ch < 4; ++ch) {
+                    const int kr = 16 * Tj + 4 * ch + fk;
+                    acc = mfma4(Mr[16 * Tj + 4 * ch + fk], tri_at(A, kr, jc), acc);
+                }
+                for (int Tk = Tj + 1; Tk < Ti; ++Tk) {
+#pragma unroll
+                    for (int ch = 0; ch < 4; ++ch) {
+                        const int kr = 16 * Tk + 4 * ch + fk;
+                        const float mv = Mr[16 * Tk + 4 * ch + fk], xv = A[tri_row_offset(kr) + jc];
+                        if (ch & 1) accb = mfma4(mv, xv, accb);
+                        else acc = mfma4(mv, xv, acc);
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[c] += accb[c];
+                if (q == 0) acc0 = acc;
+                else acc1 = acc;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int Tj = wv + q * NW;
+                if (Tj >= Ti) continue;
+                const mfx4 acc = q == 0 ? acc0 : acc1;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) A[tri_row_offset(i0 + 4 * fk + c) + 16 * Tj + fr] = -acc[c];
+            }
+        }
+        __syncthreads();
+    }
+
+    return factor_fail;
+}
+
+// D~ + diag(eta + rho) rebuilt into A after the adaptive penalty changed
+// rho: the pairs, products and order of the step's assembly, with the
+// Jacobi scales of the step and W = M^-1 J^T formed per pair from the bodies
+// (the vector region that held W now holds the iterates).  Uses the
+// reduction area (free between iterations) for the pair-task offsets.
+template <int MC, int NT>
+__device__ __attribute__((noinline)) void reassemble(const Lds &L, float *A, int m, int nb, const float *vp,
+                                                     const float *vrho, float eta) {
+    const int tid = threadIdx.x;
+    const int Mp = (m + 15) & ~15;
+    const int n4 = tri_row_offset(Mp) >> 2;
+    for (int k = tid; k < n4; k += NT) reinterpret_cast<float4 *>(A)[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    int *toff = reinterpret_cast<int *>(L.red);
+    if (tid == 0) {
+        toff[0] = 0;
+        for (int b = 0; b < nb; ++b) {
+            int kb = L.inc_off[b + 1] - L.inc_off[b];
+            toff[b + 1] = toff[b] + kb * (kb + 1) / 2;
+        }
+    }
+    __syncthreads();
+    if (tid >= m && tid < Mp) A[tri_row_offset(tid) + tid] = 1.f;
+    auto wside = [&](int r, int sd, float out[6]) {
+        const int b = L.ri(sd ? RIB : RIA, r);
+        float in[6];
+        for (int k = 0; k < 6; ++k) in[k] = L.rf(RJ + 6 * sd + k, r);
+        if (b >= 0) apply_minv(L, b, in, out);
+        else
+            for (int k = 0; k < 6; ++k) out[k] = 0.f;
+    };
+    const int ntask = toff[nb];
+    for (int t = tid; t < ntask; t += NT) {
+        int lo = 0, hi = nb - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (toff[mid] <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const int b = lo;
+        const int loc = t - toff[b];
+        int u = (int)((sqrtf(8.f * (float)loc + 1.f) - 1.f) * 0.5f);
+        while ((u + 1) * (u + 2) / 2 <= loc) ++u;
+        while (u * (u + 1) / 2 > loc) --u;
+        const int v = loc - u * (u + 1) / 2;
+        const int ri_ = L.inc_list[L.inc_off[b] + u] >> 1;
+        const int rj_ = L.inc_list[L.inc_off[b] + v] >> 1;
+        const int ia = L.ri(RIA, ri_), ib = L.ri(RIB, ri_), ja = L.ri(RIA, rj_), jb = L.ri(RIB, rj_);
+        int first = 1 << 30;
+        if (ia == ja || ia == jb) first = ia;
+        if (ib >= 0 && (ib == ja || ib == jb) && ib < first) first = ib;
+        if (first != b) continue;
+        float acc = 0.f, wv[6];
+        if (ia == ja) {
+            wside(rj_, 0, wv);
+            for (int k = 0; k < 6; ++k) acc += L.rf(RJ + k, ri_) * wv[k];
+        }
+        if (ia == jb) {
+            wside(rj_, 1, wv);
+            for (int k = 0; k < 6; ++k) acc += L.rf(RJ + k, ri_) * wv[k];
+        }
+        if (ib >= 0 && ib == ja) {
+            wside(rj_, 0, wv);
+            for (int k = 0; k < 6; ++k) acc += L.rf(RJ + 6 + k, ri_) * wv[k];
+        }
+        if (ib >= 0 && ib == jb) {
+            wside(rj_, 1, wv);
+            for (int k = 0; k < 6; ++k) acc += L.rf(RJ + 6 + k, ri_) * wv[k];
+        }
+        if (ri_ == rj_) acc += L.rf(RREG, ri_);
+        acc *= vp[ri_] * vp[rj_];
+        if (ri_ == rj_) acc += eta + vrho[ri_];
+        A[tri_row_offset(ri_) + rj_] = acc;
+    }
+    __syncthreads();
+}
+
 template <int MC, int NT>
 __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, int *s_int) {
     extern __shared__ float4 smem4[];
@@ -470,10 +783,10 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
                 if (t < rc0) {
                     v = a.lambda[W.row_base + t];
                 } else {
-                    const int key = (t - rc0) / 3, e = (t - rc0) - 3 * ((t - rc0) / 3);
+                    const int slot = (t - rc0) / 3, e = (t - rc0) - 3 * ((t - rc0) / 3);
                     const int nprev = a.ncontacts_out[w];
                     for (int q = 0; q < nprev && q < kMaxContacts; ++q)
-                        if (a.keys[w * kMaxContacts + q] == key) {
+                        if (a.keys[w * kMaxContacts + q] >= 0 && contact_slot(a.keys[w * kMaxContacts + q]) == slot) {
                             v = a.lambda[W.row_base + rc0 + 3 * q + e];
                             break;
                         }
@@ -908,15 +1221,16 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
             if (wmode == KAMX_WARM_EXTERNAL) {
                 lw = a.lambda_ext[W.row_base + i];
             } else if (wmode == KAMX_WARM_LEARNED) {
-                // network output by slot: joint and limit rows in order, then
-                // three slots per contact key
+                // network output by slot: joint, limit and drive rows in
+                // order, then three slots per contact slot (contact_slot)
                 const float *ws = a.ws_slots + (long)w * a.mlp.n_out;
                 if (i < row_c0) {
                     lw = ws[i];
                 } else {
                     int c = (i - row_c0) / 3, e = (i - row_c0) % 3;
                     int key = cint[CKEY * kMaxContacts + c];
-                    lw = key >= 0 && key < a.n_contact_slots ? ws[row_c0 + 3 * key + e] : 0.f;
+                    int sl = key >= 0 ? contact_slot(key) : -1;
+                    lw = sl >= 0 && sl < a.n_contact_slots ? ws[row_c0 + 3 * sl + e] : 0.f;
                 }
             } else if (i < row_c0) {
                 lw = a.lambda[W.row_base + i];
@@ -1212,12 +1526,13 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
     const int kind_o = io < m ? L.ri(RKIND, io) : -1;
     const bool owner_o = io < m && kind_o != kRowTangent && hh == 0;
     const int blk_o = kind_o == kRowNormal ? 3 : 1;
-    const float rho_o = io < m ? vrho[io] : 1.f;
+    float rho_o = io < m ? vrho[io] : 1.f;  // changes only with the adaptive penalty
     const float mu_o = io < m ? L.rf(RMU, io) : 0.f;
     float a_k = 1.f, c_prev = INFINITY;
     int it = 0, status = 0;
     float rp = 0.f, rd = 0.f, rc = 0.f, rncp = 0.f;
     const int N = P.fixed_iters > 0 ? P.fixed_iters : P.max_iters;
+    const int n_uni = W.nlim + 3 * nc;  // limit and contact rows: what the adaptive penalty acts on
     if (i < m) vrinv[i] = 1.f / vrho[i];  // rho is fixed for the solve: divide once
     if (factor_fail) {
         status = KAMX_WORLD_FACTOR_FAIL;
@@ -1275,271 +1590,323 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
             }
         };
         own_rhs();
-        for (it = 1; it <= N; ++it) {
-            KAMX_MARK(0);
-            __syncthreads();
-            KAMX_MARK(1);
-            // t = X r over groups of 4 rows: groups g and Q-1-g form a pair
-            // (balanced: together they span Q+1 column quads); 16 threads per
-            // pair take every 16th column quad, reading the quad of r once
-            // for the 4 rows of a group. The rows of a group lie back to back,
-            // 4(G+1) floats apart; the pads of the diagonal quad hold 0 and r
-            // is 0 past row m, and rows past m (up to the next multiple of 16)
-            // hold finite values whose sums are not stored. The eight sums
-            // are reduce-scattered over the 16 lanes as in the x update.
-            {
-                const int Q = (m + 3) >> 2;
-                const int g = tid >> 4, kq = tid & 15;
-                const int g1 = g, g2 = Q - 1 - g;
-                float4 s1 = make_float4(0.f, 0.f, 0.f, 0.f), s2 = s1;
-                if (g1 <= g2) {
+        // the solve runs in passes: a pass ends when the solve exits or when
+        // the adaptive penalty changes rho, whose refactorization then runs
+        // outside the iteration loop (so the loop itself carries no calls)
+        int adapt_pending = 0;
+        it = 1;
+        for (;;) {
+            for (; it <= N; ++it) {
+                KAMX_MARK(0);
+                __syncthreads();
+                KAMX_MARK(1);
+                // t = X r over groups of 4 rows: groups g and Q-1-g form a pair
+                // (balanced: together they span Q+1 column quads); 16 threads per
+                // pair take every 16th column quad, reading the quad of r once
+                // for the 4 rows of a group. The rows of a group lie back to back,
+                // 4(G+1) floats apart; the pads of the diagonal quad hold 0 and r
+                // is 0 past row m, and rows past m (up to the next multiple of 16)
+                // hold finite values whose sums are not stored. The eight sums
+                // are reduce-scattered over the 16 lanes as in the x update.
+                {
+                    const int Q = (m + 3) >> 2;
+                    const int g = tid >> 4, kq = tid & 15;
+                    const int g1 = g, g2 = Q - 1 - g;
+                    float4 s1 = make_float4(0.f, 0.f, 0.f, 0.f), s2 = s1;
+                    if (g1 <= g2) {
 #pragma unroll
-                    for (int part = 0; part < 2; ++part) {
-                        if (part == 1 && g2 == g1) break;
-                        const int G = part == 0 ? g1 : g2;
-                        const float *R = A + tri_row_offset(4 * G);
-                        const int rl = 4 * (G + 1);
-                        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-                        for (int c = kq; c <= G; c += 16) {
-                            const float4 rv = *reinterpret_cast<const float4 *>(vrhs + 4 * c);
-                            const float4 x0 = *reinterpret_cast<const float4 *>(R + 4 * c);
-                            const float4 x1 = *reinterpret_cast<const float4 *>(R + rl + 4 * c);
-                            const float4 x2 = *reinterpret_cast<const float4 *>(R + 2 * rl + 4 * c);
-                            const float4 x3 = *reinterpret_cast<const float4 *>(R + 3 * rl + 4 * c);
-                            acc.x += x0.x * rv.x;
-                            acc.y += x1.x * rv.x;
-                            acc.z += x2.x * rv.x;
-                            acc.w += x3.x * rv.x;
-                            acc.x += x0.y * rv.y;
-                            acc.y += x1.y * rv.y;
-                            acc.z += x2.y * rv.y;
-                            acc.w += x3.y * rv.y;
-                            acc.x += x0.z * rv.z;
-                            acc.y += x1.z * rv.z;
-                            acc.z += x2.z * rv.z;
-                            acc.w += x3.z * rv.z;
-                            acc.x += x0.w * rv.w;
-                            acc.y += x1.w * rv.w;
-                            acc.z += x2.w * rv.w;
-                            acc.w += x3.w * rv.w;
+                        for (int part = 0; part < 2; ++part) {
+                            if (part == 1 && g2 == g1) break;
+                            const int G = part == 0 ? g1 : g2;
+                            const float *R = A + tri_row_offset(4 * G);
+                            const int rl = 4 * (G + 1);
+                            float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+                            for (int c = kq; c <= G; c += 16) {
+                                const float4 rv = *reinterpret_cast<const float4 *>(vrhs + 4 * c);
+                                const float4 x0 = *reinterpret_cast<const float4 *>(R + 4 * c);
+                                const float4 x1 = *reinterpret_cast<const float4 *>(R + rl + 4 * c);
+                                const float4 x2 = *reinterpret_cast<const float4 *>(R + 2 * rl + 4 * c);
+                                const float4 x3 = *reinterpret_cast<const float4 *>(R + 3 * rl + 4 * c);
+                                acc.x += x0.x * rv.x;
+                                acc.y += x1.x * rv.x;
+                                acc.z += x2.x * rv.x;
+                                acc.w += x3.x * rv.x;
+                                acc.x += x0.y * rv.y;
+                                acc.y += x1.y * rv.y;
+                                acc.z += x2.y * rv.y;
+                                acc.w += x3.y * rv.y;
+                                acc.x += x0.z * rv.z;
+                                acc.y += x1.z * rv.z;
+                                acc.z += x2.z * rv.z;
+                                acc.w += x3.z * rv.z;
+                                acc.x += x0.w * rv.w;
+                                acc.y += x1.w * rv.w;
+                                acc.z += x2.w * rv.w;
+                                acc.w += x3.w * rv.w;
+                            }
+                            if (part == 0) s1 = acc;
+                            else s2 = acc;
                         }
-                        if (part == 0) s1 = acc;
-                        else s2 = acc;
+                    }
+                    const bool b3 = kq & 8, b2 = kq & 4, b1 = kq & 2;
+                    const float v8[8] = {s1.x, s1.y, s1.z, s1.w, s2.x, s2.y, s2.z, s2.w};
+                    float u4[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        u4[k] = (b3 ? v8[k + 4] : v8[k]) + dpp<kDppMirror16>(b3 ? v8[k] : v8[k + 4]);
+                    float u2[2];
+#pragma unroll
+                    for (int k = 0; k < 2; ++k)
+                        u2[k] = (b2 ? u4[k + 2] : u4[k]) + dpp<kDppMirror8>(b2 ? u4[k] : u4[k + 2]);
+                    float z = (b1 ? u2[1] : u2[0]) + dpp<kDppXor2>(b1 ? u2[0] : u2[1]);
+                    z += dpp<kDppXor1>(z);
+                    if (!(kq & 1) && g1 <= g2) {
+                        const int i = 4 * (b3 ? g2 : g1) + (b2 ? 2 : 0) + (b1 ? 1 : 0);
+                        if (i < m && (!b3 || g2 > g1)) vt[i] = z;
                     }
                 }
-                const bool b3 = kq & 8, b2 = kq & 4, b1 = kq & 2;
-                const float v8[8] = {s1.x, s1.y, s1.z, s1.w, s2.x, s2.y, s2.z, s2.w};
-                float u4[4];
+                __syncthreads();
+                KAMX_MARK(2);
+                // x_new = x + X^T t over column quads: quads c and Q-1-c form a
+                // pair (balanced: together they span m + 4 rows); 16 threads per
+                // pair take every 16th group of 4 rows, each reading a group's t
+                // and the 4 rows' entries of the quad as float4s; butterfly sum
+                // over the 16 threads
+                {
+                    const int Q = (m + 3) >> 2;
+                    const int g = tid >> 4, kq = tid & 15;
+                    const int c1 = g, c2 = Q - 1 - g;
+                    float4 s1 = make_float4(0.f, 0.f, 0.f, 0.f), s2 = s1;
+                    if (c1 <= c2) {
 #pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    u4[k] = (b3 ? v8[k + 4] : v8[k]) + dpp<kDppMirror16>(b3 ? v8[k] : v8[k + 4]);
-                float u2[2];
-#pragma unroll
-                for (int k = 0; k < 2; ++k)
-                    u2[k] = (b2 ? u4[k + 2] : u4[k]) + dpp<kDppMirror8>(b2 ? u4[k] : u4[k + 2]);
-                float z = (b1 ? u2[1] : u2[0]) + dpp<kDppXor2>(b1 ? u2[0] : u2[1]);
-                z += dpp<kDppXor1>(z);
-                if (!(kq & 1) && g1 <= g2) {
-                    const int i = 4 * (b3 ? g2 : g1) + (b2 ? 2 : 0) + (b1 ? 1 : 0);
-                    if (i < m && (!b3 || g2 > g1)) vt[i] = z;
-                }
-            }
-            __syncthreads();
-            KAMX_MARK(2);
-            // x_new = x + X^T t over column quads: quads c and Q-1-c form a
-            // pair (balanced: together they span m + 4 rows); 16 threads per
-            // pair take every 16th group of 4 rows, each reading a group's t
-            // and the 4 rows' entries of the quad as float4s; butterfly sum
-            // over the 16 threads
-            {
-                const int Q = (m + 3) >> 2;
-                const int g = tid >> 4, kq = tid & 15;
-                const int c1 = g, c2 = Q - 1 - g;
-                float4 s1 = make_float4(0.f, 0.f, 0.f, 0.f), s2 = s1;
-                if (c1 <= c2) {
-#pragma unroll
-                    for (int part = 0; part < 2; ++part) {
-                        if (part == 1 && c2 == c1) break;
-                        const int c = part == 0 ? c1 : c2;
-                        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f), acc2 = acc;
-                        // four consecutive rows per step (one float4 of t), every
-                        // 64th row group; packed rows are padded to 4 floats and
-                        // the pads hold 0, so the quad that contains the diagonal
-                        // reads as-is, and t is 0 past row m (the rows there, up
-                        // to the next multiple of 4, hold finite values)
-                        for (int r = 4 * c + 4 * kq; r < m; r += 64) {
-                            const float4 tv = *reinterpret_cast<const float4 *>(vt + r);
-                            const float4 x0 = *reinterpret_cast<const float4 *>(A + tri_row_offset(r) + 4 * c);
-                            const float4 x1 = *reinterpret_cast<const float4 *>(A + tri_row_offset(r + 1) + 4 * c);
-                            const float4 x2 = *reinterpret_cast<const float4 *>(A + tri_row_offset(r + 2) + 4 * c);
-                            const float4 x3 = *reinterpret_cast<const float4 *>(A + tri_row_offset(r + 3) + 4 * c);
-                            acc.x += x0.x * tv.x;
-                            acc.y += x0.y * tv.x;
-                            acc.z += x0.z * tv.x;
-                            acc.w += x0.w * tv.x;
-                            acc2.x += x1.x * tv.y;
-                            acc2.y += x1.y * tv.y;
-                            acc2.z += x1.z * tv.y;
-                            acc2.w += x1.w * tv.y;
-                            acc.x += x2.x * tv.z;
-                            acc.y += x2.y * tv.z;
-                            acc.z += x2.z * tv.z;
-                            acc.w += x2.w * tv.z;
-                            acc2.x += x3.x * tv.w;
-                            acc2.y += x3.y * tv.w;
-                            acc2.z += x3.z * tv.w;
-                            acc2.w += x3.w * tv.w;
+                        for (int part = 0; part < 2; ++part) {
+                            if (part == 1 && c2 == c1) break;
+                            const int c = part == 0 ? c1 : c2;
+                            float4 acc = make_float4(0.f, 0.f, 0.f, 0.f), acc2 = acc;
+                            // four consecutive rows per step (one float4 of t), every
+                            // 64th row group; packed rows are padded to 4 floats and
+                            // the pads hold 0, so the quad that contains the diagonal
+                            // reads as-is, and t is 0 past row m (the rows there, up
+                            // to the next multiple of 4, hold finite values)
+                            for (int r = 4 * c + 4 * kq; r < m; r += 64) {
+                                const float4 tv = *reinterpret_cast<const float4 *>(vt + r);
+                                const float4 x0 = *reinterpret_cast<const float4 *>(A + tri_row_offset(r) + 4 * c);
+                                const float4 x1 = *reinterpret_cast<const float4 *>(A + tri_row_offset(r + 1) + 4 * c);
+                                const float4 x2 = *reinterpret_cast<const float4 *>(A + tri_row_offset(r + 2) + 4 * c);
+                                const float4 x3 = *reinterpret_cast<const float4 *>(A + tri_row_offset(r + 3) + 4 * c);
+                                acc.x += x0.x * tv.x;
+                                acc.y += x0.y * tv.x;
+                                acc.z += x0.z * tv.x;
+                                acc.w += x0.w * tv.x;
+                                acc2.x += x1.x * tv.y;
+                                acc2.y += x1.y * tv.y;
+                                acc2.z += x1.z * tv.y;
+                                acc2.w += x1.w * tv.y;
+                                acc.x += x2.x * tv.z;
+                                acc.y += x2.y * tv.z;
+                                acc.z += x2.z * tv.z;
+                                acc.w += x2.w * tv.z;
+                                acc2.x += x3.x * tv.w;
+                                acc2.y += x3.y * tv.w;
+                                acc2.z += x3.z * tv.w;
+                                acc2.w += x3.w * tv.w;
+                            }
+                            acc.x += acc2.x;
+                            acc.y += acc2.y;
+                            acc.z += acc2.z;
+                            acc.w += acc2.w;
+                            if (part == 0) s1 = acc;
+                            else s2 = acc;
                         }
-                        acc.x += acc2.x;
-                        acc.y += acc2.y;
-                        acc.z += acc2.z;
-                        acc.w += acc2.w;
-                        if (part == 0) s1 = acc;
-                        else s2 = acc;
+                    }
+                    // reduce-scatter over the 16 lanes: halve the eight sums at each
+                    // exchange (row mirror, half-row mirror, then pairs), so that
+                    // lanes 2k and 2k+1 end with sum 4 b3 + 2 b2 + b1 of the bits
+                    // of k; the even lane writes it
+                    const bool b3 = kq & 8, b2 = kq & 4, b1 = kq & 2;
+                    const float v8[8] = {s1.x, s1.y, s1.z, s1.w, s2.x, s2.y, s2.z, s2.w};
+                    float u4[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        u4[k] = (b3 ? v8[k + 4] : v8[k]) + dpp<kDppMirror16>(b3 ? v8[k] : v8[k + 4]);
+                    float u2[2];
+#pragma unroll
+                    for (int k = 0; k < 2; ++k)
+                        u2[k] = (b2 ? u4[k + 2] : u4[k]) + dpp<kDppMirror8>(b2 ? u4[k] : u4[k + 2]);
+                    float z = (b1 ? u2[1] : u2[0]) + dpp<kDppXor2>(b1 ? u2[0] : u2[1]);
+                    z += dpp<kDppXor1>(z);
+                    if (!(kq & 1) && c1 <= c2) {
+                        const int idx = (b3 ? 4 : 0) + (b2 ? 2 : 0) + (b1 ? 1 : 0);
+                        const int j = 4 * (b3 ? c2 : c1) + (idx & 3);
+                        if (j < m && (!b3 || c2 > c1)) vxn[j] = vx[j] + z;
                     }
                 }
-                // reduce-scatter over the 16 lanes: halve the eight sums at each
-                // exchange (row mirror, half-row mirror, then pairs), so that
-                // lanes 2k and 2k+1 end with sum 4 b3 + 2 b2 + b1 of the bits
-                // of k; the even lane writes it
-                const bool b3 = kq & 8, b2 = kq & 4, b1 = kq & 2;
-                const float v8[8] = {s1.x, s1.y, s1.z, s1.w, s2.x, s2.y, s2.z, s2.w};
-                float u4[4];
-#pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    u4[k] = (b3 ? v8[k + 4] : v8[k]) + dpp<kDppMirror16>(b3 ? v8[k] : v8[k + 4]);
-                float u2[2];
-#pragma unroll
-                for (int k = 0; k < 2; ++k)
-                    u2[k] = (b2 ? u4[k + 2] : u4[k]) + dpp<kDppMirror8>(b2 ? u4[k] : u4[k + 2]);
-                float z = (b1 ? u2[1] : u2[0]) + dpp<kDppXor2>(b1 ? u2[0] : u2[1]);
-                z += dpp<kDppXor1>(z);
-                if (!(kq & 1) && c1 <= c2) {
-                    const int idx = (b3 ? 4 : 0) + (b2 ? 2 : 0) + (b1 ? 1 : 0);
-                    const int j = 4 * (b3 ? c2 : c1) + (idx & 3);
-                    if (j < m && (!b3 || c2 > c1)) vxn[j] = vx[j] + z;
-                }
-            }
-            __syncthreads();
-            KAMX_MARK(3);
-            // v~ - v~_f = D~ x_new (matrix-free, FP64): bodies gather here,
-            // each block owner evaluates its own rows below
-            delassus_gather_bal<NT>(L, nb, gnh, gorder, vp, vxn);
-            KAMX_MARK(4);
-            // steps 6-7 and the residuals of step 9 (block owners)
-            float lrp = 0.f, lrd = 0.f, lrc = 0.f, lcc = 0.f;
-            float yb[3], zb[3], xn[3], rr[3];
-            // v~ - v~_f of row io in FP64: J_a M_a^-1 g_a on the even lane,
-            // J_b M_b^-1 g_b on the odd lane, added by the pair sum
-            {
-                double side = 0.0;
-                if (io < m) {
-                    const int sb = hh == 0 ? L.ri(RIA, io) : L.ri(RIB, io);
-                    if (sb >= 0) {
-                        double wv[6];
-                        body_minv64(L, sb, wv);
-                        for (int c = 0; c < 6; ++c) side += (double)L.rf(RJ + 6 * hh + c, io) * wv[c];
+                __syncthreads();
+                KAMX_MARK(3);
+                // v~ - v~_f = D~ x_new (matrix-free, FP64): bodies gather here,
+                // each block owner evaluates its own rows below
+                delassus_gather_bal<NT>(L, nb, gnh, gorder, vp, vxn);
+                KAMX_MARK(4);
+                // steps 6-7 and the residuals of step 9 (block owners)
+                float lrp = 0.f, lrd = 0.f, lrc = 0.f, lcc = 0.f;
+                float yb[3], zb[3], xn[3], rr[3];
+                // v~ - v~_f of row io in FP64: J_a M_a^-1 g_a on the even lane,
+                // J_b M_b^-1 g_b on the odd lane, added by the pair sum
+                {
+                    double side = 0.0;
+                    if (io < m) {
+                        const int sb = hh == 0 ? L.ri(RIA, io) : L.ri(RIB, io);
+                        if (sb >= 0) {
+                            double wv[6];
+                            body_minv64(L, sb, wv);
+                            for (int c = 0; c < 6; ++c) side += (double)L.rf(RJ + 6 * hh + c, io) * wv[c];
+                        }
+                    }
+                    side = lane_group_sum<2>(side);
+                    if (hh == 0 && io < m) {
+                        const double pr = (double)vp[io];
+                        vdx[io] = (float)((side + (double)L.rf(RREG, io) * pr * (double)vxn[io]) * pr);
                     }
                 }
-                side = lane_group_sum<2>(side);
-                if (hh == 0 && io < m) {
-                    const double pr = (double)vp[io];
-                    vdx[io] = (float)((side + (double)L.rf(RREG, io) * pr * (double)vxn[io]) * pr);
-                }
-            }
-            __syncthreads();
-            if (owner_o) {
-                float zh[3], yh[3], ri[3], vv[3];
-                _Pragma("unroll") for (int e = 0; e < 3; ++e) if (e < blk_o) {
-                    const float dx = vdx[io + e];
-                    xn[e] = vxn[io + e];
-                    zh[e] = vzh[io + e];
-                    yh[e] = vyh[io + e];
-                    rr[e] = e == 0 ? rho_o : vrho[io + e];
-                    ri[e] = vrinv[io + e];
-                    vv[e] = dx + vvt[io + e];
-                }
-                if (kind_o == kRowNormal) {
-                    proj_cone(mu_o, xn[0] - zh[0] * ri[0], xn[1] - zh[1] * ri[1], xn[2] - zh[2] * ri[2], yb[0], yb[1],
-                              yb[2]);
-                } else if (kind_o == kRowLimit) {
-                    yb[0] = fmaxf(xn[0] - zh[0] * ri[0], 0.f);
-                } else {
-                    yb[0] = xn[0] - zh[0] * ri[0];
-                }
-                _Pragma("unroll") for (int e = 0; e < 3; ++e) if (e < blk_o) {
-                    zb[e] = zh[e] - rr[e] * (xn[e] - yb[e]);
-                    lrp = fmaxf(lrp, fabsf(xn[e] - yb[e]));
-                    float dy = yb[e] - yh[e], dz = zb[e] - zh[e];
-                    lcc += rr[e] * dy * dy + dz * dz * ri[e];
-                }
-                float g = kind_o == kRowNormal ? mu_o * hw_sqrt(vv[1] * vv[1] + vv[2] * vv[2]) : 0.f;
-                _Pragma("unroll") for (int e = 0; e < 3; ++e) if (e < blk_o) {
-                    float d = vv[e] + (e == 0 ? g : 0.f) - zb[e];
-                    lrd = fmaxf(lrd, fabsf(d));
-                    if (d != d) lrd = d;
-                }
-                if (kind_o == kRowNormal) lrc = fabsf(yb[0] * (vv[0] + g) + yb[1] * vv[1] + yb[2] * vv[2]);
-                else if (kind_o == kRowLimit) lrc = fabsf(yb[0] * vv[0]);
-                if (lrp != lrp || lcc != lcc) lrp = NAN;
-            }
-            reduce4<NT>(lrp, lrd, lrc, lcc, L.red);
-            rp = lrp;
-            rd = lrd;
-            rc = lrc;
-            KAMX_MARK(5);
-            // step 8: Nesterov with adaptive restart
-            int restart = 0;
-            float beta = 0.f;
-            if (P.accel) {
-                restart = !(lcc < P.restart_factor * c_prev);
-                if (!restart) {
-                    float a_next = 0.5f * (1.f + hw_sqrt(1.f + 4.f * a_k * a_k));
-                    beta = (a_k - 1.f) * hw_rcp(a_next);
-                    a_k = a_next;
-                    c_prev = lcc;
-                } else {
-                    a_k = 1.f;
-                    c_prev = c_prev / P.restart_factor;
-                }
-            }
-            if (owner_o) {
-                float yn[3] = {0.f, 0.f, 0.f}, zn[3] = {0.f, 0.f, 0.f};
-                _Pragma("unroll") for (int e = 0; e < 3; ++e) if (e < blk_o) {
-                    float yo = vyp[io + e], zo = vzp[io + e];
-                    if (!P.accel) {
-                        yn[e] = yb[e];
-                        zn[e] = zb[e];
-                    } else if (!restart) {
-                        yn[e] = yb[e] + beta * (yb[e] - yo);
-                        zn[e] = zb[e] + beta * (zb[e] - zo);
+                __syncthreads();
+                if (owner_o) {
+                    float zh[3], yh[3], ri[3], vv[3];
+                    _Pragma("unroll") for (int e = 0; e < 3; ++e) if (e < blk_o) {
+                        const float dx = vdx[io + e];
+                        xn[e] = vxn[io + e];
+                        zh[e] = vzh[io + e];
+                        yh[e] = vyh[io + e];
+                        rr[e] = e == 0 ? rho_o : vrho[io + e];
+                        ri[e] = vrinv[io + e];
+                        vv[e] = dx + vvt[io + e];
+                    }
+                    if (kind_o == kRowNormal) {
+                        proj_cone(mu_o, xn[0] - zh[0] * ri[0], xn[1] - zh[1] * ri[1], xn[2] - zh[2] * ri[2], yb[0], yb[1],
+                                  yb[2]);
+                    } else if (kind_o == kRowLimit) {
+                        yb[0] = fmaxf(xn[0] - zh[0] * ri[0], 0.f);
                     } else {
-                        yn[e] = yo;
-                        zn[e] = zo;
+                        yb[0] = xn[0] - zh[0] * ri[0];
                     }
-                    vyh[io + e] = yn[e];
-                    vzh[io + e] = zn[e];
-                    vx[io + e] = xn[e];
-                    vyp[io + e] = yb[e];
-                    vzp[io + e] = zb[e];
+                    _Pragma("unroll") for (int e = 0; e < 3; ++e) if (e < blk_o) {
+                        zb[e] = zh[e] - rr[e] * (xn[e] - yb[e]);
+                        lrp = fmaxf(lrp, fabsf(xn[e] - yb[e]));
+                        float dy = yb[e] - yh[e], dz = zb[e] - zh[e];
+                        lcc += rr[e] * dy * dy + dz * dz * ri[e];
+                    }
+                    float g = kind_o == kRowNormal ? mu_o * hw_sqrt(vv[1] * vv[1] + vv[2] * vv[2]) : 0.f;
+                    _Pragma("unroll") for (int e = 0; e < 3; ++e) if (e < blk_o) {
+                        float d = vv[e] + (e == 0 ? g : 0.f) - zb[e];
+                        lrd = fmaxf(lrd, fabsf(d));
+                        if (d != d) lrd = d;
+                    }
+                    if (kind_o == kRowNormal) lrc = fabsf(yb[0] * (vv[0] + g) + yb[1] * vv[1] + yb[2] * vv[2]);
+                    else if (kind_o == kRowLimit) lrc = fabsf(yb[0] * vv[0]);
+                    if (lrp != lrp || lcc != lcc) lrp = NAN;
                 }
-                // the next right-hand side (as own_rhs) from the values in registers
-                s_own = kind_o == kRowNormal ? mu_o * hw_sqrt(zn[1] * zn[1] + zn[2] * zn[2]) : 0.f;
-                _Pragma("unroll") for (int e = 0; e < 3; ++e) if (e < blk_o) {
-                    float rhs = -vvt[io + e] - (e == 0 ? s_own : 0.f) + eta * xn[e] + rr[e] * yn[e] + zn[e];
-                    vrhs[io + e] = rhs - (vdx[io + e] + (eta + rr[e]) * xn[e]);
+                reduce4<NT>(lrp, lrd, lrc, lcc, L.red);
+                rp = lrp;
+                rd = lrd;
+                rc = lrc;
+                KAMX_MARK(5);
+                // step 8: Nesterov with adaptive restart
+                int restart = 0;
+                float beta = 0.f;
+                if (P.accel) {
+                    restart = !(lcc < P.restart_factor * c_prev);
+                    if (!restart) {
+                        float a_next = 0.5f * (1.f + hw_sqrt(1.f + 4.f * a_k * a_k));
+                        beta = (a_k - 1.f) * hw_rcp(a_next);
+                        a_k = a_next;
+                        c_prev = lcc;
+                    } else {
+                        a_k = 1.f;
+                        c_prev = c_prev / P.restart_factor;
+                    }
+                }
+                if (owner_o) {
+                    float yn[3] = {0.f, 0.f, 0.f}, zn[3] = {0.f, 0.f, 0.f};
+                    _Pragma("unroll") for (int e = 0; e < 3; ++e) if (e < blk_o) {
+                        float yo = vyp[io + e], zo = vzp[io + e];
+                        if (!P.accel) {
+                            yn[e] = yb[e];
+                            zn[e] = zb[e];
+                        } else if (!restart) {
+                            yn[e] = yb[e] + beta * (yb[e] - yo);
+                            zn[e] = zb[e] + beta * (zb[e] - zo);
+                        } else {
+                            yn[e] = yo;
+                            zn[e] = zo;
+                        }
+                        vyh[io + e] = yn[e];
+                        vzh[io + e] = zn[e];
+                        vx[io + e] = xn[e];
+                        vyp[io + e] = yb[e];
+                        vzp[io + e] = zb[e];
+                    }
+                    // the next right-hand side (as own_rhs) from the values in registers
+                    s_own = kind_o == kRowNormal ? mu_o * hw_sqrt(zn[1] * zn[1] + zn[2] * zn[2]) : 0.f;
+                    _Pragma("unroll") for (int e = 0; e < 3; ++e) if (e < blk_o) {
+                        float rhs = -vvt[io + e] - (e == 0 ? s_own : 0.f) + eta * xn[e] + rr[e] * yn[e] + zn[e];
+                        vrhs[io + e] = rhs - (vdx[io + e] + (eta + rr[e]) * xn[e]);
+                    }
+                }
+                KAMX_MARK(6);
+                // adaptive penalty (not in the paper: residual balancing) at the
+                // checkpoints of a solve that does not exit here; rp and rd are
+                // the same in every thread, so the branch is uniform
+                int adapt_dir = 0;
+                if (P.adapt_ratio > 0.f && n_uni > 0 && adapt_checkpoint(it, P.adapt_first) &&
+                    !(P.fixed_iters <= 0 && rp < P.eps && rd < P.eps && rc < P.eps)) {
+                    if (rd > P.adapt_ratio * rp) adapt_dir = 1;
+                    else if (rp > P.adapt_ratio * rd) adapt_dir = 2;
+                }
+                if (tid == 0 && a.rlog && P.log_restarts && it <= P.max_iters)
+                    a.rlog[(size_t)w * P.max_iters + (it - 1)] = (uint8_t)(restart | (adapt_dir << 1));
+                if (!(isfinite(rp) && isfinite(rd) && isfinite(rc))) {
+                    status = KAMX_WORLD_NONFINITE;
+                    break;
+                }
+                if (P.fixed_iters <= 0 && rp < P.eps && rd < P.eps && rc < P.eps) {
+                    converged = true;
+                    break;
+                }
+                if (adapt_dir) {
+                    adapt_pending = adapt_dir;
+                    ++it;
+                    break;
                 }
             }
-            KAMX_MARK(6);
-            if (tid == 0 && a.rlog && P.log_restarts && it <= P.max_iters)
-                a.rlog[(size_t)w * P.max_iters + (it - 1)] = (uint8_t)restart;
-            if (!(isfinite(rp) && isfinite(rd) && isfinite(rc))) {
-                status = KAMX_WORLD_NONFINITE;
-                break;
-            }
-            if (P.fixed_iters <= 0 && rp < P.eps && rd < P.eps && rc < P.eps) {
-                converged = true;
-                break;
+            if (!adapt_pending) break;
+            {
+                // the limit and contact rows' penalty changes by the factor;
+                // D~ + diag(eta + rho) is rebuilt, refactored and inverted, and
+                // the acceleration restarts at the current (y, z)
+                const float f = adapt_pending == 1 ? 1.f / P.adapt_factor : P.adapt_factor;
+                adapt_pending = 0;
+                __syncthreads();
+                for (int r = tid; r < m; r += NT)
+                    if (L.ri(RKIND, r) != kRowBilateral) {
+                        vrho[r] *= f;
+                        vrinv[r] = 1.f / vrho[r];
+                    }
+                __syncthreads();
+                reassemble<MC, NT>(L, A, m, nb, vp, vrho, eta);
+                if (factor_invert_again<MC, NT>(L, A, m, s_int, a, w)) {
+                    status = KAMX_WORLD_FACTOR_FAIL;
+                    break;
+                }
+                rho_o = io < m ? vrho[io] : 1.f;
+                a_k = 1.f;
+                c_prev = INFINITY;
+                if (owner_o) {
+                    _Pragma("unroll") for (int e = 0; e < 3; ++e) if (e < blk_o) {
+                        vyh[io + e] = vyp[io + e];
+                        vzh[io + e] = vzp[io + e];
+                    }
+                }
+                __syncthreads();
+                own_rhs();
             }
         }
 #undef KAMX_MARK
@@ -1693,10 +2060,10 @@ __global__ void impulse_slots_kernel(const WorldInfo *worlds, int n_worlds, int 
     if (t < rc0) {
         v = lambda[W.row_base + t];
     } else {
-        const int key = (t - rc0) / 3, e = (t - rc0) % 3;
+        const int slot = (t - rc0) / 3, e = (t - rc0) % 3;
         const int n = ncontacts[w];
         for (int k = 0; k < n && k < kMaxContacts; ++k)
-            if (keys[w * kMaxContacts + k] == key) {
+            if (keys[w * kMaxContacts + k] >= 0 && contact_slot(keys[w * kMaxContacts + k]) == slot) {
                 v = lambda[W.row_base + rc0 + 3 * k + e];
                 break;
             }

@@ -36,6 +36,7 @@ class kamx_params(C.Structure):
         ("warmstart", C.c_int32), ("contact_margin", C.c_float), ("torque_sigma", C.c_float),
         ("seed", C.c_uint64), ("reset_height", C.c_float), ("log_restarts", C.c_int32),
         ("integrator", C.c_int32), ("linear_solver", C.c_int32), ("cr_iters", C.c_int32),
+        ("adapt_ratio", C.c_float), ("adapt_factor", C.c_float), ("adapt_first", C.c_int32),
     ]
 
 

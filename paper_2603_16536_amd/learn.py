@@ -82,15 +82,16 @@ def validation_loss(net, X, Y, batch=4096):
     return se / max(cnt, 1)
 
 
-def fit(model_factory, train_steps, epochs=60, batch=4096, lr=1e-3, seed=0, n_hidden=256, log=None):
+def fit(model_factory, train_steps, epochs=60, batch=4096, lr=1e-3, seed=0, n_hidden=256, log=None, capacity=None):
     """Collect a cold rollout from ``model_factory()`` and train a network
-    on it.  Returns (net, info)."""
+    on it (batch capacity: ``capacity`` worlds, at least ``batch``).
+    Returns (net, info)."""
     m = model_factory()
     X, Y = collect(m, train_steps)
     nf, ns = m.feature_dims()
     m.close()
     mu_x, sd_x, mu_y, sd_y = normalization(X, Y)
-    net = kamx.MLP(nf, ns, n_hidden=n_hidden, max_batch=batch, seed=seed)
+    net = kamx.MLP(nf, ns, n_hidden=n_hidden, max_batch=max(batch, capacity or 0), seed=seed)
     net.set_normalization(mu_x, sd_x, mu_y, sd_y + 1e-6)
     net.out_mean, net.out_std = mu_y, sd_y + 1e-6
     # hold out the last tenth of the rollout

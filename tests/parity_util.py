@@ -12,7 +12,8 @@ def oracle_params(p: "kamx.kamx_params", **over):
     P = oracle.Params(dt=p.dt, gravity=tuple(p.gravity), eta=p.eta, rho_bil=p.rho_bilateral, rho_c=p.rho_contact,
                       eps=p.eps, max_iters=p.max_iters, fixed_iters=p.fixed_iters, accel=p.accel,
                       restart_factor=p.restart_factor, precond=p.precond, baumgarte=p.baumgarte,
-                      integrator=p.integrator)
+                      integrator=p.integrator, adapt_ratio=p.adapt_ratio, adapt_factor=p.adapt_factor,
+                      adapt_first=p.adapt_first)
     return P.replace(**over)
 
 
@@ -54,20 +55,31 @@ def gpu_step(scene, params, explicit_contacts=True, ext=None, max_contacts=None,
     return out
 
 
+def contact_slot(key):
+    """Slot of a contact key in the learned layout: the key modulo 512 (the
+    probe index; box * 8 + vertex for generated box contacts)."""
+    return int(key) & 511
+
+
 def slots_to_rows(pred, model, scene):
-    """Impulses by slot (joint rows, then three slots per contact key) put on
-    the rows of the contacts the model's last step used (host mapping)."""
+    """Impulses by slot (joint, limit and drive rows, then three slots per
+    contact slot) put on the rows of the contacts the model's last step
+    used (host mapping)."""
     raw, cnt = model.contacts()
     used = kamx.contacts_to_scene(scene, raw, cnt)
-    nj = scene.joint_offsets()
+    jo = scene.joint_offsets()
+    lim = np.any(np.isfinite(scene.joint_limit), axis=1) if scene.n_joints else np.zeros(0, bool)
+    drv = getattr(scene, "joint_drive", None)
+    driven = (np.any(drv[:, :4] != 0.0, axis=1) if drv is not None and drv.shape[0] == scene.n_joints
+              else np.zeros(scene.n_joints, bool))
     ro = model.row_offsets
     lam = np.zeros(int(ro[-1]), np.float32)
     co = used.contact_offsets()
     for w in range(scene.n_worlds):
-        rc0 = 5 * (nj[w + 1] - nj[w])
+        rc0 = 5 * (jo[w + 1] - jo[w]) + int(lim[jo[w]:jo[w + 1]].sum()) + int(driven[jo[w]:jo[w + 1]].sum())
         lam[ro[w]:ro[w] + rc0] = pred[w, :rc0]
         for c in range(co[w], co[w + 1]):
-            k = int(used.contact_key[c])
+            k = contact_slot(used.contact_key[c])
             lam[ro[w] + rc0 + 3 * (c - co[w]):ro[w] + rc0 + 3 * (c - co[w]) + 3] = pred[w, rc0 + 3 * k:rc0 + 3 * k + 3]
     return lam, used
 

@@ -33,13 +33,28 @@ def test_every_declared_symbol_is_exported(libkamx):
     assert not missing, missing
 
 
-def test_struct_sizes_match_the_header_layout():
+def test_struct_sizes_match_the_header_layout(tmp_path):
+    """The binding's structs have the sizes and field offsets that the C
+    compiler gives the header's."""
+    import subprocess
     from paper_2603_16536_amd import kamx
-    assert C.sizeof(kamx.kamx_body_desc) == 20
-    assert C.sizeof(kamx.kamx_joint_desc) == 108
-    assert C.sizeof(kamx.kamx_probe_desc) == 24
-    assert kamx.CONTACT_DTYPE.itemsize == 44
-    assert C.sizeof(kamx.kamx_params) == 104
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    fields = [name for name, _ in kamx.kamx_params._fields_]
+    src = tmp_path / "sizes.c"
+    src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"kamx.h\"\nint main(void) {\n"
+                   "printf(\"%zu %zu %zu %zu %zu\\n\", sizeof(kamx_params), sizeof(kamx_body_desc), "
+                   "sizeof(kamx_joint_desc), sizeof(kamx_probe_desc), sizeof(kamx_contact));\n"
+                   + "".join(f'printf("%zu\\n", offsetof(kamx_params, {f}));\n' for f in fields)
+                   + "return 0;\n}\n")
+    exe = tmp_path / "sizes"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(root, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    sizes, offsets = [int(v) for v in out[:5]], [int(v) for v in out[5:]]
+    assert sizes == [C.sizeof(kamx.kamx_params), C.sizeof(kamx.kamx_body_desc), C.sizeof(kamx.kamx_joint_desc),
+                     C.sizeof(kamx.kamx_probe_desc), kamx.CONTACT_DTYPE.itemsize]
+    assert offsets == [getattr(kamx.kamx_params, f).offset for f in fields]
+    assert kamx.BODY_DTYPE.itemsize == sizes[1] and kamx.JOINT_DTYPE.itemsize == sizes[2]
+    assert kamx.PROBE_DTYPE.itemsize == sizes[3]
 
 
 def test_defaults_and_host_side_validation(libkamx):

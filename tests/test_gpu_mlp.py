@@ -385,3 +385,82 @@ def test_trained_network_cuts_iterations():
     print(f"\nheld-out loss {info['val_loss']:.3f}; mean iterations cold {c:.1f}, learned {l:.1f}; "
           f"median {np.median(iters['cold']):.0f} -> {np.median(iters['learned']):.0f}")
     assert l < 0.98 * c
+
+
+def test_box_bin_learned_warm_start():
+    """Boxes in a bin with contacts generated inside the step: the learned
+    warm start's contact slots are box * 8 + vertex (the contact key modulo
+    512), 160 for 20 boxes, so the network is 740 -> 256 -> 256 -> 480.  A
+    network fitted to cold solves of other drops steps a pile: equal, bit
+    for bit, to an external warm start with its prediction put on the rows
+    by slot, and each converged world against the oracle's solve from that
+    warm start (the unique quantities within the distance the tolerance
+    allows)."""
+    from parity_util import compare_worlds, slots_to_rows, summary, within_tolerance_bound
+    n = 32
+    p = dict(BIPED, torque_sigma=0.0, max_iters=2000, log_restarts=0)
+
+    def pile(seed, steps):
+        sc = scenes.round_to_f32(scenes.box_bin_batch(n, seed=seed))
+        m = kamx.Model(sc, params=p, max_contacts=64)
+        m.contacts_box_bin(scenes.BIN_HALF, 0.01)
+        m.step(steps)
+        q, u = (t.cpu().numpy().astype(np.float64) for t in m.state())
+        m.close()
+        return sc.replace(q=q, u=u)
+
+    # training data: cold solves along a rollout of other drops
+    tr = scenes.round_to_f32(scenes.box_bin_batch(n, seed=2005))
+    m = kamx.Model(tr, params=p, max_contacts=64)
+    m.contacts_box_bin(scenes.BIN_HALF, 0.01)
+    nf, ns = m.feature_dims()
+    assert (nf, ns) == (13 * 20 + 3 * 160, 3 * 160)
+    m.step(60)
+    X, Y = [], []
+    for _ in range(60):
+        X.append(m.features().clone())
+        m.step(1)
+        Y.append(m.impulse_slots().clone())
+    m.close()
+    X, Y = torch.cat(X), torch.cat(Y)
+    net = kamx.MLP(nf, ns, n_hidden=256, max_batch=X.shape[0], seed=5)
+    sd_x, sd_y = X.std(0), Y.std(0)
+    net.set_normalization(X.mean(0).cpu().numpy(), torch.where(sd_x > 1e-6, sd_x, torch.ones_like(sd_x)).cpu().numpy(),
+                          Y.mean(0).cpu().numpy(), (sd_y + 1e-6).cpu().numpy())
+    for _ in range(200):
+        net.train_step(X, Y, 1e-3)
+    s1 = pile(1005, 150)
+    models = []
+    for mode in (kamx.WARM_LEARNED, kamx.WARM_EXTERNAL, kamx.WARM_COLD):
+        mm = kamx.Model(s1, params=dict(p, warmstart=mode), max_contacts=64)
+        mm.contacts_box_bin(scenes.BIN_HALF, 0.01)
+        models.append(mm)
+    A, B, Cm = models
+    pred = net.forward(A.features()).cpu().numpy()
+    A.attach_mlp(net)
+    A.step(1)
+    Cm.step(1)
+    lam_ws, used = slots_to_rows(pred, Cm, s1)
+    raw, cnt = A.contacts()
+    B.set_warmstart(lam_ws)
+    B.step(1)
+    torch.cuda.synchronize()
+    for x, y in zip(A.state(), B.state()):
+        assert torch.equal(x, y)
+    assert torch.equal(A.impulses(), B.impulses())
+    it_l, it_c = (mm.stats()["iters"].cpu().numpy() for mm in (A, Cm))
+    print(f"\nbox bin, {n} piles: iterations learned mean {it_l.mean():.1f} (p50 {np.median(it_l):.0f}), "
+          f"cold {it_c.mean():.1f} (p50 {np.median(it_c):.0f})")
+    st = {k: v.cpu().numpy() for k, v in B.stats().items()}
+    q2, u2 = (t.cpu().numpy().astype(np.float64) for t in B.state())
+    g = dict(q=q2, u=u2, lam=B.impulses().cpu().numpy().astype(np.float64), row_offsets=B.row_offsets,
+             used_scene=used, inputs=dict(box_bin=None, explicit=True, ext=None, step=0), **st)
+    for mm in models:
+        mm.close()
+    worlds = np.nonzero(st["status"] == 0)[0][:8]
+    assert len(worlds) >= 4
+    rs = compare_worlds(used, kamx.make_params(**dict(p, warmstart=kamx.WARM_EXTERNAL)), g, worlds,
+                        mode="reference", warm=lam_ws, tol_run=True)
+    summary("box bin, learned warm start (as external), against the oracle from the same start", rs)
+    assert within_tolerance_bound(rs, 1e-4) < 1.0
+    net.close()
