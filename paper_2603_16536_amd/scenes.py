@@ -736,6 +736,31 @@ FIGURE_PD = {"base": (400.0, 8.0), "leg": (200.0, 4.0), "torso": (300.0, 6.0), "
              "arm": (100.0, 2.0), "finger": (0.2, 0.004)}  # N m / rad, N m s / rad
 
 
+def axis_inertia(mass, inertia, pose, point, axis):
+    """Moment of inertia of one body about the line through ``point`` along
+    the unit ``axis`` (world frame): the principal inertia rotated to the
+    world, plus the parallel-axis term of the centre of mass."""
+    a = np.asarray(axis, np.float64)
+    a = a / np.linalg.norm(a)
+    R = quat_to_mat(np.asarray(pose[3:], np.float64))
+    Iw = R @ np.diag(np.asarray(inertia, np.float64)) @ R.T
+    r = np.asarray(pose[:3], np.float64) - np.asarray(point, np.float64)
+    return float(a @ Iw @ a + mass * (r @ r - (a @ r) ** 2))
+
+
+def explicit_pd_gains(nominal, mass, inertia, pose, point, axis, dt):
+    """Gains of an explicit PD torque on a joint, capped so that it stays
+    stable at step dt: an explicit spring-damper on an inertia I advances
+    omega by -(kd dt / I) omega - (kp dt^2 / I) theta per step, which is
+    stable for kd dt / I < 2 and kp dt^2 / I small; the caps are
+    kd dt / I <= 0.5 and kp dt^2 / I <= 0.1 with I the child body's own
+    inertia about the joint axis (the subtree moved by the joint only adds
+    to it)."""
+    kp, kd = nominal
+    I = axis_inertia(mass, inertia, pose, point, axis)
+    return min(kp, 0.1 * I / (dt * dt)), min(kd, 0.5 * I / dt)
+
+
 def _perp_pair(a):
     """Two unit vectors completing the unit axis a to a right-handed frame."""
     a = np.asarray(a, np.float64)
@@ -776,7 +801,8 @@ def figure_world(rng, dt=2e-3, link_masses=None):
         b = _rod_body(B, p0, p1, mass, width=width)
         K = np.asarray(p0 if joint_point is None else joint_point, np.float64)
         if act:
-            B.joint(REVOLUTE, b, parent, K, axis, actuated=1, pd=FIGURE_PD[kind])
+            B.joint(REVOLUTE, b, parent, K, axis, actuated=1,
+                    pd=explicit_pd_gains(FIGURE_PD[kind], B.mass[b], B.inertia[b], B.q[b], K, axis, dt))
         else:  # a passive spring-damper coupling, solved as an implicit drive row
             kp, kd = FIGURE_PD[kind]
             B.joint(REVOLUTE, b, parent, K, axis, drive=(kp, kd, 0.0, 0.0, 0.0))
@@ -784,7 +810,9 @@ def figure_world(rng, dt=2e-3, link_masses=None):
         return b
 
     base = B.body(8.0, box_inertia(8.0, 0.30, 0.22, 0.16), (0.0, 0.0, H), ident)
-    B.joint(REVOLUTE, base, -1, (0.0, 0.0, H - 0.08), za, actuated=1, pd=FIGURE_PD["base"])
+    B.joint(REVOLUTE, base, -1, (0.0, 0.0, H - 0.08), za, actuated=1,
+            pd=explicit_pd_gains(FIGURE_PD["base"], B.mass[base], B.inertia[base], B.q[base], (0.0, 0.0, H - 0.08),
+                                 za, dt))
     # legs
     for sd in (1.0, -1.0):
         y = 0.1 * sd

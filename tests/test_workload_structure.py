@@ -106,3 +106,56 @@ def test_fixed_figure_matches_the_largest_system_of_the_table():
     got_nb, types, cyc = world_topology(scene, 0)
     assert base == "fixed" and np.any(scene.joint_body[:, 1] < 0)
     assert (got_nb, int(types.sum()), int(scene.joint_actuated.sum()), cyc) == (nb, na + npas, na, loops)
+
+
+def test_fixed_figure_explicit_gains_are_stable_at_its_step():
+    """An explicit PD torque on a joint whose moving side has inertia I about
+    the joint axis advances omega by -(kd dt / I) omega - (kp dt^2 / I) theta
+    per step: the figure's actuated joints keep kd dt / I <= 0.5 and
+    kp dt^2 / I <= 0.1 against the child body's inertia about the axis,
+    taken here from the kinetic energy of a unit rotation about the joint
+    line (1/2 m |w x r|^2 + 1/2 w^T I_world w), and the heavy joints keep
+    their nominal gains."""
+    scene = scenes.figure_batch(1, seed=1007)
+    dt = 2e-3
+    nominal_kept = 0
+    for j in np.where(scene.joint_actuated)[0]:
+        child, _ = scene.joint_body[j]
+        fa = scene.joint_frame[j, :7]
+        Rb = scenes.quat_to_mat(scene.q[child][3:])
+        point = scene.q[child][:3] + Rb @ fa[:3]
+        axis = Rb @ scenes.quat_to_mat(fa[3:])[:, 0]
+        r = scene.q[child][:3] - point
+        v = np.cross(axis, r)
+        Iw = Rb @ np.diag(scene.body_inertia[child]) @ Rb.T
+        I = scene.body_mass[child] * (v @ v) + axis @ Iw @ axis
+        kp, kd = scene.joint_pd[j]
+        assert kd * dt / I <= 0.5 + 1e-9 and kp * dt * dt / I <= 0.1 + 1e-9, (j, kp, kd, I)
+        assert kp > 0.0 and kd > 0.0
+        nominal_kept += kp in (400.0, 300.0, 200.0, 100.0, 20.0)
+    assert nominal_kept >= 10
+
+
+def test_fixed_figure_rollout_stays_bounded(orc):
+    """Two figures under their explicit PD toward the assembled pose plus
+    N(0, 5 N m) torques, stepped by the oracle (exact x-updates): every step
+    converges to 1e-6 in a few iterations and the twists stay bounded."""
+    orc.set_threads(4)
+    scene = scenes.round_to_f32(scenes.figure_batch(2, seed=1007))
+    P = orc.Params(dt=2e-3, eta=1e-4, rho_bil=1e-4, rho_c=0.3, eps=1e-6, max_iters=200, baumgarte=0.2)
+    act = np.where(scene.joint_actuated)[0]
+    rng = np.random.default_rng(3)
+    q, u = scene.q.copy(), scene.u.copy()
+    for _ in range(8):
+        qr = orc.step_configuration(scene, P, q=q, u=u)
+        tau = np.zeros(scene.n_joints)
+        for j in act:
+            kp, kd = scene.joint_pd[j]
+            c, Ja, Jb = orc.joint_coordinate(scene, qr, j)
+            a, b = scene.joint_body[j]
+            rate = Ja @ u[a] + (Jb @ u[b] if b >= 0 else 0.0)
+            tau[j] = -kp * c - kd * rate + 5.0 * rng.normal()
+        o = orc.step(scene, P, q=q, u=u, joint_torque=tau)
+        assert np.all(o["status"] == orc.OK) and o["iters"].max() <= 10
+        q, u = o["q"], o["u"]
+    assert np.abs(u).max() < 100.0
