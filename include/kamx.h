@@ -457,8 +457,8 @@ kamx_status kamx_reset_count(kamx_model m, int64_t *count, kamx_stream stream);
  * (start, Delassus, warm start, factor, inverse, iterations, outputs, end),
  * entries 8-13 the ticks spent in the iteration sub-phases (right-hand side,
  * forward mat-vec, transposed mat-vec, body gather, projections and
- * residuals, updates), entry 14 the hardware id (XCC, shader engine, CU) of
- * the compute unit that ran the world.  Only available
+ * residuals, updates), entry 14 the index of the compute unit that ran the
+ * world and entry 15 its raw hardware id register.  Only available
  * when the environment variable KAMX_PHASE_CLOCK was set at model creation;
  * otherwise ESTATE. */
 kamx_status kamx_read_phase_clock(kamx_model m, uint64_t *clk_dev, kamx_stream stream);
