@@ -15,7 +15,7 @@ if not torch.cuda.is_available():
 
 from paper_2603_16536_amd import kamx, scenes  # noqa: E402
 
-from parity_util import compare_world  # noqa: E402
+from parity_util import compare_world, compare_worlds, summary  # noqa: E402
 
 TOL = 1e-4
 
@@ -87,4 +87,40 @@ def test_box_bin_16384_worlds_sampled():
     print(f"\nbox bin 16384 worlds, sample {ws.tolist()}, iters {g['iters'][ws].tolist()}: u+ {e[:, 0].max():.2e} "
           f"J^T lambda {e[:, 1].max():.2e} FP64 r_ncp {e[:, 2].max():.2e}; converged "
           f"{np.mean(g['status'] == 0):.4f}", flush=True)
+    assert e[:, 0].max() < TOL and e[:, 1].max() < TOL
+
+
+def test_figure_4096_worlds_matrix_free_sampled():
+    """4096 fixed figures (1014 rows each, matrix-free) in the benchmark's
+    launch configuration: 40 Conjugate Residual iterations per x-update, a
+    200-iteration budget, explicit PD toward the assembled pose plus noise
+    torques, from perturbed twists.  At least 99 % converge; on sampled
+    converged worlds, u+ and the net impulse per body within 1e-4 of the
+    oracle's own solve (exact x-updates by Cholesky, to 1e-8)."""
+    scene = scenes.round_to_f32(scenes.figure_batch(4096, seed=1007))
+    rng = np.random.default_rng(13)
+    scene = scenes.perturb_state(scene, rng, 0.05, 0.2)
+    scene.u = scene.u.astype(np.float32).astype(np.float64)
+    p = dict(dt=2e-3, eta=1e-4, rho_bilateral=1e-4, rho_contact=0.3, eps=1e-6, max_iters=200, torque_sigma=5.0,
+             seed=1007, cr_iters=40, log_restarts=1)
+    m = kamx.Model(scene, params=p)
+    assert [bk["rows"] for bk in m.buckets()] == [1024]
+    m.step(1)
+    torch.cuda.synchronize()
+    q, u = (t.cpu().numpy().astype(np.float64) for t in m.state())
+    st = {k: v.cpu().numpy() for k, v in m.stats().items()}
+    g = dict(q=q, u=u, lam=m.impulses().cpu().numpy().astype(np.float64), row_offsets=m.row_offsets,
+             restart_log=m.restart_log().cpu().numpy(), **st)
+    raw, cnt = m.contacts()
+    g["used_scene"] = kamx.contacts_to_scene(scene, raw, cnt)
+    g["inputs"] = dict(ext=None, explicit=False, step=0, pd=None, refs=None)
+    m.close()
+    conv = st["status"] == 0
+    print(f"\nfigure 4096: iterations mean {st['iters'].mean():.1f} max {st['iters'].max()}, converged {conv.mean():.4f}",
+          flush=True)
+    assert conv.mean() >= 0.99
+    ws = np.sort(rng.choice(np.nonzero(conv)[0], size=6, replace=False))
+    rs = compare_worlds(scene, kamx.make_params(**p), g, ws, mode="same",
+                        oracle_over=dict(cr_iters=0, eps=1e-8, max_iters=20000))
+    e = summary(f"figure 4096, worlds {ws.tolist()}, matrix-free (40 CR iterations) vs oracle converged", rs)
     assert e[:, 0].max() < TOL and e[:, 1].max() < TOL
