@@ -354,9 +354,13 @@ def test_learned_warm_start_in_chained_launches():
 
 def test_trained_network_cuts_iterations():
     """Train the network on a short cold rollout (noise seed 2002), then run
-    a rollout with a fresh noise seed cold and warm started by the network:
-    fewer iterations with the network (the answer itself is held to the
-    same residual tolerance either way)."""
+    a rollout with a fresh noise seed cold, warm started by the previous
+    step's impulses and by the network: fewer iterations with the network
+    than either, and no fewer world-steps converged (status OK per step).
+    The 20 chained steps are timed with events on the launch stream and
+    printed; at 1024 worlds (4 per compute unit) the wall time is set by
+    where the few world-steps that reach the iteration cap fall, so time
+    to tolerance is compared at the benchmark's 4096 worlds, not here."""
     import torch
     from paper_2603_16536_amd import learn
     n, steps = 1024, 60
@@ -368,23 +372,39 @@ def test_trained_network_cuts_iterations():
                           refs=np.zeros(sc.n_joints))
 
     net, info = learn.fit(lambda: make(2002, kamx.WARM_COLD), steps, epochs=30, batch=1024, seed=3)
-    iters = {}
-    for name, warm in (("cold", kamx.WARM_COLD), ("learned", kamx.WARM_LEARNED)):
-        m = make(77, warm)
-        if warm == kamx.WARM_LEARNED:
-            m.attach_mlp(net)
-        m.step(5)
-        log = torch.zeros((20, n), dtype=torch.int32, device="cuda")
-        m.set_iteration_log(log)
-        m.step(20)
-        torch.cuda.synchronize()
-        iters[name] = log.cpu().numpy()
-        m.close()
+    iters, status, ms = {}, {}, {}
+    legs = (("cold", kamx.WARM_COLD), ("previous", kamx.WARM_PREVIOUS), ("learned", kamx.WARM_LEARNED))
+    for name, warm in legs:
+        times = []
+        for rep in range(3):
+            m = make(77, warm)
+            if warm == kamx.WARM_LEARNED:
+                m.attach_mlp(net)
+            m.step(5)
+            log = torch.zeros((20, n), dtype=torch.int32, device="cuda")
+            st = torch.zeros((20, n), dtype=torch.int32, device="cuda")
+            m.set_iteration_log(log, status=st)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            m.step(20)
+            e1.record()
+            torch.cuda.synchronize()
+            if rep > 0:
+                times.append(e0.elapsed_time(e1))
+            iters[name] = log.cpu().numpy()
+            status[name] = st.cpu().numpy()
+            m.close()
+        ms[name] = min(times)
     net.close()
-    c, l = iters["cold"].mean(), iters["learned"].mean()
-    print(f"\nheld-out loss {info['val_loss']:.3f}; mean iterations cold {c:.1f}, learned {l:.1f}; "
-          f"median {np.median(iters['cold']):.0f} -> {np.median(iters['learned']):.0f}")
-    assert l < 0.98 * c
+    c, pv, l = iters["cold"].mean(), iters["previous"].mean(), iters["learned"].mean()
+    ok = {k: float(np.mean(v == kamx.WORLD_OK)) for k, v in status.items()}
+    print(f"\nheld-out loss {info['val_loss']:.3f}; mean iterations cold {c:.1f}, previous {pv:.1f}, learned {l:.1f}; "
+          f"median {np.median(iters['cold']):.0f} -> {np.median(iters['learned']):.0f}; status OK {ok}; "
+          f"20 steps: cold {ms['cold']:.1f} ms, previous {ms['previous']:.1f} ms, learned {ms['learned']:.1f} ms")
+    # the rollouts are deterministic: every repetition logs the same counts
+    assert l < 0.98 * c and l < pv
+    assert ok["learned"] >= ok["cold"] - 1e-3
 
 
 def test_box_bin_learned_warm_start():
