@@ -194,6 +194,25 @@ typedef float mfx4 __attribute__((ext_vector_type(4)));
 __device__ inline mfx4 mfma4(float a, float b, mfx4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
 
 // element (r, c) of the packed lower triangle; 0 above the diagonal
+// Workgroup sizes each dense row bucket is built for (the first is the
+// default; see step_threads_variants).
+struct BucketSizes {
+    int mc, n, nt[3];
+};
+constexpr BucketSizes kBucketSizes[] = {{32, 3, {256, 128, 64}}, {64, 2, {256, 128, 0}}, {96, 2, {512, 256, 0}},
+                                        {128, 2, {512, 256, 0}}, {160, 2, {384, 512, 0}}, {192, 2, {384, 512, 0}},
+                                        {224, 1, {512, 0, 0}}};
+
+// The default workgroup size of a bucket.  The gather's four-thread bodies
+// are capped by it rather than by the launched size, so that every size of a
+// bucket sums each body in the same order (a smaller size runs the gather's
+// tasks in more than one pass).
+constexpr int default_bucket_threads(int mc) {
+    for (const BucketSizes &v : kBucketSizes)
+        if (v.mc == mc) return v.nt[0];
+    return 0;
+}
+
 __device__ inline float tri_at(const float *A, int r, int c) { return c <= r ? A[tri_row_offset(r) + c] : 0.f; }
 
 // Body gather of the matrix-free product: g_b = sum over the rows incident
@@ -236,15 +255,15 @@ __device__ inline void delassus_gather(const Lds &L, int nb, const float *vp, co
 // incidence lists take four threads per component, the others two, so every
 // thread walks about the same number of rows. gorder[0] = nh, the count of
 // four-thread bodies (passed as nh), and gorder[1..nb] the bodies in task
-// order, those nh first. With nh > 0 the caller guarantees 12 (nb + nh) <= NT; with nh = 0
-// this is the two-thread gather over chunks of NT tasks. The lanes of a
+// order, those nh first. The 12 (nb + nh) tasks run in passes of NT (one
+// pass when they fit); a pass starts at a multiple of NT, so the lanes of a
 // body's component form an aligned group of 4 or 2 within one wave.
 template <int NT>
 __device__ inline void delassus_gather_bal(const Lds &L, int nb, int nh, const unsigned char *gorder,
                                            const float *vp, const float *x) {
     const int nheavy = 24 * nh, ntask = nheavy + 12 * (nb - nh);
-    // one task per thread; the first chunk is straight-line code, the
-    // rest (only for nh = 0 and more than NT tasks) loops
+    // one task per thread; the first pass is straight-line code, the rest
+    // (only when the tasks outnumber the threads) loops
     auto task = [&](const int t) {
         const bool heavy = t < nheavy;
         int j, c, h, S;
@@ -1546,7 +1565,10 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
         float s_own = 0.f;
         // gather balance for the loop: bodies with more than half the longest
         // incidence list go first and take four threads per component, as
-        // far as 12 (nb + nh) <= NT allows; the order is bytes in the aux
+        // far as 12 (nb + nh) <= T allows for the bucket's default workgroup
+        // size T (the same bodies, so the same sums, at every size: a
+        // four-thread body adds its rows in another order than a two-thread
+        // one); the order is bytes in the aux
         // field (free inside the loop). Wave 0 builds it, lane b for body b
         // (nb <= 64): a wave max, then ranks from ballots.
         static_assert(kMaxBodies <= 64 && kMaxBodies + 1 <= 4 * MC, "gather order: one lane per body, bytes in aux");
@@ -1557,7 +1579,9 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
             for (int o = 32; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o));
             const unsigned long long below = (1ull << tid) - 1ull;
             const unsigned long long hv = __ballot(tid < nb && 2 * kb > kmax);
-            const int cap = max(NT / 12 - nb, 0);
+            constexpr int kGatherThreads = default_bucket_threads(MC);
+            static_assert(kGatherThreads >= 64, "gather cap from the bucket's default size");
+            const int cap = max(kGatherThreads / 12 - nb, 0);
             const bool heavy = ((hv >> tid) & 1ull) && __popcll(hv & below) < cap;
             const unsigned long long hm = __ballot(heavy);
             const int nh = __popcll(hm);
@@ -2117,17 +2141,16 @@ int bucket_capacity(int rows) {
 // default.  Results do not depend on the choice: every row, tile and
 // reduction is evaluated in the same order at every size.
 int step_threads_variants(int mc, int out[4]) {
-    switch (mc) {
-    case 256: case 512: case 1024: out[0] = mc; return 1;  // matrix-free: one thread per row
-    case 32: out[0] = 256; out[1] = 128; out[2] = 64; return 3;  // 64: one wavefront per world
-    case 64: out[0] = 256; out[1] = 128; return 2;
-    case 96: out[0] = 512; out[1] = 256; return 2;
-    case 128: out[0] = 512; out[1] = 256; return 2;
-    case 160: out[0] = 384; out[1] = 512; return 2;
-    case 192: out[0] = 384; out[1] = 512; return 2;
-    case 224: out[0] = 512; return 1;
-    default: return 0;
+    if (mc == 256 || mc == 512 || mc == 1024) {  // matrix-free: one thread per row
+        out[0] = mc;
+        return 1;
     }
+    for (const BucketSizes &v : kBucketSizes)  // 32 rows: 64 is one wavefront per world
+        if (v.mc == mc) {
+            for (int k = 0; k < v.n; ++k) out[k] = v.nt[k];
+            return v.n;
+        }
+    return 0;
 }
 
 hipError_t launch_sparse_step(const StepArgs &args, int nt, int n, hipStream_t stream);
