@@ -309,19 +309,48 @@ __device__ inline void delassus_gather_bal(const Lds &L, int nb, int nh, const u
 }
 
 // w = M_b^-1 g_b in FP64 (body frame: R diag(I^-1) R^T for the angular part)
+// (the angular part from the body's symmetric R diag(I^-1) R^T, formed once
+// per step in FP64 by body_angular_minv)
 __device__ inline void body_minv64(const Lds &L, int b, double w[6]) {
+    const double *mi = reinterpret_cast<const double *>(L.b);
     double g[6];
     for (int c = 0; c < 6; ++c) g[c] = L.wb[c * kMaxBodies + b];
-    double im = L.bf(BIM, b);
-    double R[9], t[3], s[3];
-    for (int c = 0; c < 9; ++c) R[c] = L.bf(BR + c, b);
-    mtv3(R, g + 3, t);
-    for (int c = 0; c < 3; ++c) t[c] *= (double)L.bf(BII + c, b);
-    mv3(R, t, s);
-    for (int c = 0; c < 3; ++c) {
-        w[c] = g[c] * im;
-        w[3 + c] = s[c];
+    const double im = L.bf(BIM, b);
+    const double m00 = mi[b], m11 = mi[kMaxBodies + b], m22 = mi[2 * kMaxBodies + b];
+    const double m01 = mi[3 * kMaxBodies + b], m02 = mi[4 * kMaxBodies + b], m12 = mi[5 * kMaxBodies + b];
+    for (int c = 0; c < 3; ++c) w[c] = g[c] * im;
+    // explicit fused multiply-adds: every workgroup-size variant computes the same bits
+    w[3] = __builtin_fma(m02, g[5], __builtin_fma(m01, g[4], m00 * g[3]));
+    w[4] = __builtin_fma(m12, g[5], __builtin_fma(m11, g[4], m01 * g[3]));
+    w[5] = __builtin_fma(m22, g[5], __builtin_fma(m12, g[4], m02 * g[3]));
+}
+
+// The angular inverse inertia R diag(I^-1) R^T of every body in FP64 (six
+// entries: 00, 11, 22, 01, 02, 12), stored as doubles [6][kMaxBodies] over
+// the bodies' pose and twist fields.  Called once the rows and contacts are
+// built and a barrier has passed: nothing reads those fields afterwards, and
+// the rotation and inertia fields read here lie above them.  Ends with a
+// barrier.
+template <int NT>
+__device__ inline void body_angular_minv(const Lds &L, int nb) {
+    double *mi = reinterpret_cast<double *>(L.b);
+    static_assert(12 <= BUF && BR >= 12 && BII >= 12, "six doubles per body below the fields still in use");
+    const int b = threadIdx.x;
+    if (b < nb) {
+        double m[6];
+        double R[9], ii[3];
+        for (int k = 0; k < 9; ++k) R[k] = L.bf(BR + k, b);
+        for (int k = 0; k < 3; ++k) ii[k] = L.bf(BII + k, b);
+        const int ij[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
+        for (int e = 0; e < 6; ++e) {
+            const int i = ij[e][0], j = ij[e][1];
+            double v = (R[3 * i] * ii[0]) * R[3 * j];
+            v = __builtin_fma(R[3 * i + 1] * ii[1], R[3 * j + 1], v);
+            m[e] = __builtin_fma(R[3 * i + 2] * ii[2], R[3 * j + 2], v);
+        }
+        for (int e = 0; e < 6; ++e) mi[e * kMaxBodies + b] = m[e];
     }
+    __syncthreads();
 }
 
 // Row r of the product after a gather, given w_a, w_b = M^-1 g of its bodies.
@@ -1108,6 +1137,8 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
         }
         __syncthreads();
     }
+    static_assert(kMaxBodies <= NT, "one thread per body");
+    body_angular_minv<NT>(L, nb);
 
     // ---- W = M^-1 J^T for both sides of every row (in the vector region)
     float *Wv = L.v;  // [12][MC]
