@@ -31,7 +31,7 @@ def biped_workload(n_worlds, seed=1002):
 
 CFG2 = dict(dt=2e-3, eta=1e-4, rho_bilateral=1e-4, rho_contact=0.3, eps=1e-6, max_iters=2000,
             baumgarte=0.2, contact_margin=0.02, torque_sigma=5.0, seed=1002, reset_height=0.2,
-            adapt_ratio=20.0, adapt_factor=5.0, adapt_first=100)
+            adapt_ratio=10.0, adapt_factor=5.0, adapt_first=100)
 PD = (15.0, 0.6)   # the paper's DR Legs gains (N m / rad, N m s / rad)
 WORKLOADS = {
     "biped": "biped-{n}: 31 bodies, 40 revolute joints (10 closed loops), 8 sole probes, dt 2 ms, cold-start "
@@ -533,7 +533,7 @@ def main():
         "solver": solver_stats(cold, args.worlds * args.steps),
     }
     result["config"]["penalty"] = ("per-row rho (bilateral 1e-4, limit and contact 0.3), the limit and contact rows' "
-                                   "share adapted by residual balancing (ratio 20, factor 5, at iterations 100 * 2^j; "
+                                   "share adapted by residual balancing (ratio 10, factor 5, at iterations 100 * 2^j; "
                                    "not in the paper)")
     result["solver"]["resets"] = int(cold["resets"])
     if not args.no_fixed_penalty:

@@ -231,7 +231,7 @@ typedef struct {
  * eps 1e-6, 2000 iterations, acceleration and preconditioning on, restart
  * factor 0.999, beta 0.2, cold start, margin 0.02 m, no noise, semi-implicit
  * Euler, solver chosen by world size, 9 Conjugate Residual iterations,
- * adaptive unilateral penalty with ratio 20 and factor 5 from iteration 100).  Position-level terms act over the time from the configuration
+ * adaptive unilateral penalty with ratio 10 and factor 5 from iteration 100).  Position-level terms act over the time from the configuration
  * the rows are built at to the end of the step: the Baumgarte bias of a
  * bilateral row is beta f / h, a separated contact or limit f / h, a
  * penetrating one beta f / h, with h = dt (Euler) or dt/2 (Moreau-Jean). */

@@ -248,7 +248,7 @@ void kamx_default_params(kamx_params *p) {
     p->integrator = KAMX_EULER;
     p->linear_solver = KAMX_SOLVER_AUTO;
     p->cr_iters = 9;
-    p->adapt_ratio = 20.f;
+    p->adapt_ratio = 10.f;
     p->adapt_factor = 5.f;
     p->adapt_first = 100;
 }

@@ -50,7 +50,7 @@ def biped_state(n_worlds, seed):
 
 def test_defaults_switch_the_rule_on():
     p = kamx.default_params()
-    assert p.adapt_ratio == 20.0 and p.adapt_factor == 5.0 and p.adapt_first == 100
+    assert p.adapt_ratio == 10.0 and p.adapt_factor == 5.0 and p.adapt_first == 100
     with pytest.raises(kamx.KamxError):
         kamx.Model(scenes.round_to_f32(scenes.fourbar_batch(1, seed=1001)), params=dict(adapt_factor=0.5))
 

@@ -167,10 +167,11 @@ def test_capped_biped_world_steps_converge(orc):
     """Biped world-steps that stop at the 2000-iteration cap with the fixed
     penalty (1-2 % of a rollout; in about half of them r_p falls to 1e-12
     while r_d stays at 1e-6 for 20000 iterations) converge with the rule at
-    tau = 20, f = 5 from iteration 100; the others are no slower."""
+    tau = 10 (the usual residual-balancing ratio), f = 5 from iteration 100;
+    the others are no slower."""
     orc.set_threads(8)
     P, steps = biped_states(orc, 48, 24)
-    PA = P.replace(adapt_ratio=20.0, adapt_factor=5.0, adapt_first=100)
+    PA = P.replace(adapt_ratio=10.0, adapt_factor=5.0, adapt_first=100)
     capped, slower, n = 0, 0, 0
     conv = 0
     for sc, tau, plain in steps:
