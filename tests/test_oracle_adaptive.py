@@ -9,7 +9,10 @@ f, r_p > tau r_d multiplies it by f; a change refactors
 D~ + diag(eta + rho) and restarts the acceleration at the current iterate.
 
 * the rule on two decoupled unit-diagonal rows, worked out by hand (the
-  reduction of the restart tests with the penalty changes added);
+  reduction of the restart tests with the penalty changes added): with the
+  limit row separating it never fires (no unilateral row carries impulse),
+  with the limit row pressed it lowers the penalty at each checkpoint until
+  the rows reach their fixed point;
 * switched off, or with a ratio that never fires, the solve is the plain one
   bit for bit;
 * the converged answer does not depend on it: frictionless contact against
@@ -78,12 +81,52 @@ def two_row_adaptive(n_iters, eta, rho_a, rho_b, gamma, tau, f, first):
     return out
 
 
+def two_row_pressed(n_iters, eta, rho_a, rho_b, gamma, tau, f, first):
+    """Row a as above, row b a limit row pressed by v~_b = -1/2, so that
+    y_b = x_b - z^_b / rho_b stays positive (checked) and the projection never
+    acts: z stays 0 on both rows, y = x, r_p = 0 exactly, and
+    x_a,k = (1 + eta x_a,k-1 + rho_a y^_a,k-1) / (1 + eta + rho_a),
+    x_b,k = (1/2 + eta x_b,k-1 + rho_b y^_b,k-1) / (1 + eta + rho_b);
+    r_d = max(|x_a - 1|, |x_b - 1/2|); c = rho_a (y_a - y^_a)^2 +
+    rho_b (y_b - y^_b)^2.  A row carries impulse, so at a checkpoint
+    r_d > tau r_p = 0 divides rho_b by f and restarts the acceleration.
+    Returns per iteration (log byte, x_a, x_b, rho_b)."""
+    xa = yha = ypa = 0.0
+    xb = yhb = ypb = 0.0
+    a, c_prev = 1.0, math.inf
+    out = []
+    for k in range(1, n_iters + 1):
+        xa_n = (1.0 + eta * xa + rho_a * yha) / (1.0 + eta + rho_a)
+        xb_n = (0.5 + eta * xb + rho_b * yhb) / (1.0 + eta + rho_b)
+        assert xb_n > 0.0  # the limit row stays pressed
+        c = rho_a * (xa_n - yha) ** 2 + rho_b * (xb_n - yhb) ** 2
+        restart = not c < gamma * c_prev
+        if not restart:
+            a_n = 0.5 * (1.0 + math.sqrt(1.0 + 4.0 * a * a))
+            beta = (a - 1.0) / a_n
+            yha = xa_n + beta * (xa_n - ypa)
+            yhb = xb_n + beta * (xb_n - ypb)
+            a, c_prev = a_n, c
+        else:
+            yha, yhb = ypa, ypb
+            a, c_prev = 1.0, c_prev / gamma
+        xa, ypa, xb, ypb = xa_n, xa_n, xb_n, xb_n
+        rd = max(abs(xa_n - 1.0), abs(xb_n - 0.5))
+        d = 0
+        if is_checkpoint(k, first) and rd > 0.0:
+            d, rho_b = 1, rho_b / f
+            a, c_prev = 1.0, math.inf
+            yha, yhb = xa_n, xb_n
+        out.append((int(restart) | d << 1, xa_n, xb_n, rho_b))
+    return out
+
+
 def test_rule_on_two_decoupled_rows(orc):
     eta, ra, rb, gamma, tau, f, first = 0.1, 0.5, 1.0, 0.999, 1.5, 2.0, 2
-    ref = two_row_adaptive(40, eta, ra, rb, gamma, tau, f, first)
-    # hand outcome: lowered at 8, raised at 16, lowered at 32 (checkpoints
-    # 2 and 4 leave the penalty alone)
-    assert [(k + 1, r[0] >> 1) for k, r in enumerate(ref) if r[0] >> 1] == [(8, 1), (16, 2), (32, 1)]
+    # separating limit row: no unilateral row carries impulse, so the rule
+    # never fires and the solve is the plain one
+    ref = two_row_adaptive(40, eta, ra, rb, gamma, math.inf, f, first)
+    assert not any(r[0] >> 1 for r in ref)
     D = np.diag([4.0, 0.25])
     vf = np.array([-2.0, 0.25])  # Jacobi scales (1/2, 2): D~ = I, v~ = (-1, 1/2)
     kind = np.array([orc.ROW_BILATERAL, orc.ROW_LIMIT], np.int32)
@@ -98,6 +141,19 @@ def test_rule_on_two_decoupled_rows(orc):
         assert o["lam_tilde"][1] == 0.0
         assert abs(o["resid"][0] - abs(xb)) < 1e-13
         assert abs(o["resid"][1] - max(abs(xa - 1.0), abs(xb + 0.5 - zb))) < 1e-13
+    # pressed limit row (v~_b = -1/2): lowered at every checkpoint 2, 4, 8, 16
+    # (by iteration 32 both rows reach their fixed point exactly, r_d = 0, so
+    # the comparison stops at 30, clear of that boundary)
+    ref = two_row_pressed(30, eta, ra, rb, gamma, tau, f, first)
+    assert [(k + 1, r[0] >> 1) for k, r in enumerate(ref) if r[0] >> 1] == [(2, 1), (4, 1), (8, 1), (16, 1)]
+    vf = np.array([-2.0, -0.25])  # Jacobi scales (1/2, 2): D~ = I, v~ = (-1, -1/2)
+    for k in (1, 2, 3, 5, 8, 9, 16, 17, 24, 29, 30):
+        o = orc.solve_ncp(D, vf, kind, mu, P.replace(fixed_iters=k), log_iters=k)
+        assert list(o["restart_log"]) == [r[0] for r in ref[:k]], k
+        _, xa, xb, _ = ref[k - 1]
+        assert abs(o["lam_tilde"][0] - xa) < 1e-13 and abs(o["lam_tilde"][1] - xb) < 1e-13
+        assert o["resid"][0] == 0.0
+        assert abs(o["resid"][1] - max(abs(xa - 1.0), abs(xb - 0.5))) < 1e-13
 
 
 def biped_states(orc, n_worlds, steps, seed=1002):
@@ -135,32 +191,38 @@ def test_off_or_never_firing_is_the_plain_solve(orc):
             assert np.array_equal(o["iters"], plain["iters"])
 
 
-@pytest.mark.parametrize("seed", range(6))
-def test_frictionless_contact_answer_unchanged(orc, seed):
-    """Penalty changes forced from the second iteration on: the converged
-    normal impulses are the unique solution of the enumerated LCP."""
-    rng = np.random.default_rng(seed)
-    s = scenes.box_point_contacts(rng, n_points=3, mu=0.0, gap_scale=2e-3, v_scale=0.3)
-    P = orc.Params(dt=1e-3, baumgarte=0.2, rho_c=1.0, eps=1e-13, max_iters=200000, adapt_ratio=1.5,
-                   adapt_factor=3.0, adapt_first=2)
-    out = orc.step(s, P, log_iters=64)
-    assert out["status"][0] == orc.OK
-    assert np.any(out["restart_log"][0] >> 1)  # the penalty did change
-    S = orc.world_system(s, P, 0)
-    D, vf = S["D"], S["vf"]
-    nrm = np.arange(0, 9, 3)
-    Dn, vn = D[np.ix_(nrm, nrm)], vf[nrm]
-    sols = []
-    for mask in range(8):
-        act = [k for k in range(3) if mask >> k & 1]
-        lam = np.zeros(3)
-        if act:
-            lam[act] = np.linalg.solve(Dn[np.ix_(act, act)], -vn[act])
-        v = Dn @ lam + vn
-        if np.all(lam >= -1e-12) and np.all(v >= -1e-12):
-            sols.append(lam)
-    assert len(sols) == 1
-    assert np.abs(out["lam"][nrm] - sols[0]).max() < 1e-9 * max(1.0, np.abs(sols[0]).max())
+def test_frictionless_contact_answer_unchanged(orc):
+    """Penalty changes forced from the second iteration on (at checkpoints
+    where a contact carries impulse), on a box resting on three of its lower
+    face's points under gravity with a small random twist: the converged
+    normal impulses are the unique solution of the enumerated LCP, the
+    changes did happen, and most scenes have a pressed contact."""
+    n_changed = n_pressed = 0
+    for seed in range(6):
+        rng = np.random.default_rng(seed)
+        s = scenes.box_point_contacts(rng, n_points=3, mu=0.0, gap_scale=0.0, v_scale=0.02)
+        P = orc.Params(dt=1e-3, baumgarte=0.2, rho_c=1.0, eps=1e-13, max_iters=200000, adapt_ratio=1.5,
+                       adapt_factor=3.0, adapt_first=2)
+        out = orc.step(s, P, log_iters=64)
+        assert out["status"][0] == orc.OK, seed
+        n_changed += int(np.any(out["restart_log"][0] >> 1))
+        S = orc.world_system(s, P, 0)
+        D, vf = S["D"], S["vf"]
+        nrm = np.arange(0, 9, 3)
+        Dn, vn = D[np.ix_(nrm, nrm)], vf[nrm]
+        sols = []
+        for mask in range(8):
+            act = [k for k in range(3) if mask >> k & 1]
+            lam = np.zeros(3)
+            if act:
+                lam[act] = np.linalg.solve(Dn[np.ix_(act, act)], -vn[act])
+            v = Dn @ lam + vn
+            if np.all(lam >= -1e-12) and np.all(v >= -1e-12):
+                sols.append(lam)
+        assert len(sols) == 1, seed
+        assert np.abs(out["lam"][nrm] - sols[0]).max() < 1e-9 * max(1.0, np.abs(sols[0]).max()), seed
+        n_pressed += int(np.any(sols[0] > 0.0))
+    assert n_changed == 6 and n_pressed >= 4, (n_changed, n_pressed)
 
 
 def test_capped_biped_world_steps_converge(orc):
