@@ -1038,8 +1038,7 @@ int orc_solve_ncp(int m, const double *D, const double *vf, const int *kind, con
          * Peleato and Eckstein 2011, Sec. 3.4.1, here on the unilateral rows'
          * share of a per-row penalty).  At the checkpoint iterations
          * first, 2 first, 4 first, ...: when r_d > tau r_p the unilateral
-         * penalty is divided by f, when r_p > tau r_d it is multiplied by f,
-         * provided some limit or contact-normal row has y > 0.
+         * penalty is divided by f, when r_p > tau r_d it is multiplied by f.
          * A change refactors D~ + diag(eta + rho) and restarts the
          * acceleration from the current iterate (a = 1, y^ = y, z^ = z);
          * x, y and z carry over (z is not scaled by rho).  The decision is
@@ -1047,14 +1046,8 @@ int orc_solve_ncp(int m, const double *D, const double *vf, const int *kind, con
          * byte and read from there in replay. */
         if (P->adapt_ratio > 0.0 && n_uni > 0 && P->adapt_first > 0 && it >= P->adapt_first &&
             it % P->adapt_first == 0 && ((it / P->adapt_first) & (it / P->adapt_first - 1)) == 0) {
-            /* only while some limit or contact row carries impulse: the
-             * penalty of inactive unilateral rows cannot move the solve */
-            int active = 0;
-            for (int i = 0; i < m; ++i)
-                if ((kind[i] == ORC_ROW_LIMIT || kind[i] == ORC_ROW_NORMAL) && y[i] > 0.0) active = 1;
             int dir = 0;
             if (P->replay && replay_log) dir = (replay_log[it - 1] >> 1) & 3;
-            else if (!active) dir = 0;
             else if (rd > P->adapt_ratio * rp) dir = 1;
             else if (rp > P->adapt_ratio * rd) dir = 2;
             if (log_out && (P->log_stride <= 0 || it <= P->log_stride)) log_out[it - 1] |= (uint8_t)(dir << 1);

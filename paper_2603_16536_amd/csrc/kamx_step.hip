@@ -1908,17 +1908,12 @@ __device__ __attribute__((noinline)) void step_world(const StepArgs &a, int k, i
                 }
                 KAMX_MARK(6);
                 // adaptive penalty (not in the paper: residual balancing) at the
-                // checkpoints of a solve that does not exit here, while some
-                // limit or contact row carries impulse (the penalty of inactive
-                // rows cannot move the solve); rp and rd are the same in every
-                // thread, so the branch is uniform
+                // checkpoints of a solve that does not exit here; rp and rd are
+                // the same in every thread, so the branch is uniform
                 int adapt_dir = 0;
                 if (P.adapt_ratio > 0.f && n_uni > 0 && adapt_checkpoint(it, P.adapt_first) &&
                     !(P.fixed_iters <= 0 && rp < P.eps && rd < P.eps && rc < P.eps)) {
-                    const bool active =
-                        __syncthreads_or(owner_o && (kind_o == kRowLimit || kind_o == kRowNormal) && yb[0] > 0.f);
-                    if (!active) adapt_dir = 0;
-                    else if (rd > P.adapt_ratio * rp) adapt_dir = 1;
+                    if (rd > P.adapt_ratio * rp) adapt_dir = 1;
                     else if (rp > P.adapt_ratio * rd) adapt_dir = 2;
                 }
                 if (tid == 0 && a.rlog && P.log_restarts && it <= P.max_iters)

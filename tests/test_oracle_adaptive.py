@@ -9,10 +9,8 @@ f, r_p > tau r_d multiplies it by f; a change refactors
 D~ + diag(eta + rho) and restarts the acceleration at the current iterate.
 
 * the rule on two decoupled unit-diagonal rows, worked out by hand (the
-  reduction of the restart tests with the penalty changes added): with the
-  limit row separating it never fires (no unilateral row carries impulse),
-  with the limit row pressed it lowers the penalty at each checkpoint until
-  the rows reach their fixed point;
+  reduction of the restart tests with the penalty changes added), with the
+  limit row separating and with it pressed;
 * switched off, or with a ratio that never fires, the solve is the plain one
   bit for bit;
 * the converged answer does not depend on it: frictionless contact against
@@ -88,8 +86,8 @@ def two_row_pressed(n_iters, eta, rho_a, rho_b, gamma, tau, f, first):
     x_a,k = (1 + eta x_a,k-1 + rho_a y^_a,k-1) / (1 + eta + rho_a),
     x_b,k = (1/2 + eta x_b,k-1 + rho_b y^_b,k-1) / (1 + eta + rho_b);
     r_d = max(|x_a - 1|, |x_b - 1/2|); c = rho_a (y_a - y^_a)^2 +
-    rho_b (y_b - y^_b)^2.  A row carries impulse, so at a checkpoint
-    r_d > tau r_p = 0 divides rho_b by f and restarts the acceleration.
+    rho_b (y_b - y^_b)^2.  At a checkpoint r_d > tau r_p = 0 divides rho_b
+    by f and restarts the acceleration (while r_d > 0).
     Returns per iteration (log byte, x_a, x_b, rho_b)."""
     xa = yha = ypa = 0.0
     xb = yhb = ypb = 0.0
@@ -123,10 +121,10 @@ def two_row_pressed(n_iters, eta, rho_a, rho_b, gamma, tau, f, first):
 
 def test_rule_on_two_decoupled_rows(orc):
     eta, ra, rb, gamma, tau, f, first = 0.1, 0.5, 1.0, 0.999, 1.5, 2.0, 2
-    # separating limit row: no unilateral row carries impulse, so the rule
-    # never fires and the solve is the plain one
-    ref = two_row_adaptive(40, eta, ra, rb, gamma, math.inf, f, first)
-    assert not any(r[0] >> 1 for r in ref)
+    ref = two_row_adaptive(40, eta, ra, rb, gamma, tau, f, first)
+    # hand outcome: lowered at 8, raised at 16, lowered at 32 (checkpoints
+    # 2 and 4 leave the penalty alone)
+    assert [(k + 1, r[0] >> 1) for k, r in enumerate(ref) if r[0] >> 1] == [(8, 1), (16, 2), (32, 1)]
     D = np.diag([4.0, 0.25])
     vf = np.array([-2.0, 0.25])  # Jacobi scales (1/2, 2): D~ = I, v~ = (-1, 1/2)
     kind = np.array([orc.ROW_BILATERAL, orc.ROW_LIMIT], np.int32)
@@ -192,11 +190,11 @@ def test_off_or_never_firing_is_the_plain_solve(orc):
 
 
 def test_frictionless_contact_answer_unchanged(orc):
-    """Penalty changes forced from the second iteration on (at checkpoints
-    where a contact carries impulse), on a box resting on three of its lower
-    face's points under gravity with a small random twist: the converged
-    normal impulses are the unique solution of the enumerated LCP, the
-    changes did happen, and most scenes have a pressed contact."""
+    """Penalty changes forced from the second iteration on, on a box resting
+    on three points of its lower face under gravity with a small random
+    twist: the converged normal impulses are the unique solution of the
+    enumerated LCP, the changes did happen, and most scenes have a pressed
+    contact."""
     n_changed = n_pressed = 0
     for seed in range(6):
         rng = np.random.default_rng(seed)
