@@ -45,6 +45,9 @@ WORKLOADS = {
     "figure": "figure-{n}: 151 bodies, 196 revolute joints (45 closed loops, 980 rows), fixed to the world, dt 2 ms, "
               "explicit PD (gains capped for stability at dt) + N(0,5 N m) torques, matrix-free PADMM with {cr} "
               "Conjugate Residual iterations per iteration to 1e-6 (cap 200)",
+    "biped_rl": "biped-rl-{n}: the bipeds in the paper's RL stepping setup: leg linkages driven by implicit PD rows "
+                "(15 N m/rad, 0.6 N m s/rad, rotor armature and damping) + N(0,5 N m) torques, Moreau-Jean "
+                "midpoint step at 250 Hz (dt 4 ms), cold-start PADMM to 1e-6 (cap 200)",
 }
 TRAIN_SEED = 2002  # noise seed of the rollout that feeds training (the timed rollouts use CFG2's)
 
@@ -107,9 +110,10 @@ def make_model(workload, n_worlds, warmstart, schedule, seed=None, solver="auto"
                scene_seed=None):
     """The benchmark model of a workload: the biped batch (headline), the
     heterogeneous mix of four-bars, bipeds and excavators, boxes in a bin
-    with contacts generated every step, or the large fixed figure (solved
-    matrix-free).  solver: auto (dense factorization where a world fits,
-    else matrix-free), dense or sparse (matrix-free for every world)."""
+    with contacts generated every step, the large fixed figure (solved
+    matrix-free), or the bipeds in the paper's RL stepping setup.  solver:
+    auto (dense factorization where a world fits, else matrix-free), dense
+    or sparse (matrix-free for every world)."""
     from paper_2603_16536_amd import kamx, scenes
 
     params = dict(CFG2, warmstart=warmstart, cr_iters=cr_iters,
@@ -138,6 +142,13 @@ def make_model(workload, n_worlds, warmstart, schedule, seed=None, solver="auto"
                                               max_iters=50, torque_sigma=0.0, contact_margin=0.02,
                                               warmstart=warmstart, **(extra or {})),
                            max_contacts=4)
+    elif workload == "biped_rl":
+        scene = scenes.with_drives(scenes.round_to_f32(scenes.biped_batch(n_worlds, seed=1002, dt=4e-3, sole_probes=2)),
+                                   "transmission")
+        # a 200-iteration budget: at dt 4 ms most world-steps stall with
+        # residuals a few times 1e-6 (the dual one at 2^-19), which a cap of
+        # 2000 does not clear either (41 % converge under it)
+        model = kamx.Model(scene, params=dict(params, dt=4e-3, integrator=kamx.MOREAU_JEAN, max_iters=200))
     elif workload == "boxbin":
         scene = scenes.round_to_f32(scenes.box_bin_batch(n_worlds, seed=1005 if scene_seed is None else scene_seed))
         model = kamx.Model(scene, params=dict(params, torque_sigma=0.0, max_iters=200), max_contacts=64)
@@ -449,7 +460,8 @@ def main():
     ap.add_argument("--no-previous", action="store_true", help="skip the previous-step warm-start run")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start run")
     ap.add_argument("--workload", choices=tuple(WORKLOADS), default="biped",
-                    help="biped (headline), hetero (four-bar/biped/excavator mix) or boxbin")
+                    help="biped (headline), hetero (four-bar/biped/excavator mix), boxbin, fourbar, figure "
+                         "or biped_rl (implicit drives, Moreau-Jean, dt 4 ms)")
     ap.add_argument("--train-steps", type=int, default=250, help="steps of the cold rollout that feeds training")
     ap.add_argument("--epochs", type=int, default=60)
     ap.add_argument("--schedule", choices=("chain", "lpt", "index"), default="chain",

@@ -159,3 +159,27 @@ def test_fixed_figure_rollout_stays_bounded(orc):
         assert np.all(o["status"] == orc.OK) and o["iters"].max() <= 10
         q, u = o["q"], o["u"]
     assert np.abs(u).max() < 100.0
+
+
+def test_rl_biped_drives_the_legs_through_the_linkages():
+    """The RL stepping bipeds (Sec. 6.1, Sec. 6.3): per leg the hip yaw and
+    roll keep explicit PD, hip pitch, knee and ankle are passive, and the
+    five transmission cranks carry implicit PD rows with rotor armature and
+    damping; the loops are unchanged and every world fits 224 rows
+    (5 per revolute joint, 1 per drive, 3 per sole probe)."""
+    base = scenes.round_to_f32(scenes.biped_batch(3, seed=1002, dt=4e-3, sole_probes=2))
+    scene = scenes.with_drives(base, "transmission")
+    jo, po = scene.joint_offsets(), scene.probe_offsets()
+    for w in range(scene.n_worlds):
+        js = np.arange(jo[w], jo[w + 1])
+        assert world_topology(scene, w)[2] == 10
+        driven = js[np.any(scene.joint_drive[js] != 0, axis=1)]
+        assert len(driven) == 10
+        assert np.allclose(scene.joint_drive[driven, :2], scenes.BIPED_PD)
+        assert np.all(scene.joint_drive[driven, 3] > 0) and np.all(scene.joint_drive[driven, 2] > 0)
+        assert np.all(scene.joint_actuated[driven] == 1)
+        explicit = js[np.any(scene.joint_pd[js] != 0, axis=1)]
+        assert len(explicit) == 4 and not np.intersect1d(explicit, driven).size
+        assert np.count_nonzero(scene.joint_actuated[js]) == 14
+        rows = 5 * len(js) + len(driven) + 3 * (po[w + 1] - po[w])
+        assert rows <= 224, rows
