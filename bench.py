@@ -145,9 +145,10 @@ def make_model(workload, n_worlds, warmstart, schedule, seed=None, solver="auto"
     elif workload == "biped_rl":
         scene = scenes.with_drives(scenes.round_to_f32(scenes.biped_batch(n_worlds, seed=1002, dt=4e-3, sole_probes=2)),
                                    "transmission")
-        # a 200-iteration budget: at dt 4 ms most world-steps stall with
-        # residuals a few times 1e-6 (the dual one at 2^-19), which a cap of
-        # 2000 does not clear either (41 % converge under it)
+        # a 200-iteration budget: at dt 4 ms most world-steps stall in FP32
+        # with residuals a few times 1e-6 (the dual one at 2^-19, FP32's
+        # spacing there), which a cap of 2000 does not clear either (41 %
+        # converge under it); in FP64 these steps converge in under 100
         model = kamx.Model(scene, params=dict(params, dt=4e-3, integrator=kamx.MOREAU_JEAN, max_iters=200))
     elif workload == "boxbin":
         scene = scenes.round_to_f32(scenes.box_bin_batch(n_worlds, seed=1005 if scene_seed is None else scene_seed))
